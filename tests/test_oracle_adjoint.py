@@ -1,0 +1,116 @@
+"""Pins of the oracle's reverse-mode gradient of the receiver misfit
+J = sum_r sum_n (U^n[j_r] - d_r^n)^2 with respect to the boundary source
+samples f_A[n] and the leapfrog number lam = a dt / dx.
+
+The traces are linear in (f_A, f_B) from rest, so the gradient is checked
+against a brute-force Jacobian built from unit-impulse forward solves, the
+dot-product identity <A df, w> = <df, A^T w>, causality zeros, and central
+finite differences in lam.
+"""
+import numpy as np
+import pytest
+
+import oracle
+
+
+def forward_traces(M, lam, dx, fa, fb, n_steps, rec):
+    _, tr = oracle.single(M, lam, dx, fa, fb, n_steps, rec=rec)
+    return tr
+
+
+def misfit(M, lam, dx, fa, fb, n_steps, rec, d):
+    tr = forward_traces(M, lam, dx, fa, fb, n_steps, rec)
+    return float(np.sum((tr - d) ** 2)), tr
+
+
+@pytest.fixture(scope="module")
+def tiny():
+    M, n_steps = 21, 60
+    dx = 1.0 / (M - 1)
+    g = np.random.default_rng(3)
+    fa = np.concatenate([[0.0], g.standard_normal(n_steps)])
+    fb = np.concatenate([[0.0], 0.3 * g.standard_normal(n_steps)])
+    rec = np.array([3, 10, 17], np.int64)
+    d = g.standard_normal((len(rec), n_steps))
+    return M, n_steps, dx, fa, fb, rec, d
+
+
+def test_gradient_matches_bruteforce_jacobian(tiny):
+    M, n_steps, dx, fa, fb, rec, d = tiny
+    lam = 0.9
+    J, tr = misfit(M, lam, dx, fa, fb, n_steps, rec, d)
+    resid = 2.0 * (tr - d)
+    ga, gb, _ = oracle.adjoint(M, lam, dx, fa, fb, n_steps, rec, resid, ck=5)
+    z = np.zeros(n_steps + 1)
+    for which, grad in (("a", ga), ("b", gb)):
+        bf = np.zeros(n_steps + 1)
+        for n in range(1, n_steps + 1):
+            e = np.zeros(n_steps + 1)
+            e[n] = 1.0
+            col = forward_traces(M, lam, dx, e if which == "a" else z,
+                                 z if which == "a" else e, n_steps, rec)
+            bf[n] = np.sum(col * resid)
+        assert grad[0] == 0.0
+        assert np.abs(grad - bf).max() <= 1e-12 * np.abs(bf).max(), which
+
+
+def test_dot_product_identity():
+    M, n_steps = 201, 400
+    dx = 1.0 / (M - 1)
+    g = np.random.default_rng(5)
+    rec = np.sort(g.choice(np.arange(1, M - 1), 7, replace=False))
+    w = g.standard_normal((len(rec), n_steps))
+    df = np.concatenate([[0.0], g.standard_normal(n_steps)])
+    z = np.zeros(n_steps + 1)
+    Adf = forward_traces(M, 0.9, dx, df, z, n_steps, rec)
+    ga, _, _ = oracle.adjoint(M, 0.9, dx, z, z, n_steps, rec, w)
+    lhs = np.sum(Adf * w)
+    rhs = np.sum(df * ga)
+    assert abs(lhs - rhs) <= 1e-12 * np.sqrt(np.sum(Adf ** 2) * np.sum(w ** 2))
+
+
+def test_causality_zeros():
+    M, n_steps = 301, 500
+    dx = 1.0 / (M - 1)
+    g = np.random.default_rng(8)
+    rec = np.array([40, 120, 250], np.int64)
+    w = g.standard_normal((3, n_steps))
+    z = np.zeros(n_steps + 1)
+    ga, _, _ = oracle.adjoint(M, 0.9, dx, z, z, n_steps, rec, w)
+    cut = n_steps - rec.min()
+    assert np.all(ga[cut + 1:] == 0.0)
+    assert np.all(ga[1:cut + 1] != 0.0)
+
+
+def test_lambda_gradient_central_difference():
+    M, n_steps = 161, 700
+    dx = 1.0 / (M - 1)
+    g = np.random.default_rng(9)
+    t = np.arange(n_steps + 1) * 0.9 * dx
+    fa = np.exp(-((t - 0.08) / 0.02) ** 2)
+    fb = np.zeros_like(fa)
+    rec = np.array([20, 77, 140], np.int64)
+    d = forward_traces(M, 0.99, dx, fa, fb, n_steps, rec)  # "other speed" data
+    lam = 0.9
+    J0, tr = misfit(M, lam, dx, fa, fb, n_steps, rec, d)
+    _, _, glam = oracle.adjoint(M, lam, dx, fa, fb, n_steps, rec, 2.0 * (tr - d))
+    h = 1e-6
+    Jp, _ = misfit(M, lam + h, dx, fa, fb, n_steps, rec, d)
+    Jm, _ = misfit(M, lam - h, dx, fa, fb, n_steps, rec, d)
+    fd = (Jp - Jm) / (2 * h)
+    assert abs(glam) > 1e-3
+    assert abs(fd - glam) <= 1e-6 * abs(glam)
+
+
+def test_checkpoint_interval_does_not_change_result():
+    M, n_steps = 101, 230
+    dx = 1.0 / (M - 1)
+    g = np.random.default_rng(2)
+    fa = np.concatenate([[0.0], g.standard_normal(n_steps)])
+    fb = np.zeros(n_steps + 1)
+    rec = np.array([5, 50], np.int64)
+    w = g.standard_normal((2, n_steps))
+    outs = [oracle.adjoint(M, 0.9, dx, fa, fb, n_steps, rec, w, ck=ck)
+            for ck in (1, 7, 64, 1000)]
+    for o in outs[1:]:
+        assert np.array_equal(o[0], outs[0][0]) and o[2] == outs[0][2]
