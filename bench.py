@@ -1,0 +1,183 @@
+#!/usr/bin/env python3
+"""Benchmark of the RSWR hot path on one MI355X.
+
+One step = one whole RSWR solve (Wei & Zhao, arXiv 2203.10477, Sec. 2.6 redo
+loop: predict -> select -> update per span) of the large plain workload:
+2^24 nodes on [0,1], 4096 windows, overlap 64 grid intervals, Courant 0.9,
+span 35 (the Waveform Time Span Theorem, Eq. (10)), 2*10^4 steps, FP32,
+Ricker source on the left end, at rest.  Inputs (initial state, sources) are
+resident in HBM before the timed region; each step restores the initial state
+with a device copy and runs the recorded graph of all 572 spans.
+
+Prints one JSON line: throughput in grid-point updates per second (GLUPS,
+M * n_steps / time), the roofline of the dominant kernel (the update kernel,
+timed alone with HIP events on the stream it runs on), and the CPU oracle
+timed on a bounded sample of the same workload.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "grid-point updates/sec (GLUPS) + % HBM roofline, plain vs batched vs adjoint"
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
+
+# HBM traffic of one update launch on this workload, from two rocprofv3 --pmc
+# passes (FETCH_SIZE, WRITE_SIZE; see profiles/), valid only for the kernel
+# source with this SHA-256 prefix.
+TRAFFIC = {"kernel_sha": None, "bytes": None}
+
+
+def kernel_sha():
+    path = os.path.join(ROOT, "paper_2203_10477_amd", "csrc", "rswr_kernels.hip")
+    return hashlib.sha256(open(path, "rb").read()).hexdigest()[:16]
+
+
+def update_bytes(plan, elem):
+    """Algorithmic bytes of one update launch: every window reads its two
+    levels, the owned ranges of two levels are written, and every window reads
+    its input flux waveforms (S samples per input)."""
+    lo, hi, _, _ = plan.layout()
+    sum_n = int((hi - lo + 1).sum())
+    N, M, S = plan.N, plan.M, plan.span
+    return elem * (2 * sum_n + 2 * M + 2 * (N - 1) * S)
+
+
+def cpu_baseline(prob, target_s):
+    """The CPU oracle's literal RSWR on the first spans of the same workload."""
+    import numpy as np
+    import oracle
+    lay = oracle.layout(prob.M, prob.N, prob.P)
+    S = min(lay.span_cone, oracle.span_paper(prob.P, prob.lam, prob.courant_frac))
+    fa, fb = prob.sources()
+    st = prob.state0()
+    t0 = time.perf_counter()
+    st, _, _ = oracle.rswr(lay, prob.lam, prob.dx, fa, fb, S, span=S, state=st)
+    one = time.perf_counter() - t0
+    spans = max(1, min(40, int(target_s / max(one, 1e-3)) - 1))
+    t0 = time.perf_counter()
+    oracle.rswr(lay, prob.lam, prob.dx, fa, fb, spans * S, span=S, state=st, n0=S)
+    dt = time.perf_counter() - t0
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": prob.M * spans * S / dt / 1e9, "unit": "GLUPS", "cores": threads,
+            "kind": "oracle",
+            "sample": f"literal RSWR (whole-window predict + update, FP32) on all "
+                      f"{prob.N} windows of the same {prob.M}-node workload for {spans} "
+                      f"spans of {S} steps after one warm-up span; {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--kernel-reps", type=int, default=40)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
+              "(the multi-GPU layout is a design only)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2203_10477_amd as rs
+    import workloads
+
+    dev = "cuda:0"
+    torch.cuda.set_device(0)
+    prob = workloads.config5(np.float32)
+    dtype = torch.float32
+    plan = rs.Plan(prob.M, prob.N, prob.P, dtype=dtype)
+    S = plan.span
+    fa_np, fb_np = prob.sources()
+    fa = torch.as_tensor(fa_np, device=dev)
+    fb = torch.as_tensor(fb_np, device=dev)
+    st0 = torch.as_tensor(prob.state0(), device=dev)
+    st = st0.clone()
+    ws = torch.empty(plan.workspace_bytes(0), dtype=torch.uint8, device=dev)
+
+    def step():
+        st.copy_(st0)
+        rs.rswr_solve(plan, st, fa, fb, prob.n_steps, workspace=ws)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record()
+    for _ in range(args.steps):
+        step()
+    ev1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_step = wall * 1e3 / args.steps
+    ev_ms_step = ev0.elapsed_time(ev1) / args.steps
+    glups = prob.M * prob.n_steps / (ms_step * 1e-3) / 1e9
+    if not torch.isfinite(st).all():
+        raise RuntimeError("non-finite state after the benchmark solve")
+
+    # dominant kernel: one update launch (a full span of all windows) timed
+    # alone on the current stream
+    g = np.random.default_rng(1)
+    sm = torch.as_tensor(workloads.smooth_state(prob.M, g, shift=prob.lam * prob.dx),
+                         dtype=dtype, device=dev)
+    flux = rs.rswr_predict(plan, sm, fa, fb, 0, S)
+    out = torch.empty_like(sm)
+    for _ in range(5):
+        rs.rswr_update(plan, sm, fa, fb, 0, flux, span=S, out=out)
+    torch.cuda.synchronize()
+    ev0.record()
+    for _ in range(args.kernel_reps):
+        rs.rswr_update(plan, sm, fa, fb, 0, flux, span=S, out=out)
+    ev1.record()
+    torch.cuda.synchronize()
+    upd_us = ev0.elapsed_time(ev1) * 1e3 / args.kernel_reps
+    ev0.record()
+    for _ in range(args.kernel_reps):
+        rs.rswr_predict(plan, sm, fa, fb, 0, S, flux)
+    ev1.record()
+    torch.cuda.synchronize()
+    pred_us = ev0.elapsed_time(ev1) * 1e3 / args.kernel_reps
+    nbytes = update_bytes(plan, 4)
+    achieved = nbytes / (upd_us * 1e-6) / 1e9
+    sha = kernel_sha()
+    traffic = TRAFFIC["bytes"] if TRAFFIC["kernel_sha"] == sha else None
+    n_spans = -(-prob.n_steps // S)
+    span_bytes = nbytes + 4 * 2 * (prob.N - 1) * S  # plus the predict's flux writes
+
+    line = {
+        "metric": METRIC, "value": round(glups, 2), "unit": "GLUPS", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"plain RSWR {prob.M} nodes, {prob.N} windows, overlap "
+                               f"{prob.P}, span {S}, {prob.n_steps} steps, FP32, Ricker",
+                   "n_points": prob.M, "n_sub": prob.N, "overlap": prob.P, "span": S,
+                   "n_steps": prob.n_steps, "n_spans": n_spans,
+                   "tile": [plan.info["tile_threads"], plan.info["tile_per_thread"]],
+                   "n_tiles": plan.info["n_tiles"]},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": traffic, "kernel": "k_update (one span, all windows)",
+                     "avg_us": round(upd_us, 2), "algorithmic_bytes": nbytes},
+        "step": {"event_ms_per_step": round(ev_ms_step, 4),
+                 "predict_avg_us": round(pred_us, 2),
+                 "hbm_frac_whole_step": round(span_bytes * n_spans / (ms_step * 1e-3)
+                                              / 1e9 / HBM_PEAK_GBS, 4)},
+    }
+    if not args.no_cpu:
+        line["cpu_baseline"] = cpu_baseline(prob, args.cpu_seconds)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

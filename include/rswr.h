@@ -1,0 +1,186 @@
+/*
+ * rswr.h -- C-ABI of the RSWR hot path on AMD Instinct MI355X (gfx950).
+ *
+ * Method: Wei & Zhao, "A Non-iterative Overlapping Schwarz Waveform
+ * Relaxation Algorithm for Wave Equation", arXiv 2203.10477.
+ *
+ * The library solves u_tt = a^2 u_xx on Omega = [X_A, X_B] (Sec. 2.1,
+ * Eq. (1)) with Dirichlet data f_A, f_B at the ends (Eq. (3)) by splitting
+ * Omega into N overlapping windows (Sec. 2.2 Eqs. (4)-(5), Sec. 3) and
+ * advancing them span by span with the predict (Sec. 2.3), select (Sec. 2.4)
+ * and update (Sec. 2.5) steps and the redo loop of Sec. 2.6.
+ *
+ * Discretisation (the paper fixes none): nodes x_j = X_A + j dx,
+ * j = 0..M-1, dx = (X_B - X_A)/(M-1), dt = C dx / a_ref, lam = a dt/dx;
+ * second-order leapfrog with per-node order s = ul + ur,
+ * t = fma(k, u, -u_old), u_new = fma(lam^2, s, t), k = 2 - 2 lam^2;
+ * output flux waveforms are centred differences (u_{o+1} - u_{o-1})/(2dx);
+ * a Neumann input at a right window end b uses the ghost
+ * u_{b+1} = u_{b-1} + 2dx F, at a left end u_{b-1} = u_{b+1} - 2dx F.
+ * U^n_0 = f_A[n], U^n_{M-1} = f_B[n] for n >= 1; levels -1 and 0 are the
+ * initial state (zero for the paper's Eq. (2)).
+ *
+ * Conventions
+ *  - Every `void*` data argument is a DEVICE pointer owned by the caller
+ *    (allocated, e.g., by PyTorch); the element type is the plan's dtype.
+ *    Host pointers are marked (host).
+ *  - A state is [2][M]: row 0 = level n0-1, row 1 = level n0.
+ *  - Source arrays f_a, f_b are indexed by absolute level and must hold
+ *    every level a call touches (n0 .. n0 + steps).
+ *  - A flux buffer is [N-1][2][flux_ld] (flux_ld from rswr_plan_info):
+ *    [i][0][s] = window i's output flux at lo_{i+1} (feeds window i+1's left
+ *    input), [i][1][s] = window i+1's output flux at hi_i (feeds window i's
+ *    right input), at level n0+s.  These are the corresponding waveforms of
+ *    Sec. 2.2.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *    Work is enqueued asynchronously; argument errors are reported
+ *    synchronously; asynchronous device faults surface at a later call or
+ *    stream synchronisation as RSWR_ERR_HIP.
+ *  - No function throws or aborts; each returns a status code and
+ *    rswr_last_error() gives a thread-local description of the last error.
+ *  - A plan is immutable after creation and may be used from several
+ *    streams; it owns only its host tables and small device tables that it
+ *    uploads on first use on each device.
+ */
+#ifndef RSWR_H
+#define RSWR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct rswr_plan_s* rswr_plan_t;
+
+typedef enum {
+  RSWR_OK = 0,
+  RSWR_ERR_INVALID_ARG = 1, /* null pointer, bad size or flag */
+  RSWR_ERR_UNSTABLE = 2,    /* Courant number outside (0, 1] */
+  RSWR_ERR_LAYOUT = 3,      /* windows violate Eq. (4) or are too small */
+  RSWR_ERR_SPAN = 4,        /* span beyond the light-cone limit */
+  RSWR_ERR_NOMEM = 5,       /* host or device allocation failed, or the
+                               workspace is too small */
+  RSWR_ERR_HIP = 6,         /* HIP runtime error (launch or device fault) */
+  RSWR_ERR_NONFINITE = 7,   /* reserved */
+  RSWR_ERR_UNSUPPORTED = 8  /* valid request outside the built kernels */
+} rswr_status_t;
+
+typedef enum { RSWR_F32 = 0, RSWR_F64 = 1 } rswr_dtype_t;
+
+typedef enum {
+  /* S = min(light-cone limit, Waveform Time Span Theorem, Sec. 2.4 Eq. (10))
+   * every span; select needs no data. */
+  RSWR_SPAN_FIXED = 0,
+  /* adaptive: first predictive span = light-cone limit, then
+   * Shat_k = ceil((1+beta) S_{k-1}) (Sec. 2.6); S_k = min(Shat_k,
+   * min_b min(q_b, S_cone) + S_cone) with q_b the leading exact zeros of the
+   * predicted flux feeding input b (a safe replacement for the agreement
+   * test of Sec. 2.4, which is unsafe on mirror-symmetric data). */
+  RSWR_SPAN_QUIET = 1
+} rswr_span_mode_t;
+
+typedef struct {
+  double x_a, x_b;          /* Omega = [X_A, X_B], Sec. 2.1 */
+  int64_t n_points;         /* M >= 3 grid nodes */
+  double a;                 /* wave speed a > 0, Eq. (1) */
+  double a_ref;             /* speed that fixes dt = courant dx / a_ref;
+                               0 means a (then lam = courant) */
+  double courant;           /* C in (0, 1] */
+  int32_t courant_num;      /* optional exact C = num/den for the span rule */
+  int32_t courant_den;      /* (0, 0) = use `courant` */
+  int32_t n_sub;            /* N >= 1 windows, Sec. 3 */
+  int32_t overlap;          /* P, overlap width in grid intervals, even,
+                               Eq. (5); ignored with explicit windows */
+  const int64_t* sub_lo;    /* (host) optional explicit windows [lo_i, hi_i], */
+  const int64_t* sub_hi;    /* N entries each; NULL = uniform cores
+                               round(i (M-1)/N) widened by P/2 each side */
+  int32_t span;             /* 0 = default fixed span; else 1..light-cone
+                               limit (FIXED mode) */
+  int32_t span_mode;        /* rswr_span_mode_t */
+  double beta;              /* span growth of Sec. 2.6; 0 means 0.1 */
+  int32_t dtype;            /* rswr_dtype_t */
+  int32_t tile_threads;     /* 0 = library choice; else a built kernel shape */
+  int32_t tile_per_thread;  /* nodes per lane of that shape */
+} rswr_desc_t;
+
+typedef struct {
+  int64_t n_points;
+  int32_t n_sub, dtype;
+  int32_t span;             /* fixed span S (FIXED) or the cap 2*S_cone (QUIET) */
+  int32_t span_cone;        /* light-cone limit: min distance input<->output */
+  int32_t span_paper;       /* largest S with 2 S lam < P, Eq. (10) */
+  int32_t flux_ld;          /* row stride of flux buffers */
+  int32_t n_tiles;          /* update work-groups per span */
+  int32_t tile_threads, tile_per_thread;
+  double dx, dt, lambda;
+} rswr_plan_info_t;
+
+/* Builds a plan from the problem statement of Sec. 2.1-2.2 and Sec. 3.
+ * Host only: makes no HIP call.  Errors: INVALID_ARG, UNSTABLE, LAYOUT,
+ * SPAN, UNSUPPORTED, NOMEM. */
+rswr_status_t rswr_plan(const rswr_desc_t* desc, rswr_plan_t* out);
+rswr_status_t rswr_plan_destroy(rswr_plan_t plan);
+rswr_status_t rswr_plan_info(rswr_plan_t plan, rswr_plan_info_t* info);
+/* (host) arrays of N entries each: windows and owned ranges (a node shared by
+ * two windows belongs to the lower-indexed one, Sec. 2.5 Eq. (15)). */
+rswr_status_t rswr_plan_layout(rswr_plan_t plan, int64_t* lo, int64_t* hi,
+                               int64_t* own_lo, int64_t* own_hi);
+
+/* (host) The update work-groups of one span, for inspection: for tile t,
+ * tiles[6t..6t+5] = {first node of its register region, last node of the
+ * region, first and last node it stores, window index, right-input flag}.
+ * `tiles` holds 6 * n_tiles entries (n_tiles from rswr_plan_info). */
+rswr_status_t rswr_plan_tiles(rswr_plan_t plan, int64_t* tiles);
+
+/* Predict, Sec. 2.3 Eqs. (8)-(9): every window advances `span_hat` levels
+ * from `state` (level n0) with zero input flux; writes the output flux
+ * waveforms at levels n0..n0+span_hat-1 into `flux`.  Only the light-cone
+ * trapezoid around each output node is computed; it equals the whole-window
+ * prediction exactly.  1 <= span_hat <= plan's span cap. */
+rswr_status_t rswr_predict(rswr_plan_t plan, const void* state,
+                           const void* f_a, const void* f_b, int64_t n0,
+                           int32_t span_hat, void* flux, void* stream);
+
+/* Select, Sec. 2.4 and Sec. 3 Eq. (19): writes the span for this step to the
+ * device int32 `span_dev`.  FIXED: min(span_hat, S).  QUIET: the rule above,
+ * evaluated on `flux` (span_hat samples per waveform). */
+rswr_status_t rswr_select(rswr_plan_t plan, const void* flux, int32_t span_hat,
+                          int32_t* span_dev, void* stream);
+
+/* Update, Sec. 2.5 Eqs. (13)-(14), and gluing, Eq. (15): every window
+ * advances S levels from `state_in` with its neighbours' predicted fluxes as
+ * input fluxes; the owned ranges of levels n0+S-1 and n0+S are written to
+ * `state_out` (which must not overlap `state_in`).  S is read from the device
+ * int32 `span_dev` when it is not NULL, else it is `span`. */
+rswr_status_t rswr_update(rswr_plan_t plan, const void* state_in,
+                          const void* f_a, const void* f_b, int64_t n0,
+                          const void* flux, const int32_t* span_dev,
+                          int32_t span, void* state_out, void* stream);
+
+/* Bytes of device workspace rswr_solve needs for n_rec receivers. */
+rswr_status_t rswr_solve_workspace_size(rswr_plan_t plan, int32_t n_rec,
+                                        size_t* bytes);
+
+/* The redo loop of Sec. 2.6 (FIXED mode): n_steps levels from level n0,
+ * predict -> select -> update per span, the last span shortened.  `state` is
+ * read and overwritten with levels n0+n_steps-1 and n0+n_steps.
+ * Receivers: `rec_idx` (host) holds n_rec node indices; `traces`
+ * [n_rec][n_steps] receives U^{n0+s+1}[rec] at column s.  `checkpoints`
+ * (optional, [n_spans+1][2][M]) receives the state at every span boundary,
+ * n_spans = ceil(n_steps / S).  The whole loop is recorded once into a HIP
+ * graph per argument set and replayed. */
+rswr_status_t rswr_solve(rswr_plan_t plan, void* state, const void* f_a,
+                         const void* f_b, int64_t n0, int64_t n_steps,
+                         const int64_t* rec_idx, int32_t n_rec, void* traces,
+                         void* workspace, size_t ws_bytes, void* checkpoints,
+                         void* stream);
+
+const char* rswr_status_string(rswr_status_t status);
+const char* rswr_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,259 @@
+"""RSWR hot path on AMD MI355X: Python binding of librswr.so.
+
+Method: Wei & Zhao, "A Non-iterative Overlapping Schwarz Waveform Relaxation
+Algorithm for Wave Equation" (arXiv 2203.10477).  The functions here carry the
+names of the C-ABI in include/rswr.h (rswr_plan / rswr_predict / rswr_select /
+rswr_update / rswr_solve) and only marshal arguments: PyTorch provides device
+memory and the current stream, every step of the method runs in the HIP
+kernels of librswr.so.  There is no fallback: without the built library (or
+without a GPU for the compute calls) every call raises.
+"""
+import ctypes
+import os
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIBPATH = os.path.join(_HERE, "librswr.so")
+_lib = None
+
+F32, F64 = 0, 1
+FIXED, QUIET = 0, 1
+STATUS = {0: "RSWR_OK", 1: "RSWR_ERR_INVALID_ARG", 2: "RSWR_ERR_UNSTABLE",
+          3: "RSWR_ERR_LAYOUT", 4: "RSWR_ERR_SPAN", 5: "RSWR_ERR_NOMEM",
+          6: "RSWR_ERR_HIP", 7: "RSWR_ERR_NONFINITE", 8: "RSWR_ERR_UNSUPPORTED"}
+
+
+class RSWRError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class _Desc(ctypes.Structure):
+    _fields_ = [("x_a", ctypes.c_double), ("x_b", ctypes.c_double),
+                ("n_points", ctypes.c_int64), ("a", ctypes.c_double),
+                ("a_ref", ctypes.c_double), ("courant", ctypes.c_double),
+                ("courant_num", ctypes.c_int32), ("courant_den", ctypes.c_int32),
+                ("n_sub", ctypes.c_int32), ("overlap", ctypes.c_int32),
+                ("sub_lo", ctypes.c_void_p), ("sub_hi", ctypes.c_void_p),
+                ("span", ctypes.c_int32), ("span_mode", ctypes.c_int32),
+                ("beta", ctypes.c_double), ("dtype", ctypes.c_int32),
+                ("tile_threads", ctypes.c_int32), ("tile_per_thread", ctypes.c_int32)]
+
+
+class _Info(ctypes.Structure):
+    _fields_ = [("n_points", ctypes.c_int64), ("n_sub", ctypes.c_int32),
+                ("dtype", ctypes.c_int32), ("span", ctypes.c_int32),
+                ("span_cone", ctypes.c_int32), ("span_paper", ctypes.c_int32),
+                ("flux_ld", ctypes.c_int32), ("n_tiles", ctypes.c_int32),
+                ("tile_threads", ctypes.c_int32), ("tile_per_thread", ctypes.c_int32),
+                ("dx", ctypes.c_double), ("dt", ctypes.c_double),
+                ("lambda_", ctypes.c_double)]
+
+
+def lib():
+    """Load librswr.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIBPATH):
+        raise RuntimeError(f"{LIBPATH} is missing: build it with "
+                           "`python -m paper_2203_10477_amd.build`")
+    L = ctypes.CDLL(LIBPATH)
+    vp, i32, i64, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t
+    L.rswr_plan.argtypes = [ctypes.POINTER(_Desc), ctypes.POINTER(vp)]
+    L.rswr_plan_destroy.argtypes = [vp]
+    L.rswr_plan_info.argtypes = [vp, ctypes.POINTER(_Info)]
+    L.rswr_plan_layout.argtypes = [vp, vp, vp, vp, vp]
+    L.rswr_plan_tiles.argtypes = [vp, vp]
+    L.rswr_predict.argtypes = [vp, vp, vp, vp, i64, i32, vp, vp]
+    L.rswr_select.argtypes = [vp, vp, i32, vp, vp]
+    L.rswr_update.argtypes = [vp, vp, vp, vp, i64, vp, vp, i32, vp, vp]
+    L.rswr_solve_workspace_size.argtypes = [vp, i32, ctypes.POINTER(sz)]
+    L.rswr_solve.argtypes = [vp, vp, vp, vp, i64, i64, vp, i32, vp, vp, sz, vp, vp]
+    for name in ("rswr_plan", "rswr_plan_destroy", "rswr_plan_info", "rswr_plan_layout",
+                 "rswr_plan_tiles",
+                 "rswr_predict", "rswr_select", "rswr_update",
+                 "rswr_solve_workspace_size", "rswr_solve"):
+        getattr(L, name).restype = ctypes.c_int
+    L.rswr_status_string.argtypes = [ctypes.c_int]
+    L.rswr_status_string.restype = ctypes.c_char_p
+    L.rswr_last_error.restype = ctypes.c_char_p
+    _lib = L
+    return L
+
+
+def _check(status, what):
+    if status != 0:
+        raise RSWRError(status, f"{what}: {lib().rswr_last_error().decode()}")
+
+
+def _torch_dtype(code):
+    return torch.float64 if code == F64 else torch.float32
+
+
+class Plan:
+    """rswr_plan: decomposition, span rule and kernel tiles (host only).
+
+    n_points, n_sub, overlap: M grid nodes, N windows, overlap P in grid
+    intervals (Sec. 2.2 Eqs. (4)-(5), Sec. 3).  courant = a dt / dx with dt
+    fixed by a_ref (default a); courant_frac = (num, den) makes the span rule
+    of Eq. (10) exact in integers.  windows = (lo, hi) gives explicit windows.
+    """
+
+    def __init__(self, n_points, n_sub, overlap, a=1.0, courant=0.9,
+                 courant_frac=(9, 10), x_a=0.0, x_b=1.0, a_ref=0.0, span=0,
+                 span_mode=FIXED, beta=0.1, dtype=torch.float64, windows=None,
+                 tile=None):
+        L = lib()
+        d = _Desc()
+        d.x_a, d.x_b, d.n_points = float(x_a), float(x_b), int(n_points)
+        d.a, d.a_ref, d.courant = float(a), float(a_ref), float(courant)
+        num, den = courant_frac if courant_frac is not None else (0, 0)
+        d.courant_num, d.courant_den = int(num), int(den)
+        d.n_sub, d.overlap = int(n_sub), int(overlap)
+        self._win = None
+        if windows is not None:
+            lo = np.ascontiguousarray(windows[0], np.int64)
+            hi = np.ascontiguousarray(windows[1], np.int64)
+            self._win = (lo, hi)
+            d.sub_lo = lo.ctypes.data
+            d.sub_hi = hi.ctypes.data
+        d.span, d.span_mode, d.beta = int(span), int(span_mode), float(beta)
+        d.dtype = F64 if dtype == torch.float64 else F32
+        if tile is not None:
+            d.tile_threads, d.tile_per_thread = int(tile[0]), int(tile[1])
+        h = ctypes.c_void_p()
+        _check(L.rswr_plan(ctypes.byref(d), ctypes.byref(h)), "rswr_plan")
+        self._h = h
+        info = _Info()
+        _check(L.rswr_plan_info(h, ctypes.byref(info)), "rswr_plan_info")
+        self.info = {f[0].rstrip("_"): getattr(info, f[0]) for f in _Info._fields_}
+        self.dtype = _torch_dtype(info.dtype)
+        self.M = int(info.n_points)
+        self.N = int(info.n_sub)
+        self.span = int(info.span)
+        self.flux_ld = int(info.flux_ld)
+        self.flux_numel = max(self.N - 1, 1) * 2 * self.flux_ld
+
+    @property
+    def handle(self):
+        return self._h
+
+    def layout(self):
+        """(lo, hi, own_lo, own_hi) as int64 numpy arrays."""
+        arrs = [np.zeros(self.N, np.int64) for _ in range(4)]
+        _check(lib().rswr_plan_layout(self._h, *[a.ctypes.data for a in arrs]),
+               "rswr_plan_layout")
+        return tuple(arrs)
+
+    def tiles(self):
+        """Update work-groups: int64 [n_tiles, 6] = region first, region last,
+        stored first, stored last, window, right-input flag."""
+        t = np.zeros((self.info["n_tiles"], 6), np.int64)
+        _check(lib().rswr_plan_tiles(self._h, t.ctypes.data), "rswr_plan_tiles")
+        return t
+
+    def flux_buffer(self, device="cuda"):
+        return torch.zeros((max(self.N - 1, 1), 2, self.flux_ld), dtype=self.dtype,
+                           device=device)
+
+    def workspace_bytes(self, n_rec=0):
+        b = ctypes.c_size_t()
+        _check(lib().rswr_solve_workspace_size(self._h, int(n_rec), ctypes.byref(b)),
+               "rswr_solve_workspace_size")
+        return int(b.value)
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and _lib is not None:
+            _lib.rswr_plan_destroy(h)
+            self._h = None
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dev(t, dtype, min_numel, name):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if t.numel() < min_numel:
+        raise ValueError(f"{name} holds {t.numel()} elements, needs {min_numel}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def rswr_predict(plan, state, f_a, f_b, n0, span_hat, flux=None):
+    """Predict (Sec. 2.3): output flux waveforms [N-1, 2, flux_ld]."""
+    if flux is None:
+        flux = plan.flux_buffer(state.device)
+    _check(lib().rswr_predict(plan.handle, _dev(state, plan.dtype, 2 * plan.M, "state"),
+                              _dev(f_a, plan.dtype, n0 + span_hat, "f_a"),
+                              _dev(f_b, plan.dtype, n0 + span_hat, "f_b"), int(n0),
+                              int(span_hat), _dev(flux, plan.dtype, plan.flux_numel, "flux"),
+                              _stream()), "rswr_predict")
+    return flux
+
+
+def rswr_select(plan, flux, span_hat, span_dev=None):
+    """Select (Sec. 2.4): the span for this step as a 1-element int32 tensor."""
+    if span_dev is None:
+        span_dev = torch.zeros(1, dtype=torch.int32, device=flux.device)
+    _check(lib().rswr_select(plan.handle, _dev(flux, plan.dtype, plan.flux_numel, "flux"),
+                             int(span_hat),
+                             _dev(span_dev, torch.int32, 1, "span_dev"), _stream()),
+           "rswr_select")
+    return span_dev
+
+
+def rswr_update(plan, state_in, f_a, f_b, n0, flux, span=None, span_dev=None, out=None):
+    """Update + glue (Sec. 2.5): the next two-level state [2, M]."""
+    if out is None:
+        out = torch.empty_like(state_in)
+    sd = None if span_dev is None else _dev(span_dev, torch.int32, 1, "span_dev")
+    need = n0 + 1 if span is None else n0 + span + 1
+    _check(lib().rswr_update(plan.handle, _dev(state_in, plan.dtype, 2 * plan.M, "state_in"),
+                             _dev(f_a, plan.dtype, need, "f_a"),
+                             _dev(f_b, plan.dtype, need, "f_b"), int(n0),
+                             _dev(flux, plan.dtype, plan.flux_numel, "flux"), sd,
+                             int(span or 0), _dev(out, plan.dtype, 2 * plan.M, "state_out"),
+                             _stream()), "rswr_update")
+    return out
+
+
+def rswr_solve(plan, state, f_a, f_b, n_steps, n0=0, receivers=None, checkpoints=None,
+               workspace=None, traces=None):
+    """The span loop (Sec. 2.6).  `state` [2, M] is advanced in place.
+
+    Returns the traces [n_rec, n_steps] (None without receivers)."""
+    rec = (np.zeros(0, np.int64) if receivers is None
+           else np.ascontiguousarray(np.asarray(receivers, np.int64).reshape(-1)))
+    n_rec = len(rec)
+    if n_rec and traces is None:
+        traces = torch.zeros((n_rec, n_steps), dtype=plan.dtype, device=state.device)
+    if workspace is None:
+        workspace = torch.empty(plan.workspace_bytes(n_rec), dtype=torch.uint8,
+                                device=state.device)
+    ck = None
+    if checkpoints is not None:
+        n_spans = -(-n_steps // plan.span)
+        ck = _dev(checkpoints, plan.dtype, (n_spans + 1) * 2 * plan.M, "checkpoints")
+    _check(lib().rswr_solve(plan.handle, _dev(state, plan.dtype, 2 * plan.M, "state"),
+                            _dev(f_a, plan.dtype, n0 + n_steps + 1, "f_a"),
+                            _dev(f_b, plan.dtype, n0 + n_steps + 1, "f_b"), int(n0),
+                            int(n_steps), rec.ctypes.data if n_rec else None, n_rec,
+                            _dev(traces, plan.dtype, n_rec * n_steps, "traces")
+                            if n_rec else None,
+                            _dev(workspace, torch.uint8, 1, "workspace"),
+                            workspace.numel(), ck, _stream()), "rswr_solve")
+    return traces
+
+
+# Short names of the same calls.
+predict, select, update, solve = rswr_predict, rswr_select, rswr_update, rswr_solve

@@ -1,0 +1,747 @@
+// rswr_host.cpp -- plan construction and host driver of the RSWR C-ABI.
+//
+// Method: Wei & Zhao, arXiv 2203.10477.  The plan holds the decomposition
+// (Sec. 2.2 Eqs. (4)-(5), Sec. 3), the span rules (Sec. 2.4 Eq. (10) and the
+// light-cone limit of the discrete scheme) and the update tiles; the driver
+// runs the redo loop of Sec. 2.6 as predict -> select -> update per span and
+// records it into a HIP graph.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <limits>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/rswr.h"
+#include "rswr_internal.h"
+
+using rswr::Tile;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+rswr_status_t fail(rswr_status_t st, const std::string& msg) {
+  g_last_error = msg;
+  return st;
+}
+
+rswr_status_t hip_fail(hipError_t e, const char* what) {
+  return fail(RSWR_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define RSWR_HIP(call)                                  \
+  do {                                                  \
+    hipError_t e_ = (call);                             \
+    if (e_ != hipSuccess) return hip_fail(e_, #call);   \
+  } while (0)
+
+int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
+
+struct DevTables {
+  Tile* tiles = nullptr;
+  int64_t* lo = nullptr;
+  int64_t* hi = nullptr;
+  hipStream_t capture = nullptr;
+};
+
+struct GraphKey {
+  int device;
+  const void* state;
+  const void* fa;
+  const void* fb;
+  int64_t n0, n_steps;
+  const void* traces;
+  const void* ws;
+  const void* ckpt;
+  int has_rec;
+  bool operator==(const GraphKey& o) const {
+    return device == o.device && state == o.state && fa == o.fa && fb == o.fb &&
+           n0 == o.n0 && n_steps == o.n_steps && traces == o.traces && ws == o.ws &&
+           ckpt == o.ckpt && has_rec == o.has_rec;
+  }
+};
+
+struct GraphEntry {
+  GraphKey key;
+  hipGraphExec_t exec;
+};
+
+}  // namespace
+
+struct rswr_plan_s {
+  int64_t M = 0;
+  int32_t N = 0, P = 0, dtype = 0, mode = 0;
+  double dx = 0, dt = 0, lam = 0, beta = 0.1;
+  std::vector<int64_t> lo, hi, own_lo, own_hi;
+  int32_t S_cone = 0, S_paper = 0, S = 0, S_max = 0, flux_ld = 0;
+  int32_t threads = 0, per_thread = 0;
+  std::vector<Tile> tiles;
+  std::mutex mu;
+  std::map<int, DevTables> dev;
+  std::vector<GraphEntry> graphs;
+};
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// Decomposition (Sec. 2.2, Sec. 3).
+// ---------------------------------------------------------------------------
+rswr_status_t check_windows(rswr_plan_s& p) {
+  const int64_t M = p.M;
+  const int32_t N = p.N;
+  if (p.lo[0] != 0 || p.hi[N - 1] != M - 1)
+    return fail(RSWR_ERR_LAYOUT, "windows must start at node 0 and end at node M-1");
+  for (int32_t i = 0; i < N; ++i)
+    if (p.hi[i] - p.lo[i] < 2) return fail(RSWR_ERR_LAYOUT, "window narrower than 3 nodes");
+  for (int32_t i = 0; i + 1 < N; ++i) {
+    // X_{iA} < X_{(i+1)A} < X_{iB} < X_{(i+1)B}  (Eq. (4))
+    if (!(p.lo[i] < p.lo[i + 1] && p.lo[i + 1] < p.hi[i] && p.hi[i] < p.hi[i + 1]))
+      return fail(RSWR_ERR_LAYOUT, "windows " + std::to_string(i) + " and " +
+                                       std::to_string(i + 1) + " do not overlap in order");
+  }
+  p.own_lo.resize(N);
+  p.own_hi.resize(N);
+  for (int32_t i = 0; i < N; ++i) {
+    // gluing, Eq. (15): a shared node belongs to the lower-indexed window
+    p.own_lo[i] = (i == 0) ? 0 : p.hi[i - 1] + 1;
+    p.own_hi[i] = (i == N - 1) ? M - 1 : p.hi[i];
+    if (p.own_hi[i] < p.own_lo[i]) return fail(RSWR_ERR_LAYOUT, "empty owned range");
+  }
+  return RSWR_OK;
+}
+
+rswr_status_t uniform_windows(rswr_plan_s& p) {
+  const int64_t M = p.M;
+  const int32_t N = p.N;
+  if (N > 1 && (p.P < 2 || (p.P & 1)))
+    return fail(RSWR_ERR_LAYOUT, "overlap must be an even number >= 2 of grid intervals");
+  const int64_t h = p.P / 2;
+  std::vector<int64_t> c(N + 1);
+  for (int32_t i = 0; i <= N; ++i) c[i] = (2 * int64_t(i) * (M - 1) + N) / (2 * int64_t(N));
+  p.lo.resize(N);
+  p.hi.resize(N);
+  for (int32_t i = 0; i < N; ++i) {
+    if (c[i + 1] - c[i] < 1) return fail(RSWR_ERR_LAYOUT, "more windows than grid intervals");
+    p.lo[i] = (i == 0) ? 0 : c[i] - h;
+    p.hi[i] = (i == N - 1) ? M - 1 : c[i + 1] + h;
+  }
+  if (N > 1 && (c[1] - c[0] < h + 1 || c[N] - c[N - 1] < h + 1))
+    return fail(RSWR_ERR_LAYOUT, "end cores must be at least overlap/2 + 1 nodes");
+  return check_windows(p);
+}
+
+// Smallest distance between an input boundary and an output boundary of the
+// same window: a zero-flux error entering at the input reaches an output at
+// distance d after d levels, so predicted output fluxes are exact for that
+// many levels (the discrete form of the Prediction Validation Theorem).
+int32_t light_cone_span(const rswr_plan_s& p) {
+  int64_t best = std::numeric_limits<int32_t>::max();
+  for (int32_t w = 0; w < p.N; ++w) {
+    int64_t in[2], out[2];
+    int ni = 0, no = 0;
+    if (w > 0) {
+      in[ni++] = p.lo[w];
+      out[no++] = p.hi[w - 1];
+    }
+    if (w < p.N - 1) {
+      in[ni++] = p.hi[w];
+      out[no++] = p.lo[w + 1];
+    }
+    for (int a = 0; a < ni; ++a)
+      for (int b = 0; b < no; ++b) best = std::min<int64_t>(best, in[a] > out[b] ? in[a] - out[b] : out[b] - in[a]);
+  }
+  return static_cast<int32_t>(best);
+}
+
+// Waveform Time Span Theorem (Sec. 2.4, Eq. (10)) in steps: S dt < dX/(2a)
+// <=> 2 S lam < P with P the narrowest overlap in grid intervals.
+int32_t paper_span(const rswr_plan_s& p, int32_t num, int32_t den, bool exact) {
+  int64_t P = std::numeric_limits<int32_t>::max();
+  for (int32_t i = 0; i + 1 < p.N; ++i) P = std::min(P, p.hi[i] - p.lo[i + 1]);
+  if (exact) return static_cast<int32_t>((P * den - 1) / (2 * int64_t(num)));
+  int64_t s = 0;
+  while (2.0 * double(s + 1) * p.lam < double(P)) ++s;
+  return static_cast<int32_t>(s);
+}
+
+// ---------------------------------------------------------------------------
+// Update tiles.  For window i the first tile ends at its right input hi_i
+// (ghost from the last lane) or, for the last window, at node M-1; further
+// tiles cover the rest of the owned range right to left, each ending S nodes
+// past the part it stores.  A tile's region stores only nodes that zero data
+// entering at a cut end cannot reach within S levels; window ends inside a
+// region are treated exactly (Dirichlet node, or the left input's ghost).
+// ---------------------------------------------------------------------------
+bool build_tiles(const rswr_plan_s& p, int TM, int S, std::vector<Tile>& out) {
+  out.clear();
+  for (int32_t i = 0; i < p.N; ++i) {
+    const int64_t lo = p.lo[i], hi = p.hi[i];
+    const int64_t Olo = p.own_lo[i], Ohi = p.own_hi[i];
+    const bool last = (i == p.N - 1);
+    int64_t cur = Ohi;
+    bool first = true;
+    while (cur >= Olo) {
+      Tile t{};
+      const int64_t rb = first ? (last ? p.M - 1 : hi) : cur + S;
+      if (!first && !last && rb >= hi) return false;
+      t.a = rb - TM + 1;
+      const bool lex = (t.a <= lo);
+      const int64_t vlo = lex ? lo : t.a + S;
+      t.out_hi = cur;
+      t.out_lo = std::max(vlo, Olo);
+      if (t.out_lo > t.out_hi) return false;
+      t.fr = (first && !last) ? i : -1;
+      t.lin = (lex && i > 0) ? lo : rswr::kNoNode;
+      t.fl = (lex && i > 0) ? i - 1 : -1;
+      t.window = i;
+      out.push_back(t);
+      cur = t.out_lo - 1;
+      first = false;
+    }
+  }
+  return true;
+}
+
+// Default kernel shape: the least padded work, penalising launches too small
+// to give every one of the 256 compute units a couple of work-groups.
+bool choose_shape(rswr_plan_s& p) {
+  double best = 0;
+  bool found = false;
+  std::vector<Tile> tiles;
+  for (int s = 0; s < rswr::n_shapes(); ++s) {
+    const rswr::Shape sh = rswr::shape_at(s);
+    if (p.dtype == RSWR_F64 && sh.threads * sh.per_thread > 6144) continue;
+    const int TM = sh.threads * sh.per_thread;
+    if (TM < 2 * p.S_max + 2) continue;
+    if (!build_tiles(p, TM, p.S_max, tiles)) continue;
+    const double nt = double(tiles.size());
+    const double cost = nt * TM * std::max(1.0, 512.0 / nt);
+    if (!found || cost < best) {
+      best = cost;
+      found = true;
+      p.threads = sh.threads;
+      p.per_thread = sh.per_thread;
+    }
+  }
+  return found;
+}
+
+rswr_status_t ensure_device(rswr_plan_s* p, DevTables** out, int* device) {
+  int dev = 0;
+  RSWR_HIP(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> g(p->mu);
+  auto it = p->dev.find(dev);
+  if (it == p->dev.end()) {
+    DevTables t;
+    const size_t nt = std::max<size_t>(p->tiles.size(), 1);
+    RSWR_HIP(hipMalloc(&t.tiles, nt * sizeof(Tile)));
+    RSWR_HIP(hipMalloc(&t.lo, p->N * sizeof(int64_t)));
+    RSWR_HIP(hipMalloc(&t.hi, p->N * sizeof(int64_t)));
+    if (!p->tiles.empty())
+      RSWR_HIP(hipMemcpy(t.tiles, p->tiles.data(), p->tiles.size() * sizeof(Tile),
+                         hipMemcpyHostToDevice));
+    RSWR_HIP(hipMemcpy(t.lo, p->lo.data(), p->N * sizeof(int64_t), hipMemcpyHostToDevice));
+    RSWR_HIP(hipMemcpy(t.hi, p->hi.data(), p->N * sizeof(int64_t), hipMemcpyHostToDevice));
+    RSWR_HIP(hipStreamCreateWithFlags(&t.capture, hipStreamNonBlocking));
+    it = p->dev.emplace(dev, t).first;
+  }
+  *out = &it->second;
+  if (device) *device = dev;
+  return RSWR_OK;
+}
+
+template <typename T>
+rswr::PredictArgs<T> predict_args(const rswr_plan_s& p, const DevTables& d,
+                                  const void* state, const void* fa, const void* fb,
+                                  int64_t n0, int32_t shat, void* flux) {
+  rswr::PredictArgs<T> a{};
+  a.state = static_cast<const T*>(state);
+  a.fa = static_cast<const T*>(fa);
+  a.fb = static_cast<const T*>(fb);
+  a.flux = static_cast<T*>(flux);
+  a.lo = d.lo;
+  a.hi = d.hi;
+  a.M = p.M;
+  a.n0 = n0;
+  a.N = p.N;
+  a.shat = shat;
+  a.ld = p.flux_ld;
+  const double c2 = p.lam * p.lam;
+  a.c2 = T(c2);
+  a.k = T(2.0 - 2.0 * c2);
+  a.r = T(1.0 / (2.0 * p.dx));
+  a.q = T(2.0 * p.dx);
+  return a;
+}
+
+template <typename T>
+rswr::UpdateArgs<T> update_args(const rswr_plan_s& p, const DevTables& d,
+                                const void* state_in, const void* fa, const void* fb,
+                                int64_t n0, const void* flux, const int32_t* span_dev,
+                                int32_t span, void* state_out) {
+  rswr::UpdateArgs<T> a{};
+  a.state_in = static_cast<const T*>(state_in);
+  a.state_out = static_cast<T*>(state_out);
+  a.fa = static_cast<const T*>(fa);
+  a.fb = static_cast<const T*>(fb);
+  a.flux = static_cast<const T*>(flux);
+  a.tiles = d.tiles;
+  a.span_dev = span_dev;
+  a.M = p.M;
+  a.n0 = n0;
+  a.n_tiles = static_cast<int32_t>(p.tiles.size());
+  a.span = span;
+  a.ld = p.flux_ld;
+  const double c2 = p.lam * p.lam;
+  a.c2 = T(c2);
+  a.k = T(2.0 - 2.0 * c2);
+  a.q = T(2.0 * p.dx);
+  return a;
+}
+
+size_t elem_size(const rswr_plan_s& p) { return p.dtype == RSWR_F64 ? 8 : 4; }
+
+struct WsLayout {
+  size_t state = 0, flux = 0, rec_ptr = 0, rec_node = 0, rec_id = 0, total = 0;
+};
+
+WsLayout ws_layout(const rswr_plan_s& p, int32_t n_rec) {
+  WsLayout w;
+  const size_t b = elem_size(p);
+  size_t off = 0;
+  w.state = off;
+  off += round_up(2 * size_t(p.M) * b, 256);
+  w.flux = off;
+  off += round_up(size_t(std::max(p.N - 1, 1)) * 2 * p.flux_ld * b, 256);
+  w.rec_ptr = off;
+  off += round_up((p.tiles.size() + 1) * sizeof(int32_t), 256);
+  w.rec_node = off;
+  off += round_up(size_t(std::max(n_rec, 1)) * sizeof(int64_t), 256);
+  w.rec_id = off;
+  off += round_up(size_t(std::max(n_rec, 1)) * sizeof(int32_t), 256);
+  w.total = off;
+  return w;
+}
+
+template <typename T>
+rswr_status_t enqueue_solve(rswr_plan_s* p, const DevTables& d, void* state,
+                            const void* fa, const void* fb, int64_t n0, int64_t n_steps,
+                            bool has_rec, void* traces, char* ws, const WsLayout& L,
+                            void* ckpt, hipStream_t s) {
+  const int64_t M = p->M;
+  const int64_t K = (n_steps + p->S - 1) / p->S;
+  T* const user = static_cast<T*>(state);
+  T* const buf = reinterpret_cast<T*>(ws + L.state);
+  T* const flux = reinterpret_cast<T*>(ws + L.flux);
+  T* const ck = static_cast<T*>(ckpt);
+  const size_t st_elems = 2 * size_t(M);
+  T* x = user;
+  T* y = buf;
+  if (ck) {
+    RSWR_HIP(rswr::launch_copy<T>(ck, user, 2 * M, s));
+  } else if (K & 1) {
+    RSWR_HIP(rswr::launch_copy<T>(buf, user, 2 * M, s));
+    x = buf;
+    y = user;
+  }
+  int64_t lev = n0;
+  for (int64_t k = 0; k < K; ++k) {
+    const int32_t S = static_cast<int32_t>(std::min<int64_t>(p->S, n0 + n_steps - lev));
+    const T* in = ck ? ck + k * st_elems : x;
+    T* out = ck ? ck + (k + 1) * st_elems : y;
+    rswr::PredictArgs<T> pa = predict_args<T>(*p, d, in, fa, fb, lev, S, flux);
+    RSWR_HIP(rswr::launch_predict<T>(pa, 2 * p->S_max + 1, s));
+    rswr::UpdateArgs<T> ua =
+        update_args<T>(*p, d, in, fa, fb, lev, flux, nullptr, S, out);
+    if (has_rec) {
+      ua.rec_ptr = reinterpret_cast<const int32_t*>(ws + L.rec_ptr);
+      ua.rec_node = reinterpret_cast<const int64_t*>(ws + L.rec_node);
+      ua.rec_id = reinterpret_cast<const int32_t*>(ws + L.rec_id);
+      ua.traces = static_cast<T*>(traces);
+      ua.trace_ld = n_steps;
+      ua.trace_col0 = lev - n0;
+    }
+    RSWR_HIP(rswr::launch_update<T>(ua, p->threads, p->per_thread, s));
+    lev += S;
+    std::swap(x, y);
+  }
+  if (ck) RSWR_HIP(rswr::launch_copy<T>(user, ck + K * st_elems, 2 * M, s));
+  return RSWR_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* rswr_last_error(void) { return g_last_error.c_str(); }
+
+const char* rswr_status_string(rswr_status_t s) {
+  switch (s) {
+    case RSWR_OK: return "ok";
+    case RSWR_ERR_INVALID_ARG: return "invalid argument";
+    case RSWR_ERR_UNSTABLE: return "Courant number outside (0, 1]";
+    case RSWR_ERR_LAYOUT: return "invalid window layout";
+    case RSWR_ERR_SPAN: return "span beyond the light-cone limit";
+    case RSWR_ERR_NOMEM: return "out of memory or workspace too small";
+    case RSWR_ERR_HIP: return "HIP runtime error";
+    case RSWR_ERR_NONFINITE: return "non-finite value";
+    case RSWR_ERR_UNSUPPORTED: return "unsupported configuration";
+  }
+  return "unknown status";
+}
+
+rswr_status_t rswr_plan(const rswr_desc_t* desc, rswr_plan_t* out) {
+  if (!desc || !out) return fail(RSWR_ERR_INVALID_ARG, "null descriptor or output");
+  *out = nullptr;
+  const rswr_desc_t& D = *desc;
+  if (D.n_points < 3) return fail(RSWR_ERR_INVALID_ARG, "n_points must be >= 3");
+  if (D.n_sub < 1) return fail(RSWR_ERR_INVALID_ARG, "n_sub must be >= 1");
+  if (!(D.x_b > D.x_a)) return fail(RSWR_ERR_INVALID_ARG, "x_b must exceed x_a");
+  if (!(D.a > 0)) return fail(RSWR_ERR_INVALID_ARG, "wave speed must be positive");
+  if (!(D.a_ref >= 0)) return fail(RSWR_ERR_INVALID_ARG, "a_ref must be >= 0");
+  if (D.dtype != RSWR_F32 && D.dtype != RSWR_F64)
+    return fail(RSWR_ERR_INVALID_ARG, "dtype must be RSWR_F32 or RSWR_F64");
+  if (D.span_mode != RSWR_SPAN_FIXED && D.span_mode != RSWR_SPAN_QUIET)
+    return fail(RSWR_ERR_INVALID_ARG, "unknown span mode");
+  if (D.span < 0) return fail(RSWR_ERR_INVALID_ARG, "span must be >= 0");
+  if ((D.courant_num > 0) != (D.courant_den > 0))
+    return fail(RSWR_ERR_INVALID_ARG, "courant_num and courant_den go together");
+  const double a_ref = D.a_ref > 0 ? D.a_ref : D.a;
+  const double lam = D.courant * (D.a / a_ref);
+  if (!(D.courant > 0) || !(lam <= 1.0))
+    return fail(RSWR_ERR_UNSTABLE, "a dt/dx must lie in (0, 1]");
+  if ((D.sub_lo == nullptr) != (D.sub_hi == nullptr))
+    return fail(RSWR_ERR_INVALID_ARG, "sub_lo and sub_hi go together");
+
+  rswr_plan_s* p = new (std::nothrow) rswr_plan_s;
+  if (!p) return fail(RSWR_ERR_NOMEM, "plan allocation");
+  p->M = D.n_points;
+  p->N = D.n_sub;
+  p->P = D.overlap;
+  p->dtype = D.dtype;
+  p->mode = D.span_mode;
+  p->beta = D.beta > 0 ? D.beta : 0.1;
+  p->dx = (D.x_b - D.x_a) / double(D.n_points - 1);
+  p->dt = D.courant * p->dx / a_ref;
+  p->lam = lam;
+
+  rswr_status_t st;
+  if (D.sub_lo) {
+    p->lo.assign(D.sub_lo, D.sub_lo + D.n_sub);
+    p->hi.assign(D.sub_hi, D.sub_hi + D.n_sub);
+    st = check_windows(*p);
+  } else {
+    st = uniform_windows(*p);
+  }
+  if (st != RSWR_OK) {
+    delete p;
+    return st;
+  }
+
+  if (p->N == 1) {
+    p->S_cone = rswr::kMaxSpan;
+    p->S_paper = rswr::kMaxSpan;
+  } else {
+    p->S_cone = light_cone_span(*p);
+    const bool exact = D.courant_num > 0 && D.a == a_ref;
+    p->S_paper = paper_span(*p, D.courant_num, D.courant_den, exact);
+  }
+  if (p->mode == RSWR_SPAN_FIXED) {
+    if (D.span > 0) {
+      if (D.span > p->S_cone) {
+        delete p;
+        return fail(RSWR_ERR_SPAN, "span " + std::to_string(D.span) +
+                                       " exceeds the light-cone limit " +
+                                       std::to_string(p->S_cone));
+      }
+      p->S = D.span;
+    } else {
+      p->S = (p->N == 1) ? 32 : std::min(p->S_cone, p->S_paper);
+    }
+    if (p->S < 1) {
+      delete p;
+      return fail(RSWR_ERR_SPAN, "no admissible span (overlap too narrow)");
+    }
+    if (p->S > rswr::kMaxSpan) {
+      if (D.span > 0) {
+        delete p;
+        return fail(RSWR_ERR_UNSUPPORTED, "span above the kernels' limit of " +
+                                              std::to_string(rswr::kMaxSpan));
+      }
+      p->S = rswr::kMaxSpan;
+    }
+    p->S_max = p->S;
+  } else {
+    p->S = std::min(p->S_cone, rswr::kMaxSpan);
+    p->S_max = std::min<int64_t>(2 * int64_t(p->S_cone), rswr::kMaxSpan);
+  }
+  p->flux_ld = static_cast<int32_t>(round_up(p->S_max, 16));
+
+  if (D.tile_threads > 0 || D.tile_per_thread > 0) {
+    if (!rswr::shape_built(D.tile_threads, D.tile_per_thread)) {
+      delete p;
+      return fail(RSWR_ERR_UNSUPPORTED, "tile shape not built into the library");
+    }
+    const int TM = D.tile_threads * D.tile_per_thread;
+    if (TM < 2 * p->S_max + 2 || !build_tiles(*p, TM, p->S_max, p->tiles)) {
+      delete p;
+      return fail(RSWR_ERR_UNSUPPORTED, "tile shape too small for the span");
+    }
+    p->threads = D.tile_threads;
+    p->per_thread = D.tile_per_thread;
+  } else {
+    if (!choose_shape(*p)) {
+      delete p;
+      return fail(RSWR_ERR_UNSUPPORTED, "no built kernel shape fits this span");
+    }
+    build_tiles(*p, p->threads * p->per_thread, p->S_max, p->tiles);
+  }
+  *out = p;
+  return RSWR_OK;
+}
+
+rswr_status_t rswr_plan_destroy(rswr_plan_t p) {
+  if (!p) return RSWR_OK;
+  if (p->dev.empty()) {  // never touched a device: no HIP call at all
+    delete p;
+    return RSWR_OK;
+  }
+  int cur = 0;
+  (void)hipGetDevice(&cur);
+  for (auto& kv : p->dev) {
+    (void)hipSetDevice(kv.first);
+    (void)hipFree(kv.second.tiles);
+    (void)hipFree(kv.second.lo);
+    (void)hipFree(kv.second.hi);
+    if (kv.second.capture) (void)hipStreamDestroy(kv.second.capture);
+  }
+  for (auto& g : p->graphs) (void)hipGraphExecDestroy(g.exec);
+  (void)hipSetDevice(cur);
+  delete p;
+  return RSWR_OK;
+}
+
+rswr_status_t rswr_plan_info(rswr_plan_t p, rswr_plan_info_t* info) {
+  if (!p || !info) return fail(RSWR_ERR_INVALID_ARG, "null plan or info");
+  info->n_points = p->M;
+  info->n_sub = p->N;
+  info->dtype = p->dtype;
+  info->span = p->mode == RSWR_SPAN_FIXED ? p->S : p->S_max;
+  info->span_cone = p->S_cone;
+  info->span_paper = p->S_paper;
+  info->flux_ld = p->flux_ld;
+  info->n_tiles = static_cast<int32_t>(p->tiles.size());
+  info->tile_threads = p->threads;
+  info->tile_per_thread = p->per_thread;
+  info->dx = p->dx;
+  info->dt = p->dt;
+  info->lambda = p->lam;
+  return RSWR_OK;
+}
+
+rswr_status_t rswr_plan_layout(rswr_plan_t p, int64_t* lo, int64_t* hi, int64_t* own_lo,
+                               int64_t* own_hi) {
+  if (!p) return fail(RSWR_ERR_INVALID_ARG, "null plan");
+  for (int32_t i = 0; i < p->N; ++i) {
+    if (lo) lo[i] = p->lo[i];
+    if (hi) hi[i] = p->hi[i];
+    if (own_lo) own_lo[i] = p->own_lo[i];
+    if (own_hi) own_hi[i] = p->own_hi[i];
+  }
+  return RSWR_OK;
+}
+
+rswr_status_t rswr_plan_tiles(rswr_plan_t p, int64_t* out) {
+  if (!p || !out) return fail(RSWR_ERR_INVALID_ARG, "null plan or output");
+  const int64_t TM = int64_t(p->threads) * p->per_thread;
+  for (size_t t = 0; t < p->tiles.size(); ++t) {
+    const Tile& x = p->tiles[t];
+    out[6 * t + 0] = x.a;
+    out[6 * t + 1] = x.a + TM - 1;
+    out[6 * t + 2] = x.out_lo;
+    out[6 * t + 3] = x.out_hi;
+    out[6 * t + 4] = x.window;
+    out[6 * t + 5] = x.fr >= 0 ? 1 : 0;
+  }
+  return RSWR_OK;
+}
+
+rswr_status_t rswr_predict(rswr_plan_t p, const void* state, const void* f_a,
+                           const void* f_b, int64_t n0, int32_t span_hat, void* flux,
+                           void* stream) {
+  if (!p || !state || !f_a || !f_b || !flux)
+    return fail(RSWR_ERR_INVALID_ARG, "null pointer");
+  if (n0 < 0) return fail(RSWR_ERR_INVALID_ARG, "n0 must be >= 0");
+  if (span_hat < 1 || span_hat > p->S_max)
+    return fail(RSWR_ERR_SPAN, "span_hat outside 1.." + std::to_string(p->S_max));
+  DevTables* d = nullptr;
+  rswr_status_t st = ensure_device(p, &d, nullptr);
+  if (st != RSWR_OK) return st;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipError_t e;
+  if (p->dtype == RSWR_F64)
+    e = rswr::launch_predict<double>(
+        predict_args<double>(*p, *d, state, f_a, f_b, n0, span_hat, flux), 2 * span_hat + 1, s);
+  else
+    e = rswr::launch_predict<float>(
+        predict_args<float>(*p, *d, state, f_a, f_b, n0, span_hat, flux), 2 * span_hat + 1, s);
+  if (e != hipSuccess) return hip_fail(e, "predict launch");
+  return RSWR_OK;
+}
+
+rswr_status_t rswr_select(rswr_plan_t p, const void* flux, int32_t span_hat,
+                          int32_t* span_dev, void* stream) {
+  if (!p || !span_dev || (!flux && p->N > 1))
+    return fail(RSWR_ERR_INVALID_ARG, "null pointer");
+  if (span_hat < 1 || span_hat > p->S_max)
+    return fail(RSWR_ERR_SPAN, "span_hat outside 1.." + std::to_string(p->S_max));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipError_t e;
+  if (p->dtype == RSWR_F64) {
+    rswr::SelectArgs<double> a{static_cast<const double*>(flux), span_dev, 2 * (p->N - 1),
+                               span_hat, p->flux_ld, p->S_cone, p->mode, p->S};
+    e = rswr::launch_select<double>(a, s);
+  } else {
+    rswr::SelectArgs<float> a{static_cast<const float*>(flux), span_dev, 2 * (p->N - 1),
+                              span_hat, p->flux_ld, p->S_cone, p->mode, p->S};
+    e = rswr::launch_select<float>(a, s);
+  }
+  if (e != hipSuccess) return hip_fail(e, "select launch");
+  return RSWR_OK;
+}
+
+rswr_status_t rswr_update(rswr_plan_t p, const void* state_in, const void* f_a,
+                          const void* f_b, int64_t n0, const void* flux,
+                          const int32_t* span_dev, int32_t span, void* state_out,
+                          void* stream) {
+  if (!p || !state_in || !f_a || !f_b || !state_out || (!flux && p->N > 1))
+    return fail(RSWR_ERR_INVALID_ARG, "null pointer");
+  if (n0 < 0) return fail(RSWR_ERR_INVALID_ARG, "n0 must be >= 0");
+  if (state_in == state_out) return fail(RSWR_ERR_INVALID_ARG, "state_out aliases state_in");
+  if (!span_dev && (span < 1 || span > p->S_max))
+    return fail(RSWR_ERR_SPAN, "span outside 1.." + std::to_string(p->S_max));
+  DevTables* d = nullptr;
+  rswr_status_t st = ensure_device(p, &d, nullptr);
+  if (st != RSWR_OK) return st;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipError_t e;
+  if (p->dtype == RSWR_F64)
+    e = rswr::launch_update<double>(update_args<double>(*p, *d, state_in, f_a, f_b, n0, flux,
+                                                        span_dev, span, state_out),
+                                    p->threads, p->per_thread, s);
+  else
+    e = rswr::launch_update<float>(update_args<float>(*p, *d, state_in, f_a, f_b, n0, flux,
+                                                      span_dev, span, state_out),
+                                   p->threads, p->per_thread, s);
+  if (e != hipSuccess) return hip_fail(e, "update launch");
+  return RSWR_OK;
+}
+
+rswr_status_t rswr_solve_workspace_size(rswr_plan_t p, int32_t n_rec, size_t* bytes) {
+  if (!p || !bytes || n_rec < 0) return fail(RSWR_ERR_INVALID_ARG, "bad argument");
+  *bytes = ws_layout(*p, n_rec).total;
+  return RSWR_OK;
+}
+
+rswr_status_t rswr_solve(rswr_plan_t p, void* state, const void* f_a, const void* f_b,
+                         int64_t n0, int64_t n_steps, const int64_t* rec_idx,
+                         int32_t n_rec, void* traces, void* workspace, size_t ws_bytes,
+                         void* checkpoints, void* stream) {
+  if (!p || !state || !f_a || !f_b) return fail(RSWR_ERR_INVALID_ARG, "null pointer");
+  if (p->mode != RSWR_SPAN_FIXED)
+    return fail(RSWR_ERR_UNSUPPORTED, "rswr_solve runs FIXED plans");
+  if (n0 < 0 || n_steps < 0 || n_rec < 0)
+    return fail(RSWR_ERR_INVALID_ARG, "negative n0, n_steps or n_rec");
+  if (n_rec > 0 && (!rec_idx || !traces))
+    return fail(RSWR_ERR_INVALID_ARG, "receivers need rec_idx and traces");
+  if (n_steps == 0) return RSWR_OK;
+  const WsLayout L = ws_layout(*p, n_rec);
+  if (!workspace || ws_bytes < L.total)
+    return fail(RSWR_ERR_NOMEM, "workspace needs " + std::to_string(L.total) + " bytes");
+  for (int32_t r = 0; r < n_rec; ++r)
+    if (rec_idx[r] < 0 || rec_idx[r] >= p->M)
+      return fail(RSWR_ERR_INVALID_ARG, "receiver index out of range");
+  DevTables* d = nullptr;
+  int device = 0;
+  rswr_status_t st = ensure_device(p, &d, &device);
+  if (st != RSWR_OK) return st;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  char* ws = static_cast<char*>(workspace);
+
+  if (n_rec > 0) {
+    // receiver r is recorded by the tile whose stored range holds its node
+    const size_t nt = p->tiles.size();
+    std::vector<std::vector<int32_t>> per(nt);
+    for (int32_t r = 0; r < n_rec; ++r) {
+      for (size_t t = 0; t < nt; ++t)
+        if (rec_idx[r] >= p->tiles[t].out_lo && rec_idx[r] <= p->tiles[t].out_hi) {
+          per[t].push_back(r);
+          break;
+        }
+    }
+    std::vector<int32_t> ptr(nt + 1, 0), id;
+    std::vector<int64_t> node;
+    for (size_t t = 0; t < nt; ++t) {
+      for (int32_t r : per[t]) {
+        id.push_back(r);
+        node.push_back(rec_idx[r]);
+      }
+      ptr[t + 1] = static_cast<int32_t>(id.size());
+    }
+    RSWR_HIP(hipMemcpyAsync(ws + L.rec_ptr, ptr.data(), ptr.size() * sizeof(int32_t),
+                            hipMemcpyHostToDevice, s));
+    RSWR_HIP(hipMemcpyAsync(ws + L.rec_node, node.data(), node.size() * sizeof(int64_t),
+                            hipMemcpyHostToDevice, s));
+    RSWR_HIP(hipMemcpyAsync(ws + L.rec_id, id.data(), id.size() * sizeof(int32_t),
+                            hipMemcpyHostToDevice, s));
+  }
+
+  const bool eager = std::getenv("RSWR_NO_GRAPH") != nullptr;
+  auto enqueue = [&](hipStream_t q) {
+    return p->dtype == RSWR_F64
+               ? enqueue_solve<double>(p, *d, state, f_a, f_b, n0, n_steps, n_rec > 0,
+                                       traces, ws, L, checkpoints, q)
+               : enqueue_solve<float>(p, *d, state, f_a, f_b, n0, n_steps, n_rec > 0,
+                                      traces, ws, L, checkpoints, q);
+  };
+  if (eager) return enqueue(s);
+
+  const GraphKey key{device, state, f_a, f_b, n0, n_steps, traces, workspace, checkpoints,
+                     n_rec > 0};
+  hipGraphExec_t exec = nullptr;
+  {
+    std::lock_guard<std::mutex> g(p->mu);
+    for (auto& e : p->graphs)
+      if (e.key == key) exec = e.exec;
+  }
+  if (!exec) {
+    hipGraph_t graph = nullptr;
+    RSWR_HIP(hipStreamBeginCapture(d->capture, hipStreamCaptureModeThreadLocal));
+    rswr_status_t cst = enqueue(d->capture);
+    hipError_t ee = hipStreamEndCapture(d->capture, &graph);
+    if (cst != RSWR_OK) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return cst;
+    }
+    if (ee != hipSuccess) return hip_fail(ee, "hipStreamEndCapture");
+    ee = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (ee != hipSuccess) return hip_fail(ee, "hipGraphInstantiate");
+    std::lock_guard<std::mutex> g(p->mu);
+    if (p->graphs.size() >= 8) {
+      (void)hipGraphExecDestroy(p->graphs.front().exec);
+      p->graphs.erase(p->graphs.begin());
+    }
+    p->graphs.push_back({key, exec});
+  }
+  RSWR_HIP(hipGraphLaunch(exec, s));
+  return RSWR_OK;
+}
+
+}  // extern "C"

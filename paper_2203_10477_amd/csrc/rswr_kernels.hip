@@ -1,0 +1,411 @@
+// rswr_kernels.hip -- gfx950 kernels of the RSWR hot path.
+//
+// Method: Wei & Zhao, arXiv 2203.10477.  Stencil arithmetic per node (the
+// same operation order everywhere): s = ul + ur; t = fma(k, u, -u_old);
+// u_new = fma(c2, s, t).  No packed FP32 (built with -packed-fp32-ops) and
+// no contraction (-ffp-contract=off), so every result is one fixed sequence
+// of correctly rounded IEEE operations.
+#include "rswr_internal.h"
+
+namespace rswr {
+
+__device__ __forceinline__ float fma_(float a, float b, float c) {
+  return __builtin_fmaf(a, b, c);
+}
+__device__ __forceinline__ double fma_(double a, double b, double c) {
+  return __builtin_fma(a, b, c);
+}
+
+// Second-order leapfrog for Eq. (1) at one node.
+template <typename T>
+__device__ __forceinline__ T leap(T c2, T k, T ul, T u, T ur, T u_old) {
+  const T s = ul + ur;
+  const T t = fma_(k, u, -u_old);
+  return fma_(c2, s, t);
+}
+
+// Work-groups are dispatched to the 8 XCDs round-robin by block id.  Give
+// each XCD a contiguous run of tiles, so neighbouring tiles (which share
+// overlap nodes) meet in the same L2.
+__device__ __forceinline__ int xcd_tile(int bid, int nb) {
+  const int q = nb >> 3, r = nb & 7;
+  const int x = bid & 7, i = bid >> 3;
+  return (x < r) ? x * (q + 1) + i : r * (q + 1) + (x - r) * q + i;
+}
+
+// ---------------------------------------------------------------------------
+// Predict (Sec. 2.3, Eqs. (8)-(9)).  One wave per (interface i, side): side 0
+// is window i's output node lo_{i+1}, side 1 is window i+1's output node hi_i.
+// The flux at the output node over shat levels depends only on the state in
+// [o - shat, o + shat] (one node per level), clipped to the window; the
+// window's own ends inside that range keep their exact treatment (Dirichlet
+// data, or the zero-flux ghost of the prediction), the cut ends carry zero
+// data that cannot reach o +- 1 in time.  So this trapezoid reproduces the
+// whole-window prediction bit for bit.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(64) void k_predict(const PredictArgs<T> p) {
+  extern __shared__ unsigned char smem_raw[];
+  T* const sm = reinterpret_cast<T*>(smem_raw);
+  const int i = blockIdx.x >> 1, side = blockIdx.x & 1;
+  const int w = i + side;
+  const int64_t o = (side == 0) ? p.lo[i + 1] : p.hi[i];
+  const int64_t wlo = p.lo[w], whi = p.hi[w];
+  const int shat = p.shat;
+  const int64_t A = (o - shat > wlo) ? o - shat : wlo;
+  const int64_t B = (o + shat < whi) ? o + shat : whi;
+  const int n = static_cast<int>(B - A + 1);
+  const int cap = 2 * shat + 1;
+  T* u0 = sm;        // level n-1, overwritten with level n+1
+  T* u1 = sm + cap;  // level n
+  const int tid = threadIdx.x;
+  for (int x = tid; x < n; x += 64) {
+    u0[x] = p.state[A + x];
+    u1[x] = p.state[p.M + A + x];
+  }
+  __syncthreads();
+  const bool lex = (A == wlo), rex = (B == whi);
+  const T zero = T(0);
+  T* const row = p.flux + static_cast<int64_t>(2 * i + side) * p.ld;
+  const int oi = static_cast<int>(o - A);
+  for (int s = 0; s < shat; ++s) {
+    if (tid == 0) row[s] = (u1[oi + 1] - u1[oi - 1]) * p.r;
+    if (s == shat - 1) break;
+    const T da = p.fa[p.n0 + s + 1], db = p.fb[p.n0 + s + 1];
+    for (int x = tid; x < n; x += 64) {
+      const int64_t j = A + x;
+      T v;
+      if (j == 0) {
+        v = da;
+      } else if (j == p.M - 1) {
+        v = db;
+      } else {
+        const T ul = (x == 0) ? (lex ? fma_(-p.q, zero, u1[1]) : zero) : u1[x - 1];
+        const T ur = (x == n - 1) ? (rex ? fma_(p.q, zero, u1[n - 2]) : zero) : u1[x + 1];
+        v = leap(p.c2, p.k, ul, u1[x], ur, u0[x]);
+      }
+      u0[x] = v;
+    }
+    __syncthreads();
+    T* t = u0;
+    u0 = u1;
+    u1 = t;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Update (Sec. 2.5, Eqs. (13)-(14)) and gluing (Eq. (15)).
+//
+// A tile is NT*MPT consecutive nodes; lane t of the work-group keeps nodes
+// a + t*MPT .. a + t*MPT + MPT-1 of both levels in registers for all S
+// steps.  Per step a lane needs one value from each neighbouring lane: inside
+// a wave by cross-lane shuffle, across waves through a double-buffered LDS
+// slot (one barrier per step).  The region's ends take the window's right
+// input ghost (last lane) or zero data; zero data moves one node per step,
+// and the host only stores nodes it cannot reach.  Waves holding node 0,
+// node M-1 or the window's left input run the general step with those
+// treatments; all other waves run the plain stencil.
+// Loads and stores go through an LDS staging buffer so global accesses are
+// unit-stride across lanes.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int pad32(int x) { return x + (x >> 5); }
+
+template <typename T, int NT, int MPT>
+__device__ __forceinline__ void stage_in(const T* __restrict__ src, int64_t a,
+                                         int64_t M, T* st, T (&v)[MPT]) {
+#pragma unroll
+  for (int it = 0; it < MPT; ++it) {
+    const int x = it * NT + static_cast<int>(threadIdx.x);
+    const int64_t j = a + x;
+    st[pad32(x)] = (j >= 0 && j < M) ? src[j] : T(0);
+  }
+  __syncthreads();
+#pragma unroll
+  for (int e = 0; e < MPT; ++e) v[e] = st[pad32(static_cast<int>(threadIdx.x) * MPT + e)];
+  __syncthreads();
+}
+
+template <typename T, int NT, int MPT>
+__device__ __forceinline__ void stage_out(T* __restrict__ dst, int64_t a,
+                                          int64_t lo, int64_t hi, T* st,
+                                          const T (&v)[MPT]) {
+#pragma unroll
+  for (int e = 0; e < MPT; ++e) st[pad32(static_cast<int>(threadIdx.x) * MPT + e)] = v[e];
+  __syncthreads();
+#pragma unroll
+  for (int it = 0; it < MPT; ++it) {
+    const int x = it * NT + static_cast<int>(threadIdx.x);
+    const int64_t j = a + x;
+    if (j >= lo && j <= hi) dst[j] = st[pad32(x)];
+  }
+  __syncthreads();
+}
+
+// Value of element d of a register array without indexing it: an indexed
+// read (or a select chain the compiler folds into one) would move the whole
+// array to scratch memory.
+template <typename T> struct Bits;
+template <> struct Bits<float> { using U = uint32_t; };
+template <> struct Bits<double> { using U = uint64_t; };
+
+template <typename T, int MPT>
+__device__ __forceinline__ T pick(const T (&v)[MPT], int64_t d) {
+  using U = typename Bits<T>::U;
+  U acc = 0;
+#pragma unroll
+  for (int e = 0; e < MPT; ++e) {
+    const U m = static_cast<U>(0) - static_cast<U>(d == e);
+    acc |= __builtin_bit_cast(U, v[e]) & m;
+  }
+  return __builtin_bit_cast(T, acc);
+}
+
+// cur = level n, old = level n-1 on entry; old = level n+1 on exit.
+template <typename T, int MPT, bool GEN>
+__device__ __forceinline__ void step_chunk(const T (&cur)[MPT], T (&old)[MPT],
+                                           T L, T R, T c2, T k, int64_t base,
+                                           int64_t M, int64_t lin, T glin, T q,
+                                           T da, T db) {
+#pragma unroll
+  for (int e = 0; e < MPT; ++e) {
+    T ul = (e == 0) ? L : cur[e - 1];
+    const T ur = (e == MPT - 1) ? R : cur[e + 1];
+    if (GEN) {
+      if (base + e == lin) ul = fma_(-q, glin, ur);
+    }
+    T v = leap(c2, k, ul, cur[e], ur, old[e]);
+    if (GEN) {
+      if (base + e == 0) v = da;
+      if (base + e == M - 1) v = db;
+    }
+    old[e] = v;
+  }
+}
+
+template <typename T, int NT, int MPT>
+struct UpdateCtx {
+  T (*edge)[2][NT / 64];
+  const T* sR;
+  const T* sL;
+  const T* sA;
+  const T* sB;
+  int64_t base, M, lin;
+  int rb, re, lane, wv;
+  bool gen, right_ghost;
+};
+
+template <typename T, int NT, int MPT>
+__device__ __forceinline__ void one_step(const UpdateArgs<T>& p,
+                                         const UpdateCtx<T, NT, MPT>& c,
+                                         const T (&cur)[MPT], T (&old)[MPT],
+                                         int s) {
+  constexpr int NW = NT / 64;
+  const int par = s & 1;
+  T L = __shfl_up(cur[MPT - 1], 1, 64);
+  T R = __shfl_down(cur[0], 1, 64);
+  if (c.lane == 63) c.edge[par][1][c.wv] = cur[MPT - 1];
+  if (c.lane == 0) c.edge[par][0][c.wv] = cur[0];
+  __syncthreads();
+  if (c.lane == 0) L = (c.wv > 0) ? c.edge[par][1][c.wv - 1] : T(0);
+  if (c.lane == 63)
+    R = (c.wv < NW - 1) ? c.edge[par][0][c.wv + 1]
+                        : (c.right_ghost ? fma_(p.q, c.sR[s], cur[MPT - 2]) : T(0));
+  if (c.gen)
+    step_chunk<T, MPT, true>(cur, old, L, R, p.c2, p.k, c.base, c.M, c.lin, c.sL[s],
+                             p.q, c.sA[s + 1], c.sB[s + 1]);
+  else
+    step_chunk<T, MPT, false>(cur, old, L, R, p.c2, p.k, 0, 0, 0, T(0), T(0), T(0),
+                              T(0));
+  for (int r = c.rb; r < c.re; ++r) {
+    const int64_t d = p.rec_node[r] - c.base;
+    if (d >= 0 && d < MPT)
+      p.traces[static_cast<int64_t>(p.rec_id[r]) * p.trace_ld + p.trace_col0 + s] =
+          pick<T, MPT>(old, d);
+  }
+}
+
+template <typename T, int NT, int MPT>
+__global__ __launch_bounds__(NT) void k_update(const UpdateArgs<T> p) {
+  constexpr int NW = NT / 64;
+  constexpr int TM = NT * MPT;
+  constexpr int TMP = TM + (TM >> 5) + 1;
+  static_assert(NT % 64 == 0 && MPT >= 2, "shape");
+  __shared__ T st[TMP];
+  __shared__ T sR[kMaxSpan], sL[kMaxSpan], sA[kMaxSpan + 1], sB[kMaxSpan + 1];
+  __shared__ T edge[2][2][NW];
+
+  const int tid = threadIdx.x;
+  const int tix = xcd_tile(blockIdx.x, gridDim.x);
+  const Tile tl = p.tiles[tix];
+  int S = p.span_dev ? *p.span_dev : p.span;
+  S = S < kMaxSpan ? S : kMaxSpan;
+  if (S <= 0) return;
+
+  for (int s = tid; s < S; s += NT) {
+    sR[s] = (tl.fr >= 0) ? p.flux[static_cast<int64_t>(2 * tl.fr + 1) * p.ld + s] : T(0);
+    sL[s] = (tl.fl >= 0) ? p.flux[static_cast<int64_t>(2 * tl.fl + 0) * p.ld + s] : T(0);
+  }
+  for (int s = tid; s <= S; s += NT) {
+    sA[s] = p.fa[p.n0 + s];
+    sB[s] = p.fb[p.n0 + s];
+  }
+
+  T u[MPT], uo[MPT];
+  stage_in<T, NT, MPT>(p.state_in + p.M, tl.a, p.M, st, u);  // level n0
+  stage_in<T, NT, MPT>(p.state_in, tl.a, p.M, st, uo);       // level n0-1
+
+  UpdateCtx<T, NT, MPT> c;
+  c.edge = edge;
+  c.sR = sR;
+  c.sL = sL;
+  c.sA = sA;
+  c.sB = sB;
+  c.base = tl.a + static_cast<int64_t>(tid) * MPT;
+  c.M = p.M;
+  c.lin = tl.lin;
+  c.lane = tid & 63;
+  c.wv = tid >> 6;
+  c.right_ghost = tl.fr >= 0;
+  const int64_t end = c.base + MPT;
+  const bool mine = (c.base <= 0 && 0 < end) || (c.base <= p.M - 1 && p.M - 1 < end) ||
+                    (c.base <= tl.lin && tl.lin < end);
+  c.gen = __any(mine) != 0;
+  c.rb = p.rec_ptr ? p.rec_ptr[tix] : 0;
+  c.re = p.rec_ptr ? p.rec_ptr[tix + 1] : 0;
+
+  int s = 0;
+  for (; s + 1 < S; s += 2) {
+    one_step<T, NT, MPT>(p, c, u, uo, s);      // uo <- level n0+s+1
+    one_step<T, NT, MPT>(p, c, uo, u, s + 1);  // u  <- level n0+s+2
+  }
+  if (s < S) {
+    one_step<T, NT, MPT>(p, c, u, uo, s);  // uo = level n0+S, u = n0+S-1
+    stage_out<T, NT, MPT>(p.state_out, tl.a, tl.out_lo, tl.out_hi, st, u);
+    stage_out<T, NT, MPT>(p.state_out + p.M, tl.a, tl.out_lo, tl.out_hi, st, uo);
+  } else {
+    stage_out<T, NT, MPT>(p.state_out, tl.a, tl.out_lo, tl.out_hi, st, uo);
+    stage_out<T, NT, MPT>(p.state_out + p.M, tl.a, tl.out_lo, tl.out_hi, st, u);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Select (Sec. 2.4, Sec. 3 Eq. (19)).  mode 0: min(shat, fixed_span).
+// mode 1: S = min(shat, min_rows min(q_row, cone) + cone), q_row = leading
+// exact zeros of a predicted flux waveform (shat samples).
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(256) void k_select(const SelectArgs<T> a) {
+  __shared__ int smin;
+  if (threadIdx.x == 0) smin = 0x7fffffff;
+  __syncthreads();
+  if (a.mode == 1) {
+    int local = 0x7fffffff;
+    for (int r = threadIdx.x; r < a.n_rows; r += 256) {
+      const T* f = a.flux + static_cast<int64_t>(r) * a.ld;
+      int q = 0;
+      while (q < a.shat && f[q] == T(0)) ++q;
+      q = q < a.cone ? q : a.cone;
+      local = q < local ? q : local;
+    }
+    atomicMin(&smin, local);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int S;
+    if (a.mode == 0) {
+      S = a.shat < a.fixed_span ? a.shat : a.fixed_span;
+    } else {
+      S = a.shat;
+      if (a.n_rows > 0) {
+        const long long lim = static_cast<long long>(smin) + a.cone;
+        if (lim < S) S = static_cast<int>(lim);
+      }
+    }
+    *a.span_dev = S;
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_copy(T* __restrict__ dst, const T* __restrict__ src,
+                                             int64_t n) {
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+       i += stride)
+    dst[i] = src[i];
+}
+
+// ---------------------------------------------------------------------------
+// Launchers.
+// ---------------------------------------------------------------------------
+template <typename T>
+hipError_t launch_predict(const PredictArgs<T>& a, int shmem_nodes, hipStream_t s) {
+  if (a.N < 2) return hipSuccess;
+  const size_t shm = static_cast<size_t>(2 * shmem_nodes) * sizeof(T);
+  hipLaunchKernelGGL(k_predict<T>, dim3(2 * (a.N - 1)), dim3(64), shm, s, a);
+  return hipGetLastError();
+}
+
+#define RSWR_SHAPES(X) \
+  X(64, 8)             \
+  X(128, 8)            \
+  X(256, 8)            \
+  X(256, 16)           \
+  X(320, 13)           \
+  X(512, 8)            \
+  X(512, 12)
+
+static const Shape kShapes[] = {
+#define RSWR_SHAPE_ENTRY(a, b) {a, b},
+    RSWR_SHAPES(RSWR_SHAPE_ENTRY)
+#undef RSWR_SHAPE_ENTRY
+};
+
+int n_shapes() { return static_cast<int>(sizeof(kShapes) / sizeof(kShapes[0])); }
+Shape shape_at(int i) { return kShapes[i]; }
+bool shape_built(int threads, int per_thread) {
+  for (const Shape& s : kShapes)
+    if (s.threads == threads && s.per_thread == per_thread) return true;
+  return false;
+}
+
+template <typename T>
+hipError_t launch_update(const UpdateArgs<T>& a, int threads, int per_thread,
+                         hipStream_t s) {
+  if (a.n_tiles <= 0) return hipSuccess;
+#define RSWR_LAUNCH(NT_, MPT_)                                                   \
+  if (threads == NT_ && per_thread == MPT_) {                                  \
+    hipLaunchKernelGGL((k_update<T, NT_, MPT_>), dim3(a.n_tiles), dim3(NT_), 0, \
+                       s, a);                                                  \
+    return hipGetLastError();                                                  \
+  }
+  RSWR_SHAPES(RSWR_LAUNCH)
+#undef RSWR_LAUNCH
+  return hipErrorInvalidValue;
+}
+
+template <typename T>
+hipError_t launch_select(const SelectArgs<T>& a, hipStream_t s) {
+  hipLaunchKernelGGL(k_select<T>, dim3(1), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_copy(T* dst, const T* src, int64_t n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  int64_t blocks = (n + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(k_copy<T>, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s,
+                     dst, src, n);
+  return hipGetLastError();
+}
+
+template hipError_t launch_predict<float>(const PredictArgs<float>&, int, hipStream_t);
+template hipError_t launch_predict<double>(const PredictArgs<double>&, int, hipStream_t);
+template hipError_t launch_update<float>(const UpdateArgs<float>&, int, int, hipStream_t);
+template hipError_t launch_update<double>(const UpdateArgs<double>&, int, int, hipStream_t);
+template hipError_t launch_select<float>(const SelectArgs<float>&, hipStream_t);
+template hipError_t launch_select<double>(const SelectArgs<double>&, hipStream_t);
+template hipError_t launch_copy<float>(float*, const float*, int64_t, hipStream_t);
+template hipError_t launch_copy<double>(double*, const double*, int64_t, hipStream_t);
+
+}  // namespace rswr

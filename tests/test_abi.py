@@ -1,0 +1,114 @@
+"""Host-side checks of the C-ABI (no GPU needed): the library loads, exports
+every function include/rswr.h declares, and rswr_plan (host only) builds the
+decomposition of Sec. 2.2 / Sec. 3 and the span rule of Sec. 2.4 Eq. (10)."""
+import ctypes
+import json
+import os
+import re
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2203_10477_amd as rs
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+GOLD = os.path.join(ROOT, "tests", "golden")
+
+
+def declared_functions():
+    text = open(os.path.join(ROOT, "include", "rswr.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(rswr_[a-z_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = rs.lib()
+    names = declared_functions()
+    assert "rswr_solve" in names and "rswr_predict" in names and len(names) >= 10
+    for n in names:
+        assert hasattr(L, n), n
+
+
+def test_status_strings():
+    L = rs.lib()
+    for code in range(9):
+        assert L.rswr_status_string(code)
+
+
+@pytest.mark.parametrize("M,N,P", [(1001, 2, 20), (4097, 8, 64), (2 ** 16, 64, 32),
+                                   (301, 20, 20), (257, 1, 2)])
+def test_plan_layout_matches_definition(M, N, P):
+    plan = rs.Plan(M, N, P)
+    lo, hi, olo, ohi = plan.layout()
+    ref = oracle.layout(M, N, P)
+    assert np.array_equal(lo, ref.lo) and np.array_equal(hi, ref.hi)
+    assert np.array_equal(olo, ref.own_lo) and np.array_equal(ohi, ref.own_hi)
+    if N > 1:
+        assert plan.info["span_cone"] == ref.span_cone
+
+
+def test_plan_span_table_golden():
+    gold = json.load(open(os.path.join(GOLD, "span_table.json")))
+    for P, S in gold["rows"]:
+        M = 40 * P + 1
+        plan = rs.Plan(M, 4, P)
+        assert plan.info["span_paper"] == S
+        assert plan.span == min(S, P)
+        plan_d = rs.Plan(M, 4, P, courant_frac=None)  # double-precision rule
+        assert plan_d.info["span_paper"] == S
+
+
+def test_plan_golden_layout():
+    gold = json.load(open(os.path.join(GOLD, "layout_1001_N2_P20.json")))
+    plan = rs.Plan(gold["M"], gold["N"], gold["P"])
+    lo, hi, olo, ohi = plan.layout()
+    assert list(lo) == gold["lo"] and list(hi) == gold["hi"]
+    assert list(olo) == gold["own_lo"] and list(ohi) == gold["own_hi"]
+    assert plan.info["span_cone"] == gold["span_cone"] and plan.span == 11
+
+
+def test_plan_errors():
+    with pytest.raises(rs.RSWRError) as e:
+        rs.Plan(1001, 2, 21)  # odd overlap
+    assert e.value.status == 3
+    with pytest.raises(rs.RSWRError) as e:
+        rs.Plan(1001, 2, 20, courant=1.2)
+    assert e.value.status == 2
+    with pytest.raises(rs.RSWRError) as e:
+        rs.Plan(1001, 2, 20, span=21)  # beyond the light cone
+    assert e.value.status == 4
+    with pytest.raises(rs.RSWRError) as e:
+        rs.Plan(2, 1, 2)
+    assert e.value.status == 1
+    with pytest.raises(rs.RSWRError) as e:
+        rs.Plan(1001, 2, 20, tile=(96, 3))
+    assert e.value.status == 8
+    with pytest.raises(rs.RSWRError) as e:
+        rs.Plan(101, 60, 20)  # cores narrower than the end-core rule allows
+    assert e.value.status == 3
+
+
+def test_explicit_windows_and_cone():
+    lo = [0, 90, 200, 260]
+    hi = [110, 230, 290, 399]
+    plan = rs.Plan(400, 4, 0, windows=(lo, hi))
+    ref = oracle.explicit_layout(400, lo, hi)
+    assert plan.info["span_cone"] == ref.span_cone == 20
+    l2, h2, ol, oh = plan.layout()
+    assert np.array_equal(ol, ref.own_lo) and np.array_equal(oh, ref.own_hi)
+    with pytest.raises(rs.RSWRError):
+        rs.Plan(400, 4, 0, windows=([0, 120, 100, 260], hi))
+
+
+def test_quiet_plan_caps_span_at_twice_the_cone():
+    plan = rs.Plan(1001, 2, 20, span_mode=rs.QUIET)
+    assert plan.info["span"] == 40 and plan.flux_ld >= 40
+
+
+def test_compute_calls_need_a_gpu_tensor():
+    plan = rs.Plan(1001, 2, 20)
+    st = torch.zeros(2, 1001, dtype=torch.float64)
+    with pytest.raises(TypeError):
+        rs.rswr_solve(plan, st, st[0], st[0], 10)
