@@ -129,9 +129,10 @@ rswr_status_t rswr_plan_layout(rswr_plan_t plan, int64_t* lo, int64_t* hi,
                                int64_t* own_lo, int64_t* own_hi);
 
 /* (host) The update work-groups of one span, for inspection: for tile t,
- * tiles[6t..6t+5] = {first node of its register region, last node of the
- * region, first and last node it stores, window index, right-input flag}.
- * `tiles` holds 6 * n_tiles entries (n_tiles from rswr_plan_info). */
+ * tiles[8t..8t+7] = {first node of its register region, last node of the
+ * region, first and last node it stores, window index, left end, right end
+ * (0 zero data, 1 the window's input ghost, 2 the Dirichlet neighbour),
+ * general flag}.  `tiles` holds 8 * n_tiles entries. */
 rswr_status_t rswr_plan_tiles(rswr_plan_t plan, int64_t* tiles);
 
 /* Predict, Sec. 2.3 Eqs. (8)-(9): every window advances `span_hat` levels

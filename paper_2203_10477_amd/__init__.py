@@ -150,9 +150,10 @@ class Plan:
         return tuple(arrs)
 
     def tiles(self):
-        """Update work-groups: int64 [n_tiles, 6] = region first, region last,
-        stored first, stored last, window, right-input flag."""
-        t = np.zeros((self.info["n_tiles"], 6), np.int64)
+        """Update work-groups: int64 [n_tiles, 8] = region first node, region
+        last node, first and last stored node, window, left end, right end
+        (0 zero data, 1 input ghost, 2 Dirichlet neighbour), general flag."""
+        t = np.zeros((self.info["n_tiles"], 8), np.int64)
         _check(lib().rswr_plan_tiles(self._h, t.ctypes.data), "rswr_plan_tiles")
         return t
 

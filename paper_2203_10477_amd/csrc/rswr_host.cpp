@@ -45,6 +45,7 @@ int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
 
 struct DevTables {
   Tile* tiles = nullptr;
+  int32_t* idx = nullptr;  // general tiles first, then the plain ones
   int64_t* lo = nullptr;
   int64_t* hi = nullptr;
   hipStream_t capture = nullptr;
@@ -59,11 +60,12 @@ struct GraphKey {
   const void* traces;
   const void* ws;
   const void* ckpt;
-  int has_rec;
+  int has_rec, n_gen, n_fast;
   bool operator==(const GraphKey& o) const {
     return device == o.device && state == o.state && fa == o.fa && fb == o.fb &&
            n0 == o.n0 && n_steps == o.n_steps && traces == o.traces && ws == o.ws &&
-           ckpt == o.ckpt && has_rec == o.has_rec;
+           ckpt == o.ckpt && has_rec == o.has_rec && n_gen == o.n_gen &&
+           n_fast == o.n_fast;
   }
 };
 
@@ -82,6 +84,8 @@ struct rswr_plan_s {
   int32_t S_cone = 0, S_paper = 0, S = 0, S_max = 0, flux_ld = 0;
   int32_t threads = 0, per_thread = 0;
   std::vector<Tile> tiles;
+  std::vector<int32_t> idx;  // tile order of the launches: general ones first
+  int32_t n_gen = 0;
   std::mutex mu;
   std::map<int, DevTables> dev;
   std::vector<GraphEntry> graphs;
@@ -171,12 +175,15 @@ int32_t paper_span(const rswr_plan_s& p, int32_t num, int32_t den, bool exact) {
 }
 
 // ---------------------------------------------------------------------------
-// Update tiles.  For window i the first tile ends at its right input hi_i
-// (ghost from the last lane) or, for the last window, at node M-1; further
-// tiles cover the rest of the owned range right to left, each ending S nodes
-// past the part it stores.  A tile's region stores only nodes that zero data
-// entering at a cut end cannot reach within S levels; window ends inside a
-// region are treated exactly (Dirichlet node, or the left input's ghost).
+// Update tiles.  Window i is covered right to left.  Its first tile ends at
+// the window's exact right end -- the right input hi_i (ghost from the flux
+// waveform) or, for the last window, node M-2 next to the Dirichlet node
+// M-1.  Further tiles end S nodes past the part they store, since zero data
+// entering at a cut end moves one node per level.  A tile that would reach
+// past the window's exact left end -- the left input lo_i, or node 1 next to
+// the Dirichlet node 0 -- starts exactly there instead.  Only a window
+// smaller than one tile leaves its left end strictly inside the region; that
+// tile is "general" (handled by the general kernel).
 // ---------------------------------------------------------------------------
 bool build_tiles(const rswr_plan_s& p, int TM, int S, std::vector<Tile>& out) {
   out.clear();
@@ -184,22 +191,50 @@ bool build_tiles(const rswr_plan_s& p, int TM, int S, std::vector<Tile>& out) {
     const int64_t lo = p.lo[i], hi = p.hi[i];
     const int64_t Olo = p.own_lo[i], Ohi = p.own_hi[i];
     const bool last = (i == p.N - 1);
+    const int64_t rb0 = last ? p.M - 2 : hi;
+    const int32_t rmode0 = last ? rswr::kEndDirichlet : rswr::kEndGhost;
+    const int64_t lb0 = (i == 0) ? 1 : lo;
+    const int32_t lmode0 = (i == 0) ? rswr::kEndDirichlet : rswr::kEndGhost;
     int64_t cur = Ohi;
     bool first = true;
     while (cur >= Olo) {
       Tile t{};
-      const int64_t rb = first ? (last ? p.M - 1 : hi) : cur + S;
-      if (!first && !last && rb >= hi) return false;
-      t.a = rb - TM + 1;
-      const bool lex = (t.a <= lo);
-      const int64_t vlo = lex ? lo : t.a + S;
-      t.out_hi = cur;
-      t.out_lo = std::max(vlo, Olo);
-      if (t.out_lo > t.out_hi) return false;
-      t.fr = (first && !last) ? i : -1;
-      t.lin = (lex && i > 0) ? lo : rswr::kNoNode;
-      t.fl = (lex && i > 0) ? i - 1 : -1;
+      t.lin = rswr::kNoNode;
+      t.fl = -1;
+      t.fr = -1;
       t.window = i;
+      int64_t rb;
+      if (first) {
+        rb = rb0;
+        t.rmode = rmode0;
+        if (!last) t.fr = i;
+      } else {
+        rb = cur + S;
+        t.rmode = rswr::kEndZero;
+        if (rb >= rb0) return false;
+      }
+      t.a = rb - TM + 1;
+      t.lmode = rswr::kEndZero;
+      bool exact_left = false;
+      if (t.a <= lb0) {
+        exact_left = true;
+        if (t.a == lb0 || !first) {
+          t.a = lb0;
+          t.lmode = lmode0;
+          if (i > 0) t.fl = i - 1;
+        } else {
+          t.general = 1;  // the window's left end lies inside the region
+          if (i > 0) {
+            t.lin = lo;
+            t.fl = i - 1;
+          }
+        }
+      }
+      t.out_hi = cur;
+      t.out_lo = exact_left ? Olo : std::max(t.a + S, Olo);
+      const int64_t b = t.a + TM - 1;
+      if (t.rmode == rswr::kEndZero && t.out_hi > b - S) return false;
+      if (t.out_lo > t.out_hi) return false;
       out.push_back(t);
       cur = t.out_lo - 1;
       first = false;
@@ -220,8 +255,9 @@ bool choose_shape(rswr_plan_s& p) {
     const int TM = sh.threads * sh.per_thread;
     if (TM < 2 * p.S_max + 2) continue;
     if (!build_tiles(p, TM, p.S_max, tiles)) continue;
-    const double nt = double(tiles.size());
-    const double cost = nt * TM * std::max(1.0, 512.0 / nt);
+    double nt = 0;
+    for (const Tile& t : tiles) nt += t.general ? 2.0 : 1.0;
+    const double cost = nt * TM * std::max(1.0, 512.0 / double(tiles.size()));
     if (!found || cost < best) {
       best = cost;
       found = true;
@@ -241,11 +277,15 @@ rswr_status_t ensure_device(rswr_plan_s* p, DevTables** out, int* device) {
     DevTables t;
     const size_t nt = std::max<size_t>(p->tiles.size(), 1);
     RSWR_HIP(hipMalloc(&t.tiles, nt * sizeof(Tile)));
+    RSWR_HIP(hipMalloc(&t.idx, nt * sizeof(int32_t)));
     RSWR_HIP(hipMalloc(&t.lo, p->N * sizeof(int64_t)));
     RSWR_HIP(hipMalloc(&t.hi, p->N * sizeof(int64_t)));
-    if (!p->tiles.empty())
+    if (!p->tiles.empty()) {
       RSWR_HIP(hipMemcpy(t.tiles, p->tiles.data(), p->tiles.size() * sizeof(Tile),
                          hipMemcpyHostToDevice));
+      RSWR_HIP(hipMemcpy(t.idx, p->idx.data(), p->idx.size() * sizeof(int32_t),
+                         hipMemcpyHostToDevice));
+    }
     RSWR_HIP(hipMemcpy(t.lo, p->lo.data(), p->N * sizeof(int64_t), hipMemcpyHostToDevice));
     RSWR_HIP(hipMemcpy(t.hi, p->hi.data(), p->N * sizeof(int64_t), hipMemcpyHostToDevice));
     RSWR_HIP(hipStreamCreateWithFlags(&t.capture, hipStreamNonBlocking));
@@ -295,7 +335,6 @@ rswr::UpdateArgs<T> update_args(const rswr_plan_s& p, const DevTables& d,
   a.span_dev = span_dev;
   a.M = p.M;
   a.n0 = n0;
-  a.n_tiles = static_cast<int32_t>(p.tiles.size());
   a.span = span;
   a.ld = p.flux_ld;
   const double c2 = p.lam * p.lam;
@@ -305,22 +344,50 @@ rswr::UpdateArgs<T> update_args(const rswr_plan_s& p, const DevTables& d,
   return a;
 }
 
+// The two update launches of one span: general tiles (and, in a solve, the
+// tiles holding receivers) through the general kernel, the rest through the
+// plain one.
+template <typename T>
+hipError_t launch_update_pair(const rswr_plan_s& p, rswr::UpdateArgs<T> a,
+                              const int32_t* gen_idx, int32_t n_gen,
+                              const int32_t* fast_idx, int32_t n_fast, hipStream_t s) {
+  if (n_gen > 0) {
+    a.tile_idx = gen_idx;
+    a.n_tiles = n_gen;
+    hipError_t e = rswr::launch_update<T>(a, p.threads, p.per_thread, true, s);
+    if (e != hipSuccess) return e;
+  }
+  if (n_fast > 0) {
+    a.tile_idx = fast_idx;
+    a.n_tiles = n_fast;
+    a.rec_ptr = nullptr;
+    return rswr::launch_update<T>(a, p.threads, p.per_thread, false, s);
+  }
+  return hipSuccess;
+}
+
 size_t elem_size(const rswr_plan_s& p) { return p.dtype == RSWR_F64 ? 8 : 4; }
 
 struct WsLayout {
-  size_t state = 0, flux = 0, rec_ptr = 0, rec_node = 0, rec_id = 0, total = 0;
+  size_t state = 0, flux = 0, gen_idx = 0, fast_idx = 0, rec_ptr = 0, rec_node = 0,
+         rec_id = 0, total = 0;
 };
 
 WsLayout ws_layout(const rswr_plan_s& p, int32_t n_rec) {
   WsLayout w;
   const size_t b = elem_size(p);
+  const size_t nt = p.tiles.size();
   size_t off = 0;
   w.state = off;
   off += round_up(2 * size_t(p.M) * b, 256);
   w.flux = off;
   off += round_up(size_t(std::max(p.N - 1, 1)) * 2 * p.flux_ld * b, 256);
+  w.gen_idx = off;
+  off += round_up(std::max<size_t>(nt, 1) * sizeof(int32_t), 256);
+  w.fast_idx = off;
+  off += round_up(std::max<size_t>(nt, 1) * sizeof(int32_t), 256);
   w.rec_ptr = off;
-  off += round_up((p.tiles.size() + 1) * sizeof(int32_t), 256);
+  off += round_up((nt + 1) * sizeof(int32_t), 256);
   w.rec_node = off;
   off += round_up(size_t(std::max(n_rec, 1)) * sizeof(int64_t), 256);
   w.rec_id = off;
@@ -329,10 +396,20 @@ WsLayout ws_layout(const rswr_plan_s& p, int32_t n_rec) {
   return w;
 }
 
+// Launch lists of one solve: where the lists live and how long they are.
+struct Lists {
+  const int32_t* gen = nullptr;
+  const int32_t* fast = nullptr;
+  int32_t n_gen = 0, n_fast = 0;
+  const int32_t* rec_ptr = nullptr;
+  const int64_t* rec_node = nullptr;
+  const int32_t* rec_id = nullptr;
+};
+
 template <typename T>
 rswr_status_t enqueue_solve(rswr_plan_s* p, const DevTables& d, void* state,
                             const void* fa, const void* fb, int64_t n0, int64_t n_steps,
-                            bool has_rec, void* traces, char* ws, const WsLayout& L,
+                            const Lists& lists, void* traces, char* ws, const WsLayout& L,
                             void* ckpt, hipStream_t s) {
   const int64_t M = p->M;
   const int64_t K = (n_steps + p->S - 1) / p->S;
@@ -359,15 +436,16 @@ rswr_status_t enqueue_solve(rswr_plan_s* p, const DevTables& d, void* state,
     RSWR_HIP(rswr::launch_predict<T>(pa, 2 * p->S_max + 1, s));
     rswr::UpdateArgs<T> ua =
         update_args<T>(*p, d, in, fa, fb, lev, flux, nullptr, S, out);
-    if (has_rec) {
-      ua.rec_ptr = reinterpret_cast<const int32_t*>(ws + L.rec_ptr);
-      ua.rec_node = reinterpret_cast<const int64_t*>(ws + L.rec_node);
-      ua.rec_id = reinterpret_cast<const int32_t*>(ws + L.rec_id);
+    if (lists.rec_ptr) {
+      ua.rec_ptr = lists.rec_ptr;
+      ua.rec_node = lists.rec_node;
+      ua.rec_id = lists.rec_id;
       ua.traces = static_cast<T*>(traces);
       ua.trace_ld = n_steps;
       ua.trace_col0 = lev - n0;
     }
-    RSWR_HIP(rswr::launch_update<T>(ua, p->threads, p->per_thread, s));
+    RSWR_HIP(launch_update_pair<T>(*p, ua, lists.gen, lists.n_gen, lists.fast, lists.n_fast,
+                                   s));
     lev += S;
     std::swap(x, y);
   }
@@ -502,6 +580,11 @@ rswr_status_t rswr_plan(const rswr_desc_t* desc, rswr_plan_t* out) {
     }
     build_tiles(*p, p->threads * p->per_thread, p->S_max, p->tiles);
   }
+  for (size_t t = 0; t < p->tiles.size(); ++t)
+    if (p->tiles[t].general) p->idx.push_back(static_cast<int32_t>(t));
+  p->n_gen = static_cast<int32_t>(p->idx.size());
+  for (size_t t = 0; t < p->tiles.size(); ++t)
+    if (!p->tiles[t].general) p->idx.push_back(static_cast<int32_t>(t));
   *out = p;
   return RSWR_OK;
 }
@@ -517,6 +600,7 @@ rswr_status_t rswr_plan_destroy(rswr_plan_t p) {
   for (auto& kv : p->dev) {
     (void)hipSetDevice(kv.first);
     (void)hipFree(kv.second.tiles);
+    (void)hipFree(kv.second.idx);
     (void)hipFree(kv.second.lo);
     (void)hipFree(kv.second.hi);
     if (kv.second.capture) (void)hipStreamDestroy(kv.second.capture);
@@ -562,12 +646,15 @@ rswr_status_t rswr_plan_tiles(rswr_plan_t p, int64_t* out) {
   const int64_t TM = int64_t(p->threads) * p->per_thread;
   for (size_t t = 0; t < p->tiles.size(); ++t) {
     const Tile& x = p->tiles[t];
-    out[6 * t + 0] = x.a;
-    out[6 * t + 1] = x.a + TM - 1;
-    out[6 * t + 2] = x.out_lo;
-    out[6 * t + 3] = x.out_hi;
-    out[6 * t + 4] = x.window;
-    out[6 * t + 5] = x.fr >= 0 ? 1 : 0;
+    int64_t* o = out + 8 * t;
+    o[0] = x.a;
+    o[1] = x.a + TM - 1;
+    o[2] = x.out_lo;
+    o[3] = x.out_hi;
+    o[4] = x.window;
+    o[5] = x.lmode;
+    o[6] = x.rmode;
+    o[7] = x.general;
   }
   return RSWR_OK;
 }
@@ -630,15 +717,18 @@ rswr_status_t rswr_update(rswr_plan_t p, const void* state_in, const void* f_a,
   rswr_status_t st = ensure_device(p, &d, nullptr);
   if (st != RSWR_OK) return st;
   hipStream_t s = static_cast<hipStream_t>(stream);
+  const int32_t n_all = static_cast<int32_t>(p->tiles.size());
   hipError_t e;
   if (p->dtype == RSWR_F64)
-    e = rswr::launch_update<double>(update_args<double>(*p, *d, state_in, f_a, f_b, n0, flux,
-                                                        span_dev, span, state_out),
-                                    p->threads, p->per_thread, s);
+    e = launch_update_pair<double>(
+        *p, update_args<double>(*p, *d, state_in, f_a, f_b, n0, flux, span_dev, span,
+                                state_out),
+        d->idx, p->n_gen, d->idx + p->n_gen, n_all - p->n_gen, s);
   else
-    e = rswr::launch_update<float>(update_args<float>(*p, *d, state_in, f_a, f_b, n0, flux,
-                                                      span_dev, span, state_out),
-                                   p->threads, p->per_thread, s);
+    e = launch_update_pair<float>(
+        *p, update_args<float>(*p, *d, state_in, f_a, f_b, n0, flux, span_dev, span,
+                               state_out),
+        d->idx, p->n_gen, d->idx + p->n_gen, n_all - p->n_gen, s);
   if (e != hipSuccess) return hip_fail(e, "update launch");
   return RSWR_OK;
 }
@@ -674,46 +764,70 @@ rswr_status_t rswr_solve(rswr_plan_t p, void* state, const void* f_a, const void
   hipStream_t s = static_cast<hipStream_t>(stream);
   char* ws = static_cast<char*>(workspace);
 
-  if (n_rec > 0) {
-    // receiver r is recorded by the tile whose stored range holds its node
-    const size_t nt = p->tiles.size();
-    std::vector<std::vector<int32_t>> per(nt);
-    for (int32_t r = 0; r < n_rec; ++r) {
-      for (size_t t = 0; t < nt; ++t)
+  Lists lists;
+  const int32_t n_all = static_cast<int32_t>(p->tiles.size());
+  if (n_rec == 0) {
+    lists.gen = d->idx;
+    lists.n_gen = p->n_gen;
+    lists.fast = d->idx + p->n_gen;
+    lists.n_fast = n_all - p->n_gen;
+  } else {
+    // receiver r is recorded by the tile whose stored range holds its node;
+    // such tiles run through the general kernel, which records traces
+    std::vector<std::vector<int32_t>> per(n_all);
+    for (int32_t r = 0; r < n_rec; ++r)
+      for (int32_t t = 0; t < n_all; ++t)
         if (rec_idx[r] >= p->tiles[t].out_lo && rec_idx[r] <= p->tiles[t].out_hi) {
           per[t].push_back(r);
           break;
         }
-    }
-    std::vector<int32_t> ptr(nt + 1, 0), id;
+    std::vector<int32_t> gen, fast, ptr(1, 0), id;
     std::vector<int64_t> node;
-    for (size_t t = 0; t < nt; ++t) {
-      for (int32_t r : per[t]) {
-        id.push_back(r);
-        node.push_back(rec_idx[r]);
+    for (int32_t t = 0; t < n_all; ++t) {
+      if (p->tiles[t].general || !per[t].empty()) {
+        gen.push_back(t);
+        for (int32_t r : per[t]) {
+          id.push_back(r);
+          node.push_back(rec_idx[r]);
+        }
+        ptr.push_back(static_cast<int32_t>(id.size()));
+      } else {
+        fast.push_back(t);
       }
-      ptr[t + 1] = static_cast<int32_t>(id.size());
     }
+    if (!gen.empty())
+      RSWR_HIP(hipMemcpyAsync(ws + L.gen_idx, gen.data(), gen.size() * sizeof(int32_t),
+                              hipMemcpyHostToDevice, s));
+    if (!fast.empty())
+      RSWR_HIP(hipMemcpyAsync(ws + L.fast_idx, fast.data(), fast.size() * sizeof(int32_t),
+                              hipMemcpyHostToDevice, s));
     RSWR_HIP(hipMemcpyAsync(ws + L.rec_ptr, ptr.data(), ptr.size() * sizeof(int32_t),
                             hipMemcpyHostToDevice, s));
     RSWR_HIP(hipMemcpyAsync(ws + L.rec_node, node.data(), node.size() * sizeof(int64_t),
                             hipMemcpyHostToDevice, s));
     RSWR_HIP(hipMemcpyAsync(ws + L.rec_id, id.data(), id.size() * sizeof(int32_t),
                             hipMemcpyHostToDevice, s));
+    lists.gen = reinterpret_cast<const int32_t*>(ws + L.gen_idx);
+    lists.fast = reinterpret_cast<const int32_t*>(ws + L.fast_idx);
+    lists.n_gen = static_cast<int32_t>(gen.size());
+    lists.n_fast = static_cast<int32_t>(fast.size());
+    lists.rec_ptr = reinterpret_cast<const int32_t*>(ws + L.rec_ptr);
+    lists.rec_node = reinterpret_cast<const int64_t*>(ws + L.rec_node);
+    lists.rec_id = reinterpret_cast<const int32_t*>(ws + L.rec_id);
   }
 
   const bool eager = std::getenv("RSWR_NO_GRAPH") != nullptr;
   auto enqueue = [&](hipStream_t q) {
     return p->dtype == RSWR_F64
-               ? enqueue_solve<double>(p, *d, state, f_a, f_b, n0, n_steps, n_rec > 0,
+               ? enqueue_solve<double>(p, *d, state, f_a, f_b, n0, n_steps, lists,
                                        traces, ws, L, checkpoints, q)
-               : enqueue_solve<float>(p, *d, state, f_a, f_b, n0, n_steps, n_rec > 0,
+               : enqueue_solve<float>(p, *d, state, f_a, f_b, n0, n_steps, lists,
                                       traces, ws, L, checkpoints, q);
   };
   if (eager) return enqueue(s);
 
   const GraphKey key{device, state, f_a, f_b, n0, n_steps, traces, workspace, checkpoints,
-                     n_rec > 0};
+                     n_rec > 0, lists.n_gen, lists.n_fast};
   hipGraphExec_t exec = nullptr;
   {
     std::lock_guard<std::mutex> g(p->mu);

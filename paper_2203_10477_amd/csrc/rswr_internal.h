@@ -13,21 +13,32 @@ constexpr int kMaxSpan = 256;
 // Sentinel for "no left-input ghost in this tile".
 constexpr int64_t kNoNode = INT64_MIN;
 
-// One update work-group: a contiguous register-resident region
-// [a, a + threads*per_thread - 1] of one window.  Only out_lo..out_hi (the
-// part of the window's owned range that the region computes exactly) is
-// stored.  fr >= 0: the region's last node is the window's right input
-// boundary hi_fr, whose ghost comes from flux row [fr][1].  lin != kNoNode:
-// node lin (inside the region) is the window's left input boundary, ghost
-// from flux row [fl][0].  Nodes 0 and M-1 are Dirichlet wherever they fall.
+// Treatment of the neighbour just outside a tile's register region.
+enum : int32_t {
+  kEndZero = 0,       // zero data: the host stores no node it can reach
+  kEndGhost = 1,      // the region end is the window's input boundary: ghost
+                      // value from that input's flux waveform
+  kEndDirichlet = 2   // the neighbour is node 0 (left) or node M-1 (right):
+                      // its Dirichlet value, Eq. (3)
+};
+
+// One update work-group: lanes hold the register region
+// [a, a + threads*per_thread - 1] of window `window` for the whole span.  The
+// tile stores the nodes out_lo..out_hi (clipped to the region, plus node 0 /
+// node M-1 when the matching end is kEndDirichlet).  fl / fr: flux rows of
+// the left / right input ([fl][0], [fr][1]).  General tiles hold the
+// window's left input `lin` or node 0 strictly inside the region (small
+// windows); they run the general kernel.
 struct Tile {
   int64_t a;
   int64_t out_lo, out_hi;
   int64_t lin;
   int32_t fl, fr;
-  int32_t window, pad;
+  int32_t lmode, rmode;
+  int32_t window, general;
+  int32_t pad[2];
 };
-static_assert(sizeof(Tile) == 48, "Tile layout");
+static_assert(sizeof(Tile) == 64, "Tile layout");
 
 template <typename T>
 struct PredictArgs {
@@ -50,8 +61,9 @@ struct UpdateArgs {
   const T* fb;
   const T* flux;        // [N-1][2][ld]
   const Tile* tiles;
+  const int32_t* tile_idx;  // [n_tiles] entries of `tiles` this launch runs
   const int32_t* span_dev;  // nullable
-  const int32_t* rec_ptr;   // [n_tiles+1] or nullptr
+  const int32_t* rec_ptr;   // [n_tiles+1] CSR over this launch, or nullptr
   const int64_t* rec_node;
   const int32_t* rec_id;
   T* traces;
@@ -73,7 +85,7 @@ hipError_t launch_predict(const PredictArgs<T>& a, int shmem_nodes,
                           hipStream_t s);
 template <typename T>
 hipError_t launch_update(const UpdateArgs<T>& a, int threads, int per_thread,
-                         hipStream_t s);
+                         bool general, hipStream_t s);
 template <typename T>
 hipError_t launch_select(const SelectArgs<T>& a, hipStream_t s);
 template <typename T>

@@ -16,6 +16,30 @@ __device__ __forceinline__ double fma_(double a, double b, double c) {
   return __builtin_fma(a, b, c);
 }
 
+// Whole-wave lane shifts (DPP wave_shr:1 / wave_shl:1): a VALU move, no LDS
+// round trip.  Lane l receives lane l-1's (prev) or lane l+1's (next) value;
+// the lane at the wave's end receives its own value and is overwritten by
+// the caller.
+template <int CTRL>
+__device__ __forceinline__ uint32_t dpp32(uint32_t v) {
+  return static_cast<uint32_t>(__builtin_amdgcn_update_dpp(
+      static_cast<int>(v), static_cast<int>(v), CTRL, 0xf, 0xf, false));
+}
+constexpr int kWaveShr1 = 0x138;
+constexpr int kWaveShl1 = 0x130;
+
+template <int CTRL>
+__device__ __forceinline__ float lane_shift(float v) {
+  return __builtin_bit_cast(float, dpp32<CTRL>(__builtin_bit_cast(uint32_t, v)));
+}
+template <int CTRL>
+__device__ __forceinline__ double lane_shift(double v) {
+  const uint64_t b = __builtin_bit_cast(uint64_t, v);
+  const uint64_t lo = dpp32<CTRL>(static_cast<uint32_t>(b));
+  const uint64_t hi = dpp32<CTRL>(static_cast<uint32_t>(b >> 32));
+  return __builtin_bit_cast(double, lo | (hi << 32));
+}
+
 // Second-order leapfrog for Eq. (1) at one node.
 template <typename T>
 __device__ __forceinline__ T leap(T c2, T k, T ul, T u, T ur, T u_old) {
@@ -47,6 +71,7 @@ template <typename T>
 __global__ __launch_bounds__(64) void k_predict(const PredictArgs<T> p) {
   extern __shared__ unsigned char smem_raw[];
   T* const sm = reinterpret_cast<T*>(smem_raw);
+  __shared__ T sda[kMaxSpan], sdb[kMaxSpan];
   const int i = blockIdx.x >> 1, side = blockIdx.x & 1;
   const int w = i + side;
   const int64_t o = (side == 0) ? p.lo[i + 1] : p.hi[i];
@@ -59,6 +84,10 @@ __global__ __launch_bounds__(64) void k_predict(const PredictArgs<T> p) {
   T* u0 = sm;        // level n-1, overwritten with level n+1
   T* u1 = sm + cap;  // level n
   const int tid = threadIdx.x;
+  for (int s = tid; s + 1 < shat; s += 64) {
+    sda[s] = p.fa[p.n0 + s + 1];
+    sdb[s] = p.fb[p.n0 + s + 1];
+  }
   for (int x = tid; x < n; x += 64) {
     u0[x] = p.state[A + x];
     u1[x] = p.state[p.M + A + x];
@@ -71,7 +100,7 @@ __global__ __launch_bounds__(64) void k_predict(const PredictArgs<T> p) {
   for (int s = 0; s < shat; ++s) {
     if (tid == 0) row[s] = (u1[oi + 1] - u1[oi - 1]) * p.r;
     if (s == shat - 1) break;
-    const T da = p.fa[p.n0 + s + 1], db = p.fb[p.n0 + s + 1];
+    const T da = sda[s], db = sdb[s];
     for (int x = tid; x < n; x += 64) {
       const int64_t j = A + x;
       T v;
@@ -99,8 +128,8 @@ __global__ __launch_bounds__(64) void k_predict(const PredictArgs<T> p) {
 // A tile is NT*MPT consecutive nodes; lane t of the work-group keeps nodes
 // a + t*MPT .. a + t*MPT + MPT-1 of both levels in registers for all S
 // steps.  Per step a lane needs one value from each neighbouring lane: inside
-// a wave by cross-lane shuffle, across waves through a double-buffered LDS
-// slot (one barrier per step).  The region's ends take the window's right
+// a wave by a DPP lane shift, across waves through a double-buffered LDS slot
+// (one barrier per step).  The region's ends take the window's right
 // input ghost (last lane) or zero data; zero data moves one node per step,
 // and the host only stores nodes it cannot reach.  Waves holding node 0,
 // node M-1 or the window's left input run the general step with those
@@ -110,33 +139,61 @@ __global__ __launch_bounds__(64) void k_predict(const PredictArgs<T> p) {
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ int pad32(int x) { return x + (x >> 5); }
 
+// Issue every load of a level before the first wait.  Regions fully inside
+// [0, M) read through a wave-uniform base pointer with 32-bit lane offsets;
+// edge regions clamp the index into [0, M) and replace the out-of-range
+// nodes by zero afterwards, so no load sits behind a branch either way.
 template <typename T, int NT, int MPT>
-__device__ __forceinline__ void stage_in(const T* __restrict__ src, int64_t a,
-                                         int64_t M, T* st, T (&v)[MPT]) {
+__device__ __forceinline__ void load_level(const T* __restrict__ src, int64_t a,
+                                           int64_t M, bool inside, T (&tmp)[MPT]) {
+  const int tid = static_cast<int>(threadIdx.x);
+  if (inside) {
+    const T* __restrict__ b = src + a;
 #pragma unroll
-  for (int it = 0; it < MPT; ++it) {
-    const int x = it * NT + static_cast<int>(threadIdx.x);
-    const int64_t j = a + x;
-    st[pad32(x)] = (j >= 0 && j < M) ? src[j] : T(0);
+    for (int it = 0; it < MPT; ++it) tmp[it] = b[it * NT + tid];
+  } else {
+#pragma unroll
+    for (int it = 0; it < MPT; ++it) {
+      const int64_t j = a + it * NT + tid;
+      const int64_t jc = j < 0 ? 0 : (j >= M ? M - 1 : j);
+      tmp[it] = src[jc];
+    }
+#pragma unroll
+    for (int it = 0; it < MPT; ++it) {
+      const int64_t j = a + it * NT + tid;
+      tmp[it] = (j >= 0 && j < M) ? tmp[it] : T(0);
+    }
   }
+}
+
+// Unit-stride (coalesced) values -> LDS -> this lane's MPT consecutive nodes.
+template <typename T, int NT, int MPT>
+__device__ __forceinline__ void transpose_in(const T (&tmp)[MPT], T* st, T (&v)[MPT]) {
+#pragma unroll
+  for (int it = 0; it < MPT; ++it) st[pad32(it * NT + static_cast<int>(threadIdx.x))] = tmp[it];
   __syncthreads();
 #pragma unroll
   for (int e = 0; e < MPT; ++e) v[e] = st[pad32(static_cast<int>(threadIdx.x) * MPT + e)];
   __syncthreads();
 }
 
+// This lane's nodes -> LDS -> unit-stride stores of the stored range
+// [a + xlo, a + xhi] (offsets relative to the region start).
 template <typename T, int NT, int MPT>
-__device__ __forceinline__ void stage_out(T* __restrict__ dst, int64_t a,
-                                          int64_t lo, int64_t hi, T* st,
-                                          const T (&v)[MPT]) {
+__device__ __forceinline__ void stage_out(T* __restrict__ dst, int64_t a, int xlo,
+                                          int xhi, T* st, const T (&v)[MPT]) {
+  const int tid = static_cast<int>(threadIdx.x);
 #pragma unroll
-  for (int e = 0; e < MPT; ++e) st[pad32(static_cast<int>(threadIdx.x) * MPT + e)] = v[e];
+  for (int e = 0; e < MPT; ++e) st[pad32(tid * MPT + e)] = v[e];
   __syncthreads();
+  T tmp[MPT];
+#pragma unroll
+  for (int it = 0; it < MPT; ++it) tmp[it] = st[pad32(it * NT + tid)];
+  T* __restrict__ b = dst + a;
 #pragma unroll
   for (int it = 0; it < MPT; ++it) {
-    const int x = it * NT + static_cast<int>(threadIdx.x);
-    const int64_t j = a + x;
-    if (j >= lo && j <= hi) dst[j] = st[pad32(x)];
+    const int x = it * NT + tid;
+    if (x >= xlo && x <= xhi) b[x] = tmp[it];
   }
   __syncthreads();
 }
@@ -161,23 +218,20 @@ __device__ __forceinline__ T pick(const T (&v)[MPT], int64_t d) {
 }
 
 // cur = level n, old = level n-1 on entry; old = level n+1 on exit.
+// GEN: element dl takes the left-input ghost as its left neighbour and
+// element d0 is the Dirichlet node 0 (offsets relative to this lane's first
+// node; out-of-range offsets match no element).
 template <typename T, int MPT, bool GEN>
 __device__ __forceinline__ void step_chunk(const T (&cur)[MPT], T (&old)[MPT],
-                                           T L, T R, T c2, T k, int64_t base,
-                                           int64_t M, int64_t lin, T glin, T q,
-                                           T da, T db) {
+                                           T L, T R, T c2, T k, int dl, int d0,
+                                           T ghost, T da) {
 #pragma unroll
   for (int e = 0; e < MPT; ++e) {
     T ul = (e == 0) ? L : cur[e - 1];
     const T ur = (e == MPT - 1) ? R : cur[e + 1];
-    if (GEN) {
-      if (base + e == lin) ul = fma_(-q, glin, ur);
-    }
+    if (GEN) ul = (e == dl) ? ghost : ul;
     T v = leap(c2, k, ul, cur[e], ur, old[e]);
-    if (GEN) {
-      if (base + e == 0) v = da;
-      if (base + e == M - 1) v = db;
-    }
+    if (GEN) v = (e == d0) ? da : v;
     old[e] = v;
   }
 }
@@ -189,42 +243,63 @@ struct UpdateCtx {
   const T* sL;
   const T* sA;
   const T* sB;
-  int64_t base, M, lin;
+  int64_t base;
+  int dl, d0;
   int rb, re, lane, wv;
-  bool gen, right_ghost;
+  int lmode, rmode;
+  bool gen;
 };
 
-template <typename T, int NT, int MPT>
+// Value just outside the region: zero data, the input ghost (Eqs. (6)-(7)
+// with a centred flux), or the Dirichlet value of Eq. (3).
+template <typename T>
+__device__ __forceinline__ T end_value(int mode, T ghost, T dir) {
+  return (mode == kEndGhost) ? ghost : ((mode == kEndDirichlet) ? dir : T(0));
+}
+
+template <typename T, int NT, int MPT, bool GEN>
 __device__ __forceinline__ void one_step(const UpdateArgs<T>& p,
                                          const UpdateCtx<T, NT, MPT>& c,
                                          const T (&cur)[MPT], T (&old)[MPT],
                                          int s) {
   constexpr int NW = NT / 64;
   const int par = s & 1;
-  T L = __shfl_up(cur[MPT - 1], 1, 64);
-  T R = __shfl_down(cur[0], 1, 64);
+  T L = lane_shift<kWaveShr1>(cur[MPT - 1]);
+  T R = lane_shift<kWaveShl1>(cur[0]);
   if (c.lane == 63) c.edge[par][1][c.wv] = cur[MPT - 1];
   if (c.lane == 0) c.edge[par][0][c.wv] = cur[0];
   __syncthreads();
-  if (c.lane == 0) L = (c.wv > 0) ? c.edge[par][1][c.wv - 1] : T(0);
+  if (c.lane == 0)
+    L = (c.wv > 0) ? c.edge[par][1][c.wv - 1]
+                   : end_value(c.lmode, fma_(-p.q, c.sL[s], cur[1]), c.sA[s]);
   if (c.lane == 63)
     R = (c.wv < NW - 1) ? c.edge[par][0][c.wv + 1]
-                        : (c.right_ghost ? fma_(p.q, c.sR[s], cur[MPT - 2]) : T(0));
-  if (c.gen)
-    step_chunk<T, MPT, true>(cur, old, L, R, p.c2, p.k, c.base, c.M, c.lin, c.sL[s],
-                             p.q, c.sA[s + 1], c.sB[s + 1]);
-  else
-    step_chunk<T, MPT, false>(cur, old, L, R, p.c2, p.k, 0, 0, 0, T(0), T(0), T(0),
-                              T(0));
-  for (int r = c.rb; r < c.re; ++r) {
-    const int64_t d = p.rec_node[r] - c.base;
-    if (d >= 0 && d < MPT)
-      p.traces[static_cast<int64_t>(p.rec_id[r]) * p.trace_ld + p.trace_col0 + s] =
-          pick<T, MPT>(old, d);
+                        : end_value(c.rmode, fma_(p.q, c.sR[s], cur[MPT - 2]), c.sB[s]);
+  if (GEN && c.gen) {
+    // the left-input ghost u_{lin-1} = u_{lin+1} - 2dx F; its right
+    // neighbour may sit in the next lane
+    const int rn = c.dl + 1;
+    const T right = (rn == MPT) ? R : pick<T, MPT>(cur, rn);
+    const T ghost = fma_(-p.q, c.sL[s], right);
+    step_chunk<T, MPT, true>(cur, old, L, R, p.c2, p.k, c.dl, c.d0, ghost, c.sA[s + 1]);
+  } else {
+    step_chunk<T, MPT, false>(cur, old, L, R, p.c2, p.k, 0, 0, T(0), T(0));
+  }
+  if (GEN) {
+    for (int r = c.rb; r < c.re; ++r) {
+      const int64_t d = p.rec_node[r] - c.base;
+      T* dst = p.traces + static_cast<int64_t>(p.rec_id[r]) * p.trace_ld + p.trace_col0 + s;
+      if (d >= 0 && d < MPT)
+        *dst = pick<T, MPT>(old, d);
+      else if (d == -1 && c.lane == 0 && c.wv == 0 && c.lmode == kEndDirichlet)
+        *dst = c.sA[s + 1];
+      else if (d == MPT && c.lane == 63 && c.wv == NW - 1 && c.rmode == kEndDirichlet)
+        *dst = c.sB[s + 1];
+    }
   }
 }
 
-template <typename T, int NT, int MPT>
+template <typename T, int NT, int MPT, bool GEN>
 __global__ __launch_bounds__(NT) void k_update(const UpdateArgs<T> p) {
   constexpr int NW = NT / 64;
   constexpr int TM = NT * MPT;
@@ -235,24 +310,33 @@ __global__ __launch_bounds__(NT) void k_update(const UpdateArgs<T> p) {
   __shared__ T edge[2][2][NW];
 
   const int tid = threadIdx.x;
-  const int tix = xcd_tile(blockIdx.x, gridDim.x);
+  const int slot = xcd_tile(blockIdx.x, gridDim.x);
+  const int tix = p.tile_idx[slot];
   const Tile tl = p.tiles[tix];
   int S = p.span_dev ? *p.span_dev : p.span;
   S = S < kMaxSpan ? S : kMaxSpan;
   if (S <= 0) return;
 
+  // per-step boundary data: input flux waveforms, and the Dirichlet values of
+  // nodes 0 and M-1 (level n0 from the state, later levels from f_A, f_B)
   for (int s = tid; s < S; s += NT) {
     sR[s] = (tl.fr >= 0) ? p.flux[static_cast<int64_t>(2 * tl.fr + 1) * p.ld + s] : T(0);
     sL[s] = (tl.fl >= 0) ? p.flux[static_cast<int64_t>(2 * tl.fl + 0) * p.ld + s] : T(0);
   }
   for (int s = tid; s <= S; s += NT) {
-    sA[s] = p.fa[p.n0 + s];
-    sB[s] = p.fb[p.n0 + s];
+    sA[s] = (s == 0) ? p.state_in[p.M] : p.fa[p.n0 + s];
+    sB[s] = (s == 0) ? p.state_in[2 * p.M - 1] : p.fb[p.n0 + s];
   }
 
+  const bool inside = tl.a >= 0 && tl.a + TM <= p.M;
   T u[MPT], uo[MPT];
-  stage_in<T, NT, MPT>(p.state_in + p.M, tl.a, p.M, st, u);  // level n0
-  stage_in<T, NT, MPT>(p.state_in, tl.a, p.M, st, uo);       // level n0-1
+  {
+    T t1[MPT], t0[MPT];
+    load_level<T, NT, MPT>(p.state_in + p.M, tl.a, p.M, inside, t1);  // level n0
+    load_level<T, NT, MPT>(p.state_in, tl.a, p.M, inside, t0);        // level n0-1
+    transpose_in<T, NT, MPT>(t1, st, u);
+    transpose_in<T, NT, MPT>(t0, st, uo);
+  }
 
   UpdateCtx<T, NT, MPT> c;
   c.edge = edge;
@@ -261,30 +345,55 @@ __global__ __launch_bounds__(NT) void k_update(const UpdateArgs<T> p) {
   c.sA = sA;
   c.sB = sB;
   c.base = tl.a + static_cast<int64_t>(tid) * MPT;
-  c.M = p.M;
-  c.lin = tl.lin;
   c.lane = tid & 63;
   c.wv = tid >> 6;
-  c.right_ghost = tl.fr >= 0;
-  const int64_t end = c.base + MPT;
-  const bool mine = (c.base <= 0 && 0 < end) || (c.base <= p.M - 1 && p.M - 1 < end) ||
-                    (c.base <= tl.lin && tl.lin < end);
-  c.gen = __any(mine) != 0;
-  c.rb = p.rec_ptr ? p.rec_ptr[tix] : 0;
-  c.re = p.rec_ptr ? p.rec_ptr[tix + 1] : 0;
+  c.lmode = tl.lmode;
+  c.rmode = tl.rmode;
+  c.dl = -1000;
+  c.d0 = -1000;
+  c.gen = false;
+  c.rb = 0;
+  c.re = 0;
+  if (GEN) {
+    // offsets of the special nodes from this lane's first node, clamped so
+    // that far-away nodes match no element
+    auto rel = [](int64_t node, int64_t base) -> int {
+      const int64_t d = node - base;
+      return (d < -2 || d > MPT + 1) ? -1000 : static_cast<int>(d);
+    };
+    c.dl = (tl.lin == kNoNode) ? -1000 : rel(tl.lin, c.base);
+    c.d0 = rel(0, c.base);
+    const bool mine = (c.dl >= 0 && c.dl < MPT) || (c.d0 >= 0 && c.d0 < MPT);
+    c.gen = __any(mine) != 0;
+    c.rb = p.rec_ptr ? p.rec_ptr[slot] : 0;
+    c.re = p.rec_ptr ? p.rec_ptr[slot + 1] : 0;
+  }
+  const int64_t rlo = tl.out_lo > tl.a ? tl.out_lo : tl.a;
+  const int64_t rhi = tl.out_hi < tl.a + TM - 1 ? tl.out_hi : tl.a + TM - 1;
+  const int xlo = static_cast<int>(rlo - tl.a);
+  const int xhi = static_cast<int>(rhi - tl.a);
 
   int s = 0;
   for (; s + 1 < S; s += 2) {
-    one_step<T, NT, MPT>(p, c, u, uo, s);      // uo <- level n0+s+1
-    one_step<T, NT, MPT>(p, c, uo, u, s + 1);  // u  <- level n0+s+2
+    one_step<T, NT, MPT, GEN>(p, c, u, uo, s);      // uo <- level n0+s+1
+    one_step<T, NT, MPT, GEN>(p, c, uo, u, s + 1);  // u  <- level n0+s+2
   }
   if (s < S) {
-    one_step<T, NT, MPT>(p, c, u, uo, s);  // uo = level n0+S, u = n0+S-1
-    stage_out<T, NT, MPT>(p.state_out, tl.a, tl.out_lo, tl.out_hi, st, u);
-    stage_out<T, NT, MPT>(p.state_out + p.M, tl.a, tl.out_lo, tl.out_hi, st, uo);
+    one_step<T, NT, MPT, GEN>(p, c, u, uo, s);  // uo = level n0+S, u = n0+S-1
+    stage_out<T, NT, MPT>(p.state_out, tl.a, xlo, xhi, st, u);
+    stage_out<T, NT, MPT>(p.state_out + p.M, tl.a, xlo, xhi, st, uo);
   } else {
-    stage_out<T, NT, MPT>(p.state_out, tl.a, tl.out_lo, tl.out_hi, st, uo);
-    stage_out<T, NT, MPT>(p.state_out + p.M, tl.a, tl.out_lo, tl.out_hi, st, u);
+    stage_out<T, NT, MPT>(p.state_out, tl.a, xlo, xhi, st, uo);
+    stage_out<T, NT, MPT>(p.state_out + p.M, tl.a, xlo, xhi, st, u);
+  }
+  // Dirichlet nodes next to the region
+  if (tid == 0 && tl.lmode == kEndDirichlet) {
+    p.state_out[0] = sA[S - 1];
+    p.state_out[p.M] = sA[S];
+  }
+  if (tid == NT - 1 && tl.rmode == kEndDirichlet) {
+    p.state_out[p.M - 1] = sB[S - 1];
+    p.state_out[2 * p.M - 1] = sB[S];
   }
 }
 
@@ -370,13 +479,17 @@ bool shape_built(int threads, int per_thread) {
 
 template <typename T>
 hipError_t launch_update(const UpdateArgs<T>& a, int threads, int per_thread,
-                         hipStream_t s) {
+                         bool general, hipStream_t s) {
   if (a.n_tiles <= 0) return hipSuccess;
-#define RSWR_LAUNCH(NT_, MPT_)                                                   \
-  if (threads == NT_ && per_thread == MPT_) {                                  \
-    hipLaunchKernelGGL((k_update<T, NT_, MPT_>), dim3(a.n_tiles), dim3(NT_), 0, \
-                       s, a);                                                  \
-    return hipGetLastError();                                                  \
+#define RSWR_LAUNCH(NT_, MPT_)                                                    \
+  if (threads == NT_ && per_thread == MPT_) {                                   \
+    if (general)                                                                \
+      hipLaunchKernelGGL((k_update<T, NT_, MPT_, true>), dim3(a.n_tiles),       \
+                         dim3(NT_), 0, s, a);                                   \
+    else                                                                        \
+      hipLaunchKernelGGL((k_update<T, NT_, MPT_, false>), dim3(a.n_tiles),      \
+                         dim3(NT_), 0, s, a);                                   \
+    return hipGetLastError();                                                   \
   }
   RSWR_SHAPES(RSWR_LAUNCH)
 #undef RSWR_LAUNCH
@@ -401,8 +514,10 @@ hipError_t launch_copy(T* dst, const T* src, int64_t n, hipStream_t s) {
 
 template hipError_t launch_predict<float>(const PredictArgs<float>&, int, hipStream_t);
 template hipError_t launch_predict<double>(const PredictArgs<double>&, int, hipStream_t);
-template hipError_t launch_update<float>(const UpdateArgs<float>&, int, int, hipStream_t);
-template hipError_t launch_update<double>(const UpdateArgs<double>&, int, int, hipStream_t);
+template hipError_t launch_update<float>(const UpdateArgs<float>&, int, int, bool,
+                                         hipStream_t);
+template hipError_t launch_update<double>(const UpdateArgs<double>&, int, int, bool,
+                                          hipStream_t);
 template hipError_t launch_select<float>(const SelectArgs<float>&, hipStream_t);
 template hipError_t launch_select<double>(const SelectArgs<double>&, hipStream_t);
 template hipError_t launch_copy<float>(float*, const float*, int64_t, hipStream_t);

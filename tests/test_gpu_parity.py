@@ -278,12 +278,12 @@ def test_plain_2p20_fp64_sampled():
     tr = rs.rswr_solve(plan, st, dev(fa, torch.float64), dev(fb, torch.float64),
                        prob.n_steps, receivers=rec)
     got = host(st)
-    nodes = np.array([0, 1, 2, 500, 3000, 6000, 8000, 8500, 9000, 9500, 20000, 400000,
-                      prob.M - 2, prob.M - 1])
+    nodes = np.concatenate([np.arange(0, 9600, 97), [20000, 400000, prob.M - 2,
+                                                      prob.M - 1]])
     ref = oracle.point_values(prob.M, prob.lam, prob.dx, fa, fb, prob.n_steps,
                               prob.state0(), nodes)
     scale = np.abs(ref).max()
-    assert scale > 0.1
+    assert scale > 0.1 and np.count_nonzero(ref) > 100
     assert np.abs(got[:, nodes] - ref).max() <= 1e-12 * scale
     # traces: from rest and driven at node 0 only, U^n_j = 0 for j >= n, so
     # cutting the domain at node n_steps + 1 changes no value before it

@@ -35,18 +35,28 @@ def check_plan(plan):
     assert st[0, 2] == 0 and st[-1, 3] == M - 1
     assert np.all(st[1:, 2] == st[:-1, 3] + 1)     # contiguous, disjoint
     assert np.all(st[:, 3] >= st[:, 2])
-    for a, b, s_lo, s_hi, w, fr in t:
+    for a, b, s_lo, s_hi, w, lm, rm, gen in t:
         assert olo[w] <= s_lo and s_hi <= ohi[w]
-        # left end: exact only when the window's left end lies in the region
-        if a > lo[w]:
-            assert s_lo >= a + S
-        right_exact = (w == plan.N - 1 and b >= M - 1) or fr == 1
-        if fr == 1:
-            assert b == hi[w]
-        if not right_exact:
-            edge = min(b, hi[w] if w < plan.N - 1 else M - 1)
-            assert s_hi <= edge - S
-        assert b < M + TM and a > -TM
+        lb0 = 1 if w == 0 else lo[w]
+        rb0 = M - 2 if w == plan.N - 1 else hi[w]
+        # left end: exact at the window's left end, inside it (general), or
+        # far enough from every stored node
+        if lm == 1:
+            assert w > 0 and a == lo[w]
+        elif lm == 2:
+            assert w == 0 and a == 1
+        elif gen:
+            assert a < lb0
+        else:
+            assert a > lb0 and s_lo >= a + S
+        if rm == 1:
+            assert w < plan.N - 1 and b == hi[w]
+        elif rm == 2:
+            assert w == plan.N - 1 and b == M - 2
+        else:
+            assert b < rb0 and s_hi <= b - S
+        assert s_lo >= a or (lm == 2 and s_lo == 0)
+        assert s_hi <= b or (rm == 2 and s_hi == M - 1)
 
 
 @pytest.mark.parametrize("kw", LAYOUTS)
