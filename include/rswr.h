@@ -164,19 +164,51 @@ rswr_status_t rswr_update(rswr_plan_t plan, const void* state_in,
 rswr_status_t rswr_solve_workspace_size(rswr_plan_t plan, int32_t n_rec,
                                         size_t* bytes);
 
+/* Bytes of a checkpoint buffer for an n_steps solve: the states at the
+ * n_spans+1 span boundaries ([n_spans+1][2][M]) followed by the predicted
+ * flux waveforms of every span ([n_spans][N-1][2][flux_ld]), n_spans =
+ * ceil(n_steps / S).  This is what rswr_solve_adjoint reads. */
+rswr_status_t rswr_checkpoint_size(rswr_plan_t plan, int64_t n_steps,
+                                   size_t* bytes);
+
 /* The redo loop of Sec. 2.6 (FIXED mode): n_steps levels from level n0,
  * predict -> select -> update per span, the last span shortened.  `state` is
  * read and overwritten with levels n0+n_steps-1 and n0+n_steps.
  * Receivers: `rec_idx` (host) holds n_rec node indices; `traces`
  * [n_rec][n_steps] receives U^{n0+s+1}[rec] at column s.  `checkpoints`
- * (optional, [n_spans+1][2][M]) receives the state at every span boundary,
- * n_spans = ceil(n_steps / S).  The whole loop is recorded once into a HIP
- * graph per argument set and replayed. */
+ * (optional, rswr_checkpoint_size bytes) receives the state at every span
+ * boundary and every span's predicted fluxes.  The whole loop is recorded
+ * once into a HIP graph per argument set and replayed. */
 rswr_status_t rswr_solve(rswr_plan_t plan, void* state, const void* f_a,
                          const void* f_b, int64_t n0, int64_t n_steps,
                          const int64_t* rec_idx, int32_t n_rec, void* traces,
                          void* workspace, size_t ws_bytes, void* checkpoints,
                          void* stream);
+
+/* Bytes of device workspace rswr_solve_adjoint needs for n_rec receivers. */
+rswr_status_t rswr_adjoint_workspace_size(rswr_plan_t plan, int32_t n_rec,
+                                          size_t* bytes);
+
+/* Gradient of the receiver misfit J = sum_r sum_n (U^n[rec_r] - d_r^n)^2 of
+ * an n_steps solve from level 0 (FIXED plan), given dJ/dtrace in
+ * `grad_traces` [n_rec][n_steps] (2 (trace - d) for this J; any upstream
+ * gradient works).  Reverse mode of the discrete solve: the adjoint field
+ * obeys the same leapfrog backward in time with the trace gradients as point
+ * sources, and is advanced span by span, last span first, with the method's
+ * own predict / update exchange (Sec. 2.3-2.5) on the plan's windows; the
+ * forward field is rebuilt inside each span from the span-end checkpoint by
+ * running the leapfrog backward.  `checkpoints` is the buffer filled by
+ * rswr_solve over the same n_steps.  Writes dJ/df_A[n], dJ/df_B[n]
+ * (n = 0..n_steps, entry 0 is 0) to grad_f_a / grad_f_b and dJ/dlam
+ * (lam = a dt/dx at fixed dt) to the device double *grad_lambda; dJ/da is
+ * dJ/dlam * lam / a. */
+rswr_status_t rswr_solve_adjoint(rswr_plan_t plan, const void* checkpoints,
+                                 const void* f_a, const void* f_b,
+                                 int64_t n_steps, const int64_t* rec_idx,
+                                 int32_t n_rec, const void* grad_traces,
+                                 void* grad_f_a, void* grad_f_b,
+                                 double* grad_lambda, void* workspace,
+                                 size_t ws_bytes, void* stream);
 
 const char* rswr_status_string(rswr_status_t status);
 const char* rswr_last_error(void);

@@ -72,11 +72,16 @@ def lib():
     L.rswr_select.argtypes = [vp, vp, i32, vp, vp]
     L.rswr_update.argtypes = [vp, vp, vp, vp, i64, vp, vp, i32, vp, vp]
     L.rswr_solve_workspace_size.argtypes = [vp, i32, ctypes.POINTER(sz)]
+    L.rswr_checkpoint_size.argtypes = [vp, i64, ctypes.POINTER(sz)]
+    L.rswr_adjoint_workspace_size.argtypes = [vp, i32, ctypes.POINTER(sz)]
+    L.rswr_solve_adjoint.argtypes = [vp, vp, vp, vp, i64, vp, i32, vp, vp, vp, vp, vp, sz,
+                                     vp]
     L.rswr_solve.argtypes = [vp, vp, vp, vp, i64, i64, vp, i32, vp, vp, sz, vp, vp]
     for name in ("rswr_plan", "rswr_plan_destroy", "rswr_plan_info", "rswr_plan_layout",
                  "rswr_plan_tiles",
                  "rswr_predict", "rswr_select", "rswr_update",
-                 "rswr_solve_workspace_size", "rswr_solve"):
+                 "rswr_solve_workspace_size", "rswr_solve", "rswr_checkpoint_size",
+                 "rswr_adjoint_workspace_size", "rswr_solve_adjoint"):
         getattr(L, name).restype = ctypes.c_int
     L.rswr_status_string.argtypes = [ctypes.c_int]
     L.rswr_status_string.restype = ctypes.c_char_p
@@ -167,6 +172,23 @@ class Plan:
                "rswr_solve_workspace_size")
         return int(b.value)
 
+    def n_spans(self, n_steps):
+        return -(-int(n_steps) // self.span)
+
+    def checkpoint_buffer(self, n_steps, device="cuda"):
+        """Flat buffer for rswr_solve's checkpoints: span-boundary states, then
+        every span's predicted fluxes (rswr_checkpoint_size)."""
+        b = ctypes.c_size_t()
+        _check(lib().rswr_checkpoint_size(self._h, int(n_steps), ctypes.byref(b)),
+               "rswr_checkpoint_size")
+        elem = 8 if self.dtype == torch.float64 else 4
+        return torch.zeros(b.value // elem, dtype=self.dtype, device=device)
+
+    def checkpoint_states(self, buf, n_steps):
+        """View [n_spans+1, 2, M] of the span-boundary states in `buf`."""
+        K = self.n_spans(n_steps)
+        return buf[:(K + 1) * 2 * self.M].view(K + 1, 2, self.M)
+
     def __del__(self):
         h = getattr(self, "_h", None)
         if h is not None and _lib is not None:
@@ -243,8 +265,11 @@ def rswr_solve(plan, state, f_a, f_b, n_steps, n0=0, receivers=None, checkpoints
                                 device=state.device)
     ck = None
     if checkpoints is not None:
-        n_spans = -(-n_steps // plan.span)
-        ck = _dev(checkpoints, plan.dtype, (n_spans + 1) * 2 * plan.M, "checkpoints")
+        b = ctypes.c_size_t()
+        _check(lib().rswr_checkpoint_size(plan.handle, int(n_steps), ctypes.byref(b)),
+               "rswr_checkpoint_size")
+        elem = 8 if plan.dtype == torch.float64 else 4
+        ck = _dev(checkpoints, plan.dtype, b.value // elem, "checkpoints")
     _check(lib().rswr_solve(plan.handle, _dev(state, plan.dtype, 2 * plan.M, "state"),
                             _dev(f_a, plan.dtype, n0 + n_steps + 1, "f_a"),
                             _dev(f_b, plan.dtype, n0 + n_steps + 1, "f_b"), int(n0),
@@ -256,5 +281,87 @@ def rswr_solve(plan, state, f_a, f_b, n_steps, n0=0, receivers=None, checkpoints
     return traces
 
 
+def rswr_solve_adjoint(plan, checkpoints, f_a, f_b, n_steps, receivers, grad_traces,
+                       workspace=None):
+    """Reverse mode of an n_steps solve from level 0 (see include/rswr.h).
+
+    Returns (dJ/df_a [n_steps+1], dJ/df_b [n_steps+1], dJ/dlam as a 0-d
+    float64 tensor)."""
+    rec = np.ascontiguousarray(np.asarray(receivers, np.int64).reshape(-1))
+    n_rec = len(rec)
+    dev_ = f_a.device
+    if workspace is None:
+        b = ctypes.c_size_t()
+        _check(lib().rswr_adjoint_workspace_size(plan.handle, n_rec, ctypes.byref(b)),
+               "rswr_adjoint_workspace_size")
+        workspace = torch.empty(b.value, dtype=torch.uint8, device=dev_)
+    ga = torch.empty(n_steps + 1, dtype=plan.dtype, device=dev_)
+    gb = torch.empty(n_steps + 1, dtype=plan.dtype, device=dev_)
+    gl = torch.empty((), dtype=torch.float64, device=dev_)
+    b = ctypes.c_size_t()
+    _check(lib().rswr_checkpoint_size(plan.handle, int(n_steps), ctypes.byref(b)),
+           "rswr_checkpoint_size")
+    elem = 8 if plan.dtype == torch.float64 else 4
+    gtr = grad_traces.contiguous()
+    _check(lib().rswr_solve_adjoint(
+        plan.handle, _dev(checkpoints, plan.dtype, b.value // elem, "checkpoints"),
+        _dev(f_a, plan.dtype, n_steps + 1, "f_a"), _dev(f_b, plan.dtype, n_steps + 1, "f_b"),
+        int(n_steps), rec.ctypes.data if n_rec else None, n_rec,
+        _dev(gtr, plan.dtype, n_rec * n_steps, "grad_traces") if n_rec else None,
+        _dev(ga, plan.dtype, n_steps + 1, "grad_f_a"),
+        _dev(gb, plan.dtype, n_steps + 1, "grad_f_b"),
+        ctypes.c_void_p(gl.data_ptr()), _dev(workspace, torch.uint8, 1, "workspace"),
+        workspace.numel(), _stream()), "rswr_solve_adjoint")
+    return ga, gb, gl
+
+
+class ProblemSpec:
+    """Everything but f_A and a that fixes an RSWR forward run for autograd."""
+
+    def __init__(self, n_points, n_sub, overlap, n_steps, receivers, f_b=None,
+                 courant=0.9, a_ref=1.0, dtype=torch.float64, x_a=0.0, x_b=1.0):
+        self.n_points, self.n_sub, self.overlap = n_points, n_sub, overlap
+        self.n_steps, self.courant, self.a_ref = n_steps, courant, a_ref
+        self.receivers = np.asarray(receivers, np.int64)
+        self.f_b, self.dtype, self.x_a, self.x_b = f_b, dtype, x_a, x_b
+
+    def plan(self, a):
+        return Plan(self.n_points, self.n_sub, self.overlap, a=float(a),
+                    courant=self.courant, a_ref=self.a_ref, courant_frac=None,
+                    dtype=self.dtype, x_a=self.x_a, x_b=self.x_b)
+
+
+class RSWRFunction(torch.autograd.Function):
+    """traces = RSWRFunction.apply(f_a, a, spec): receiver traces of an RSWR
+    solve from rest with boundary samples f_a [n_steps+1] and wave speed a (a
+    0-d tensor; dt stays fixed by spec.a_ref).  backward runs
+    rswr_solve_adjoint on the span checkpoints of the forward run and returns
+    dJ/df_a and dJ/da."""
+
+    @staticmethod
+    def forward(ctx, f_a, a, spec):
+        plan = spec.plan(a.item())
+        n = spec.n_steps
+        f_b = spec.f_b if spec.f_b is not None else torch.zeros_like(f_a)
+        st = torch.zeros((2, spec.n_points), dtype=spec.dtype, device=f_a.device)
+        ck = plan.checkpoint_buffer(n, f_a.device)
+        tr = rswr_solve(plan, st, f_a.contiguous(), f_b, n, receivers=spec.receivers,
+                        checkpoints=ck)
+        ctx.plan, ctx.spec = plan, spec
+        ctx.save_for_backward(f_a, f_b, ck, a)
+        return tr
+
+    @staticmethod
+    def backward(ctx, grad_traces):
+        f_a, f_b, ck, a = ctx.saved_tensors
+        plan, spec = ctx.plan, ctx.spec
+        ga, _, gl = rswr_solve_adjoint(plan, ck, f_a.contiguous(), f_b, spec.n_steps,
+                                       spec.receivers, grad_traces.to(spec.dtype))
+        # lam = courant * a / a_ref at fixed dt
+        grad_a = (gl * (spec.courant / spec.a_ref)).to(a.dtype)
+        return ga, grad_a, None
+
+
 # Short names of the same calls.
 predict, select, update, solve = rswr_predict, rswr_select, rswr_update, rswr_solve
+solve_adjoint = rswr_solve_adjoint

@@ -16,7 +16,7 @@ FLAGS = [
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-command-line-argument",
 ]
-SOURCES = ["rswr_kernels.hip", "rswr_host.cpp"]
+SOURCES = ["rswr_kernels.hip", "rswr_adjoint.hip", "rswr_host.cpp"]
 
 
 def build(verbose: bool = False) -> str:

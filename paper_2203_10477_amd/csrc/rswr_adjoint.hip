@@ -1,0 +1,456 @@
+// rswr_adjoint.hip -- gfx950 kernels of the adjoint of the RSWR solve.
+//
+// Misfit J = sum_r sum_n (U^n[j_r] - d_r^n)^2; its reverse mode (the
+// transposed leapfrog) is W^n_j = g^n_j + k W^{n+1}_j - W^{n+2}_j +
+// c2 (W^{n+1}_{j-1} + W^{n+1}_{j+1}) on interior nodes, W = 0 on the two
+// Dirichlet nodes, g = dJ/dtrace on receiver nodes.  It is the same
+// self-adjoint wave equation run backward in time with point sources, so
+// each span of it is advanced with the method's own predict / update
+// exchange (Sec. 2.3-2.5 of Wei & Zhao, arXiv 2203.10477) on the forward
+// plan's windows.  dJ/df_A[n] = c2 W^{n+1}_1 (+ g^n_0), and
+// dJ/dlam = 2 lam sum_n sum_j W^n_j (U^{n-1}_{j-1} - 2 U^{n-1}_j + U^{n-1}_{j+1});
+// the forward field is rebuilt span by span by running the leapfrog
+// backward from the span-end checkpoint (it is time-reversible), with the
+// stored forward flux waveforms as ghost data.
+#include "rswr_device.h"
+
+namespace rswr {
+
+// ---------------------------------------------------------------------------
+// Adjoint predict: the light-cone trapezoid of W around each output node,
+// zero input flux at the window's own inputs, receiver sources injected in
+// receiver order after each level (the order the single-domain reverse sweep
+// uses).
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(64) void k_adj_predict(const AdjPredictArgs<T> p) {
+  extern __shared__ unsigned char smem_raw[];
+  T* const sm = reinterpret_cast<T*>(smem_raw);
+  const int i = blockIdx.x >> 1, side = blockIdx.x & 1;
+  const int w = i + side;
+  const int64_t o = (side == 0) ? p.lo[i + 1] : p.hi[i];
+  const int64_t wlo = p.lo[w], whi = p.hi[w];
+  const int shat = p.shat;
+  const int64_t A = (o - shat > wlo) ? o - shat : wlo;
+  const int64_t B = (o + shat < whi) ? o + shat : whi;
+  const int n = static_cast<int>(B - A + 1);
+  const int cap = 2 * shat + 1;
+  T* w0 = sm;        // W^{L+2}, overwritten with W^L
+  T* w1 = sm + cap;  // W^{L+1}
+  const int tid = threadIdx.x;
+  for (int x = tid; x < n; x += 64) {
+    w0[x] = p.w[A + x];
+    w1[x] = p.w[p.M + A + x];
+  }
+  __syncthreads();
+  const bool lex = (A == wlo), rex = (B == whi);
+  const T zero = T(0);
+  T* const row = p.flux + static_cast<int64_t>(2 * i + side) * p.ld;
+  const int oi = static_cast<int>(o - A);
+  for (int s = 0; s < shat; ++s) {
+    if (tid == 0) row[s] = (w1[oi + 1] - w1[oi - 1]) * p.r;
+    if (s == shat - 1) break;
+    for (int x = tid; x < n; x += 64) {
+      const int64_t j = A + x;
+      T v;
+      if (j == 0 || j == p.M - 1) {
+        v = zero;
+      } else {
+        const T ul = (x == 0) ? (lex ? fma_(-p.q, zero, w1[1]) : zero) : w1[x - 1];
+        const T ur = (x == n - 1) ? (rex ? fma_(p.q, zero, w1[n - 2]) : zero) : w1[x + 1];
+        v = leap(p.c2, p.k, ul, w1[x], ur, w0[x]);
+      }
+      w0[x] = v;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      const int64_t L = p.n_e - s;  // level just computed
+      for (int r = 0; r < p.n_rec; ++r) {
+        const int64_t j = p.rec_node[r];
+        if (j > 0 && j < p.M - 1 && j >= A && j <= B)
+          w0[j - A] = w0[j - A] + p.gtr[static_cast<int64_t>(r) * p.gtr_ld + (L - 1)];
+      }
+    }
+    __syncthreads();
+    T* t = w0;
+    w0 = w1;
+    w1 = t;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Adjoint update.  Per lane MPT consecutive nodes of four register arrays:
+// W^{L+1}, W^{L+2} (adjoint) and U^{L-1}, U^L (forward, rebuilt backward).
+// One step: exchange lane-end values (DPP inside a wave, LDS across waves),
+// W^L by the leapfrog (+ sources, general tiles), the dJ/dlam terms of the
+// stored interior nodes, then U^{L-2} by the reversed leapfrog.
+// ---------------------------------------------------------------------------
+template <typename T, int NT, int MPT>
+struct AdjCtx {
+  T (*edge)[4][NT / 64];
+  const T* sRw;
+  const T* sLw;
+  const T* sRu;
+  const T* sLu;
+  const T* sAu;
+  const T* sBu;
+  int64_t base;
+  int dl, d0, dM, d1, dM2;
+  int sb, se, lane, wv, lmode, rmode;
+  uint32_t cnt;  // bit e: element e is stored and interior (enters dJ/dlam)
+  bool gen, wr_fa, wr_fb;
+};
+
+// W (or a reversed U) one level: old <- leap(cur) with the general tile's
+// treatments (ghost at element dl, Dirichlet value at d0 / dM).
+template <typename T, int MPT, bool GEN>
+__device__ __forceinline__ void adj_chunk(const T (&cur)[MPT], T (&old)[MPT], T L,
+                                          T R, T c2, T k, int dl, int d0, int dM,
+                                          T ghost, T pin0, T pinM) {
+#pragma unroll
+  for (int e = 0; e < MPT; ++e) {
+    T ul = (e == 0) ? L : cur[e - 1];
+    const T ur = (e == MPT - 1) ? R : cur[e + 1];
+    if (GEN) ul = (e == dl) ? ghost : ul;
+    T v = leap(c2, k, ul, cur[e], ur, old[e]);
+    if (GEN) {
+      v = (e == d0) ? pin0 : v;
+      v = (e == dM) ? pinM : v;
+    }
+    old[e] = v;
+  }
+}
+
+// dJ/dlam terms W^L_j (U_{j-1} + U_{j+1} - 2 U_j) of the counted elements,
+// accumulated in double; then (if rev) U^{L-2} into uold.
+template <typename T, int MPT, bool GEN>
+__device__ __forceinline__ void lap_and_reverse(const T (&wn)[MPT], const T (&ucur)[MPT],
+                                                T (&uold)[MPT], T L, T R, T c2, T k,
+                                                int dl, int d0, int dM, T ghost, T pin0,
+                                                T pinM, uint32_t cnt, bool rev,
+                                                double& acc) {
+#pragma unroll
+  for (int e = 0; e < MPT; ++e) {
+    T ul = (e == 0) ? L : ucur[e - 1];
+    const T ur = (e == MPT - 1) ? R : ucur[e + 1];
+    if (GEN) ul = (e == dl) ? ghost : ul;
+    const T s = ul + ur;
+    const T lap = s - T(2) * ucur[e];
+    const T lapm = ((cnt >> e) & 1u) ? lap : T(0);
+    acc = __builtin_fma(static_cast<double>(wn[e]), static_cast<double>(lapm), acc);
+    if (rev) {
+      T v = fma_(c2, s, fma_(k, ucur[e], -uold[e]));
+      if (GEN) {
+        v = (e == d0) ? pin0 : v;
+        v = (e == dM) ? pinM : v;
+      }
+      uold[e] = v;
+    }
+  }
+}
+
+template <typename T, int NT, int MPT, bool GEN>
+__device__ __forceinline__ void adj_step(const AdjUpdateArgs<T>& p,
+                                         const AdjCtx<T, NT, MPT>& c,
+                                         const T (&wc)[MPT], T (&wp)[MPT],
+                                         const T (&uc)[MPT], T (&up)[MPT], int tau,
+                                         int S, double& acc) {
+  constexpr int NW = NT / 64;
+  const int par = tau & 1;
+  const int64_t L = p.n_e - tau;  // adjoint level computed now
+  const int mi = S - 1 - tau;     // sample of the forward level m = L-1
+  T Lw = lane_shift<kWaveShr1>(wc[MPT - 1]);
+  T Rw = lane_shift<kWaveShl1>(wc[0]);
+  T Lu = lane_shift<kWaveShr1>(uc[MPT - 1]);
+  T Ru = lane_shift<kWaveShl1>(uc[0]);
+  if (c.lane == 63) {
+    c.edge[par][1][c.wv] = wc[MPT - 1];
+    c.edge[par][3][c.wv] = uc[MPT - 1];
+  }
+  if (c.lane == 0) {
+    c.edge[par][0][c.wv] = wc[0];
+    c.edge[par][2][c.wv] = uc[0];
+  }
+  __syncthreads();
+  if (c.lane == 0) {
+    if (c.wv > 0) {
+      Lw = c.edge[par][1][c.wv - 1];
+      Lu = c.edge[par][3][c.wv - 1];
+    } else {
+      Lw = end_value(c.lmode, fma_(-p.q, c.sLw[tau], wc[1]), T(0));
+      Lu = end_value(c.lmode, fma_(-p.q, c.sLu[mi], uc[1]), c.sAu[mi]);
+    }
+  }
+  if (c.lane == 63) {
+    if (c.wv < NW - 1) {
+      Rw = c.edge[par][0][c.wv + 1];
+      Ru = c.edge[par][2][c.wv + 1];
+    } else {
+      Rw = end_value(c.rmode, fma_(p.q, c.sRw[tau], wc[MPT - 2]), T(0));
+      Ru = end_value(c.rmode, fma_(p.q, c.sRu[mi], uc[MPT - 2]), c.sBu[mi]);
+    }
+  }
+  if (GEN) {
+    // dJ/df at level L from W^{L+1} next to the Dirichlet nodes
+    if (c.wr_fa && c.d1 >= 0 && c.d1 < MPT) p.grad_fa[L] = p.c2 * pick<T, MPT>(wc, c.d1);
+    if (c.wr_fb && c.dM2 >= 0 && c.dM2 < MPT) p.grad_fb[L] = p.c2 * pick<T, MPT>(wc, c.dM2);
+  }
+  const bool rev = tau < S - 1;
+  if (GEN && c.gen) {
+    const int rn = c.dl + 1;
+    const T rw = (rn == MPT) ? Rw : pick<T, MPT>(wc, rn);
+    const T gw = fma_(-p.q, c.sLw[tau], rw);
+    adj_chunk<T, MPT, true>(wc, wp, Lw, Rw, p.c2, p.k, c.dl, c.d0, c.dM, gw, T(0), T(0));
+  } else {
+    adj_chunk<T, MPT, false>(wc, wp, Lw, Rw, p.c2, p.k, 0, 0, 0, T(0), T(0), T(0));
+  }
+  if (GEN) {
+    for (int r = c.sb; r < c.se; ++r) {
+      const int64_t d = p.src_node[r] - c.base;
+      if (d >= 0 && d < MPT) {
+        const T g = p.gtr[static_cast<int64_t>(p.src_id[r]) * p.gtr_ld + (L - 1)];
+#pragma unroll
+        for (int e = 0; e < MPT; ++e) wp[e] = (d == e) ? wp[e] + g : wp[e];
+      }
+    }
+  }
+  if (GEN && c.gen) {
+    const int rn = c.dl + 1;
+    const T ru = (rn == MPT) ? Ru : pick<T, MPT>(uc, rn);
+    const T gu = fma_(-p.q, c.sLu[mi], ru);
+    const T p0 = rev ? c.sAu[mi - 1] : T(0);
+    const T pM = rev ? c.sBu[mi - 1] : T(0);
+    lap_and_reverse<T, MPT, true>(wp, uc, up, Lu, Ru, p.c2, p.k, c.dl, c.d0, c.dM, gu, p0,
+                                  pM, c.cnt, rev, acc);
+  } else {
+    lap_and_reverse<T, MPT, false>(wp, uc, up, Lu, Ru, p.c2, p.k, 0, 0, 0, T(0), T(0),
+                                   T(0), c.cnt, rev, acc);
+  }
+}
+
+template <typename T, int NT, int MPT, bool GEN>
+__global__ __launch_bounds__(NT) void k_adj_update(const AdjUpdateArgs<T> p) {
+  constexpr int NW = NT / 64;
+  constexpr int TM = NT * MPT;
+  constexpr int TMP = TM + (TM >> 5) + 1;
+  __shared__ T st[TMP];
+  __shared__ T sRw[kMaxSpan], sLw[kMaxSpan], sRu[kMaxSpan], sLu[kMaxSpan];
+  __shared__ T sAu[kMaxSpan], sBu[kMaxSpan];
+  __shared__ T edge[2][4][NW];
+  __shared__ double red[NW];
+
+  const int tid = threadIdx.x;
+  const int slot = xcd_tile(blockIdx.x, gridDim.x);
+  const int tix = p.tile_idx[slot];
+  const Tile tl = p.tiles[tix];
+  int S = p.span < kMaxSpan ? p.span : kMaxSpan;
+  if (S <= 0) return;
+  const int64_t M = p.M;
+
+  for (int s = tid; s < S; s += NT) {
+    const int64_t rr = static_cast<int64_t>(2 * tl.fr + 1) * p.ld + s;
+    const int64_t rl = static_cast<int64_t>(2 * tl.fl + 0) * p.ld + s;
+    sRw[s] = (tl.fr >= 0) ? p.afl[rr] : T(0);
+    sLw[s] = (tl.fl >= 0) ? p.afl[rl] : T(0);
+    sRu[s] = (tl.fr >= 0) ? p.ffl[rr] : T(0);
+    sLu[s] = (tl.fl >= 0) ? p.ffl[rl] : T(0);
+    sAu[s] = (s == 0) ? p.u_beg[M] : p.fa[p.n_k + s];
+    sBu[s] = (s == 0) ? p.u_beg[2 * M - 1] : p.fb[p.n_k + s];
+  }
+
+  const bool inside = tl.a >= 0 && tl.a + TM <= M;
+  T wc[MPT], wp[MPT], uc[MPT], up[MPT];
+  {
+    T t[MPT];
+    load_level<T, NT, MPT>(p.w_in + M, tl.a, M, inside, t);
+    transpose_in<T, NT, MPT>(t, st, wc);  // W^{n_e+1}
+    load_level<T, NT, MPT>(p.w_in, tl.a, M, inside, t);
+    transpose_in<T, NT, MPT>(t, st, wp);  // W^{n_e+2}
+    load_level<T, NT, MPT>(p.u_end, tl.a, M, inside, t);
+    transpose_in<T, NT, MPT>(t, st, uc);  // U^{n_e-1}
+    load_level<T, NT, MPT>(p.u_end + M, tl.a, M, inside, t);
+    transpose_in<T, NT, MPT>(t, st, up);  // U^{n_e}
+  }
+
+  AdjCtx<T, NT, MPT> c;
+  c.edge = edge;
+  c.sRw = sRw;
+  c.sLw = sLw;
+  c.sRu = sRu;
+  c.sLu = sLu;
+  c.sAu = sAu;
+  c.sBu = sBu;
+  c.base = tl.a + static_cast<int64_t>(tid) * MPT;
+  c.lane = tid & 63;
+  c.wv = tid >> 6;
+  c.lmode = tl.lmode;
+  c.rmode = tl.rmode;
+  auto rel = [](int64_t node, int64_t base) -> int {
+    const int64_t d = node - base;
+    return (d < -2 || d > MPT + 1) ? -1000 : static_cast<int>(d);
+  };
+  c.dl = (tl.lin == kNoNode) ? -1000 : rel(tl.lin, c.base);
+  c.d0 = rel(0, c.base);
+  c.dM = rel(M - 1, c.base);
+  c.d1 = rel(1, c.base);
+  c.dM2 = rel(M - 2, c.base);
+  c.wr_fa = tl.out_lo <= 1 && 1 <= tl.out_hi;
+  c.wr_fb = tl.out_lo <= M - 2 && M - 2 <= tl.out_hi;
+  {
+    const bool mine = (c.dl >= 0 && c.dl < MPT) || (c.d0 >= 0 && c.d0 < MPT) ||
+                      (c.dM >= 0 && c.dM < MPT);
+    c.gen = GEN && (__any(mine) != 0);
+  }
+  c.sb = (GEN && p.src_ptr) ? p.src_ptr[slot] : 0;
+  c.se = (GEN && p.src_ptr) ? p.src_ptr[slot + 1] : 0;
+  uint32_t cnt = 0;
+#pragma unroll
+  for (int e = 0; e < MPT; ++e) {
+    const int64_t j = c.base + e;
+    const bool counts = j >= tl.out_lo && j <= tl.out_hi && j > 0 && j < M - 1;
+    cnt |= counts ? (1u << e) : 0u;
+  }
+  c.cnt = cnt;
+
+  double acc = 0.0;
+  int tau = 0;
+  for (; tau + 1 < S; tau += 2) {
+    adj_step<T, NT, MPT, GEN>(p, c, wc, wp, uc, up, tau, S, acc);
+    adj_step<T, NT, MPT, GEN>(p, c, wp, wc, up, uc, tau + 1, S, acc);
+  }
+  const int64_t rlo = tl.out_lo > tl.a ? tl.out_lo : tl.a;
+  const int64_t rhi = tl.out_hi < tl.a + TM - 1 ? tl.out_hi : tl.a + TM - 1;
+  const int xlo = static_cast<int>(rlo - tl.a);
+  const int xhi = static_cast<int>(rhi - tl.a);
+  if (tau < S) {
+    adj_step<T, NT, MPT, GEN>(p, c, wc, wp, uc, up, tau, S, acc);
+    stage_out<T, NT, MPT>(p.w_out, tl.a, xlo, xhi, st, wc);      // W^{n_k+2}
+    stage_out<T, NT, MPT>(p.w_out + M, tl.a, xlo, xhi, st, wp);  // W^{n_k+1}
+  } else {
+    stage_out<T, NT, MPT>(p.w_out, tl.a, xlo, xhi, st, wp);
+    stage_out<T, NT, MPT>(p.w_out + M, tl.a, xlo, xhi, st, wc);
+  }
+  // Dirichlet nodes next to the region: W = 0
+  if (tid == 0 && tl.lmode == kEndDirichlet) {
+    p.w_out[0] = T(0);
+    p.w_out[M] = T(0);
+  }
+  if (tid == NT - 1 && tl.rmode == kEndDirichlet) {
+    p.w_out[M - 1] = T(0);
+    p.w_out[2 * M - 1] = T(0);
+  }
+  // fixed-order reduction of the dJ/dlam partial of this tile
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+  if (c.lane == 0) red[c.wv] = acc;
+  __syncthreads();
+  if (tid == 0) {
+    double t = 0.0;
+    for (int w = 0; w < NW; ++w) t += red[w];
+    p.lam_part[tix] += t;
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_adj_finish(T* grad_fa, T* grad_fb, const T* gtr,
+                                                   int64_t gtr_ld, const int64_t* rec_node,
+                                                   int32_t n_rec, int64_t M, int64_t n_steps,
+                                                   const double* lam_part, int32_t n_part,
+                                                   double lam, double* grad_lam) {
+  __shared__ double red[256];
+  const int tid = threadIdx.x;
+  for (int64_t L = 1 + tid; L <= n_steps; L += 256) {
+    T ga = grad_fa[L], gb = grad_fb[L];
+    for (int r = 0; r < n_rec; ++r) {
+      const T g = gtr[static_cast<int64_t>(r) * gtr_ld + (L - 1)];
+      if (rec_node[r] == 0) ga = ga + g;
+      if (rec_node[r] == M - 1) gb = gb + g;
+    }
+    grad_fa[L] = ga;
+    grad_fb[L] = gb;
+  }
+  double t = 0.0;
+  for (int i = tid; i < n_part; i += 256) t += lam_part[i];
+  red[tid] = t;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (tid < w) red[tid] += red[tid + w];
+    __syncthreads();
+  }
+  if (tid == 0) *grad_lam = 2.0 * lam * red[0];
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_fill(T* __restrict__ dst, T v, int64_t n) {
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+       i += stride)
+    dst[i] = v;
+}
+
+template <typename T>
+hipError_t launch_adj_predict(const AdjPredictArgs<T>& a, int shmem_nodes, hipStream_t s) {
+  if (a.N < 2) return hipSuccess;
+  const size_t shm = static_cast<size_t>(2 * shmem_nodes) * sizeof(T);
+  hipLaunchKernelGGL(k_adj_predict<T>, dim3(2 * (a.N - 1)), dim3(64), shm, s, a);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_adj_update(const AdjUpdateArgs<T>& a, int threads, int per_thread,
+                             bool general, hipStream_t s) {
+  if (a.n_tiles <= 0) return hipSuccess;
+#define RSWR_ADJ_LAUNCH(NT_, MPT_)                                                  \
+  if (threads == NT_ && per_thread == MPT_) {                                     \
+    if (general)                                                                  \
+      hipLaunchKernelGGL((k_adj_update<T, NT_, MPT_, true>), dim3(a.n_tiles),     \
+                         dim3(NT_), 0, s, a);                                     \
+    else                                                                          \
+      hipLaunchKernelGGL((k_adj_update<T, NT_, MPT_, false>), dim3(a.n_tiles),    \
+                         dim3(NT_), 0, s, a);                                     \
+    return hipGetLastError();                                                     \
+  }
+  RSWR_SHAPES(RSWR_ADJ_LAUNCH)
+#undef RSWR_ADJ_LAUNCH
+  return hipErrorInvalidValue;
+}
+
+template <typename T>
+hipError_t launch_adj_finish(T* grad_fa, T* grad_fb, const T* gtr, int64_t gtr_ld,
+                             const int64_t* rec_node, int32_t n_rec, int64_t M,
+                             int64_t n_steps, const double* lam_part, int32_t n_part,
+                             double lam, double* grad_lam, hipStream_t s) {
+  hipLaunchKernelGGL(k_adj_finish<T>, dim3(1), dim3(256), 0, s, grad_fa, grad_fb, gtr,
+                     gtr_ld, rec_node, n_rec, M, n_steps, lam_part, n_part, lam, grad_lam);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_fill(T* dst, T v, int64_t n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  int64_t blocks = (n + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(k_fill<T>, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s, dst,
+                     v, n);
+  return hipGetLastError();
+}
+
+template hipError_t launch_adj_predict<float>(const AdjPredictArgs<float>&, int, hipStream_t);
+template hipError_t launch_adj_predict<double>(const AdjPredictArgs<double>&, int,
+                                               hipStream_t);
+template hipError_t launch_adj_update<float>(const AdjUpdateArgs<float>&, int, int, bool,
+                                             hipStream_t);
+template hipError_t launch_adj_update<double>(const AdjUpdateArgs<double>&, int, int, bool,
+                                              hipStream_t);
+template hipError_t launch_adj_finish<float>(float*, float*, const float*, int64_t,
+                                             const int64_t*, int32_t, int64_t, int64_t,
+                                             const double*, int32_t, double, double*,
+                                             hipStream_t);
+template hipError_t launch_adj_finish<double>(double*, double*, const double*, int64_t,
+                                              const int64_t*, int32_t, int64_t, int64_t,
+                                              const double*, int32_t, double, double*,
+                                              hipStream_t);
+template hipError_t launch_fill<float>(float*, float, int64_t, hipStream_t);
+template hipError_t launch_fill<double>(double*, double, int64_t, hipStream_t);
+
+}  // namespace rswr

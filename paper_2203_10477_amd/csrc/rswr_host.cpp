@@ -51,23 +51,9 @@ struct DevTables {
   hipStream_t capture = nullptr;
 };
 
-struct GraphKey {
-  int device;
-  const void* state;
-  const void* fa;
-  const void* fb;
-  int64_t n0, n_steps;
-  const void* traces;
-  const void* ws;
-  const void* ckpt;
-  int has_rec, n_gen, n_fast;
-  bool operator==(const GraphKey& o) const {
-    return device == o.device && state == o.state && fa == o.fa && fb == o.fb &&
-           n0 == o.n0 && n_steps == o.n_steps && traces == o.traces && ws == o.ws &&
-           ckpt == o.ckpt && has_rec == o.has_rec && n_gen == o.n_gen &&
-           n_fast == o.n_fast;
-  }
-};
+// Everything a recorded graph depends on: the entry point and its pointer
+// and size arguments.
+using GraphKey = std::vector<int64_t>;
 
 struct GraphEntry {
   GraphKey key;
@@ -418,6 +404,10 @@ rswr_status_t enqueue_solve(rswr_plan_s* p, const DevTables& d, void* state,
   T* const flux = reinterpret_cast<T*>(ws + L.flux);
   T* const ck = static_cast<T*>(ckpt);
   const size_t st_elems = 2 * size_t(M);
+  // checkpoint buffer: [K+1][2][M] span-boundary states, then [K][flux]
+  // predicted fluxes of every span
+  const size_t fl_elems = size_t(std::max(p->N - 1, 1)) * 2 * p->flux_ld;
+  T* const ck_flux = ck ? ck + (K + 1) * st_elems : nullptr;
   T* x = user;
   T* y = buf;
   if (ck) {
@@ -432,10 +422,11 @@ rswr_status_t enqueue_solve(rswr_plan_s* p, const DevTables& d, void* state,
     const int32_t S = static_cast<int32_t>(std::min<int64_t>(p->S, n0 + n_steps - lev));
     const T* in = ck ? ck + k * st_elems : x;
     T* out = ck ? ck + (k + 1) * st_elems : y;
-    rswr::PredictArgs<T> pa = predict_args<T>(*p, d, in, fa, fb, lev, S, flux);
+    T* const fl = ck ? ck_flux + k * fl_elems : flux;
+    rswr::PredictArgs<T> pa = predict_args<T>(*p, d, in, fa, fb, lev, S, fl);
     RSWR_HIP(rswr::launch_predict<T>(pa, 2 * p->S_max + 1, s));
     rswr::UpdateArgs<T> ua =
-        update_args<T>(*p, d, in, fa, fb, lev, flux, nullptr, S, out);
+        update_args<T>(*p, d, in, fa, fb, lev, fl, nullptr, S, out);
     if (lists.rec_ptr) {
       ua.rec_ptr = lists.rec_ptr;
       ua.rec_node = lists.rec_node;
@@ -450,6 +441,170 @@ rswr_status_t enqueue_solve(rswr_plan_s* p, const DevTables& d, void* state,
     std::swap(x, y);
   }
   if (ck) RSWR_HIP(rswr::launch_copy<T>(user, ck + K * st_elems, 2 * M, s));
+  return RSWR_OK;
+}
+
+// Records `enqueue` into a HIP graph once per key and replays it on `s`.
+template <typename F>
+rswr_status_t run_graph(rswr_plan_s* p, DevTables* d, const GraphKey& key, F&& enqueue,
+                        hipStream_t s) {
+  if (std::getenv("RSWR_NO_GRAPH") != nullptr) return enqueue(s);
+  hipGraphExec_t exec = nullptr;
+  {
+    std::lock_guard<std::mutex> g(p->mu);
+    for (auto& e : p->graphs)
+      if (e.key == key) exec = e.exec;
+  }
+  if (!exec) {
+    hipGraph_t graph = nullptr;
+    RSWR_HIP(hipStreamBeginCapture(d->capture, hipStreamCaptureModeThreadLocal));
+    rswr_status_t cst = enqueue(d->capture);
+    hipError_t ee = hipStreamEndCapture(d->capture, &graph);
+    if (cst != RSWR_OK) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return cst;
+    }
+    if (ee != hipSuccess) return hip_fail(ee, "hipStreamEndCapture");
+    ee = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (ee != hipSuccess) return hip_fail(ee, "hipGraphInstantiate");
+    std::lock_guard<std::mutex> g(p->mu);
+    if (p->graphs.size() >= 8) {
+      (void)hipGraphExecDestroy(p->graphs.front().exec);
+      p->graphs.erase(p->graphs.begin());
+    }
+    p->graphs.push_back({key, exec});
+  }
+  RSWR_HIP(hipGraphLaunch(exec, s));
+  return RSWR_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Adjoint driver.
+// ---------------------------------------------------------------------------
+struct AdjWs {
+  size_t w0 = 0, w1 = 0, afl = 0, lam = 0, gen_idx = 0, fast_idx = 0, src_ptr = 0,
+         src_node = 0, src_id = 0, rec_node = 0, total = 0;
+};
+
+AdjWs adj_ws_layout(const rswr_plan_s& p, int32_t n_rec) {
+  AdjWs w;
+  const size_t b = elem_size(p);
+  const size_t nt = std::max<size_t>(p.tiles.size(), 1);
+  const size_t nr = size_t(std::max(n_rec, 1));
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = off;
+    off += round_up(bytes, 256);
+    return at;
+  };
+  w.w0 = take(2 * size_t(p.M) * b);
+  w.w1 = take(2 * size_t(p.M) * b);
+  w.afl = take(size_t(std::max(p.N - 1, 1)) * 2 * p.flux_ld * b);
+  w.lam = take(nt * sizeof(double));
+  w.gen_idx = take(nt * sizeof(int32_t));
+  w.fast_idx = take(nt * sizeof(int32_t));
+  w.src_ptr = take((nt + 1) * sizeof(int32_t));
+  w.src_node = take(nt * nr * sizeof(int64_t));
+  w.src_id = take(nt * nr * sizeof(int32_t));
+  w.rec_node = take(nr * sizeof(int64_t));
+  w.total = off;
+  return w;
+}
+
+struct AdjLists {
+  int32_t n_gen = 0, n_fast = 0;
+};
+
+template <typename T>
+rswr_status_t enqueue_adjoint(rswr_plan_s* p, const DevTables& d, const void* ckpt,
+                              const void* fa, const void* fb, int64_t n_steps,
+                              const AdjLists& al, const void* gtr, void* gfa, void* gfb,
+                              double* glam, char* ws, const AdjWs& L, int32_t n_rec,
+                              hipStream_t s) {
+  const int64_t M = p->M;
+  const int64_t K = (n_steps + p->S - 1) / p->S;
+  const size_t st_elems = 2 * size_t(M);
+  const size_t fl_elems = size_t(std::max(p->N - 1, 1)) * 2 * p->flux_ld;
+  const T* ck = static_cast<const T*>(ckpt);
+  const T* ck_flux = ck + (K + 1) * st_elems;
+  T* w_cur = reinterpret_cast<T*>(ws + L.w0);
+  T* w_nxt = reinterpret_cast<T*>(ws + L.w1);
+  T* afl = reinterpret_cast<T*>(ws + L.afl);
+  double* lam = reinterpret_cast<double*>(ws + L.lam);
+  const int32_t n_all = static_cast<int32_t>(p->tiles.size());
+  RSWR_HIP(rswr::launch_fill<T>(w_cur, T(0), 2 * M, s));
+  RSWR_HIP(rswr::launch_fill<double>(lam, 0.0, std::max(n_all, 1), s));
+  RSWR_HIP(rswr::launch_fill<T>(static_cast<T*>(gfa), T(0), n_steps + 1, s));
+  RSWR_HIP(rswr::launch_fill<T>(static_cast<T*>(gfb), T(0), n_steps + 1, s));
+  const double c2 = p->lam * p->lam;
+  for (int64_t k = K - 1; k >= 0; --k) {
+    const int64_t n_k = k * p->S;
+    const int32_t S = static_cast<int32_t>(std::min<int64_t>(p->S, n_steps - n_k));
+    const int64_t n_e = n_k + S;
+    rswr::AdjPredictArgs<T> pa{};
+    pa.w = w_cur;
+    pa.flux = afl;
+    pa.lo = d.lo;
+    pa.hi = d.hi;
+    pa.rec_node = reinterpret_cast<const int64_t*>(ws + L.rec_node);
+    pa.gtr = static_cast<const T*>(gtr);
+    pa.gtr_ld = n_steps;
+    pa.M = M;
+    pa.n_e = n_e;
+    pa.N = p->N;
+    pa.shat = S;
+    pa.ld = p->flux_ld;
+    pa.n_rec = n_rec;
+    pa.c2 = T(c2);
+    pa.k = T(2.0 - 2.0 * c2);
+    pa.r = T(1.0 / (2.0 * p->dx));
+    pa.q = T(2.0 * p->dx);
+    RSWR_HIP(rswr::launch_adj_predict<T>(pa, 2 * p->S_max + 1, s));
+    rswr::AdjUpdateArgs<T> ua{};
+    ua.w_in = w_cur;
+    ua.w_out = w_nxt;
+    ua.u_end = ck + (k + 1) * st_elems;
+    ua.u_beg = ck + k * st_elems;
+    ua.ffl = ck_flux + k * fl_elems;
+    ua.afl = afl;
+    ua.fa = static_cast<const T*>(fa);
+    ua.fb = static_cast<const T*>(fb);
+    ua.tiles = d.tiles;
+    ua.gtr = static_cast<const T*>(gtr);
+    ua.gtr_ld = n_steps;
+    ua.grad_fa = static_cast<T*>(gfa);
+    ua.grad_fb = static_cast<T*>(gfb);
+    ua.lam_part = lam;
+    ua.M = M;
+    ua.n_e = n_e;
+    ua.n_k = n_k;
+    ua.span = S;
+    ua.ld = p->flux_ld;
+    ua.c2 = T(c2);
+    ua.k = T(2.0 - 2.0 * c2);
+    ua.q = T(2.0 * p->dx);
+    if (al.n_gen > 0) {
+      rswr::AdjUpdateArgs<T> g = ua;
+      g.tile_idx = reinterpret_cast<const int32_t*>(ws + L.gen_idx);
+      g.n_tiles = al.n_gen;
+      g.src_ptr = reinterpret_cast<const int32_t*>(ws + L.src_ptr);
+      g.src_node = reinterpret_cast<const int64_t*>(ws + L.src_node);
+      g.src_id = reinterpret_cast<const int32_t*>(ws + L.src_id);
+      RSWR_HIP(rswr::launch_adj_update<T>(g, p->threads, p->per_thread, true, s));
+    }
+    if (al.n_fast > 0) {
+      rswr::AdjUpdateArgs<T> f = ua;
+      f.tile_idx = reinterpret_cast<const int32_t*>(ws + L.fast_idx);
+      f.n_tiles = al.n_fast;
+      RSWR_HIP(rswr::launch_adj_update<T>(f, p->threads, p->per_thread, false, s));
+    }
+    std::swap(w_cur, w_nxt);
+  }
+  RSWR_HIP(rswr::launch_adj_finish<T>(
+      static_cast<T*>(gfa), static_cast<T*>(gfb), static_cast<const T*>(gtr), n_steps,
+      reinterpret_cast<const int64_t*>(ws + L.rec_node), n_rec, M, n_steps, lam, n_all,
+      p->lam, glam, s));
   return RSWR_OK;
 }
 
@@ -733,6 +888,15 @@ rswr_status_t rswr_update(rswr_plan_t p, const void* state_in, const void* f_a,
   return RSWR_OK;
 }
 
+rswr_status_t rswr_checkpoint_size(rswr_plan_t p, int64_t n_steps, size_t* bytes) {
+  if (!p || !bytes || n_steps < 0) return fail(RSWR_ERR_INVALID_ARG, "bad argument");
+  const int64_t K = (n_steps + p->S - 1) / p->S;
+  const size_t st = 2 * size_t(p->M);
+  const size_t fl = size_t(std::max(p->N - 1, 1)) * 2 * p->flux_ld;
+  *bytes = (size_t(K + 1) * st + size_t(K) * fl) * elem_size(*p);
+  return RSWR_OK;
+}
+
 rswr_status_t rswr_solve_workspace_size(rswr_plan_t p, int32_t n_rec, size_t* bytes) {
   if (!p || !bytes || n_rec < 0) return fail(RSWR_ERR_INVALID_ARG, "bad argument");
   *bytes = ws_layout(*p, n_rec).total;
@@ -816,7 +980,6 @@ rswr_status_t rswr_solve(rswr_plan_t p, void* state, const void* f_a, const void
     lists.rec_id = reinterpret_cast<const int32_t*>(ws + L.rec_id);
   }
 
-  const bool eager = std::getenv("RSWR_NO_GRAPH") != nullptr;
   auto enqueue = [&](hipStream_t q) {
     return p->dtype == RSWR_F64
                ? enqueue_solve<double>(p, *d, state, f_a, f_b, n0, n_steps, lists,
@@ -824,38 +987,117 @@ rswr_status_t rswr_solve(rswr_plan_t p, void* state, const void* f_a, const void
                : enqueue_solve<float>(p, *d, state, f_a, f_b, n0, n_steps, lists,
                                       traces, ws, L, checkpoints, q);
   };
-  if (eager) return enqueue(s);
+  const GraphKey key{1,
+                     device,
+                     reinterpret_cast<int64_t>(state),
+                     reinterpret_cast<int64_t>(f_a),
+                     reinterpret_cast<int64_t>(f_b),
+                     n0,
+                     n_steps,
+                     reinterpret_cast<int64_t>(traces),
+                     reinterpret_cast<int64_t>(workspace),
+                     reinterpret_cast<int64_t>(checkpoints),
+                     n_rec > 0,
+                     lists.n_gen,
+                     lists.n_fast};
+  return run_graph(p, d, key, enqueue, s);
+}
 
-  const GraphKey key{device, state, f_a, f_b, n0, n_steps, traces, workspace, checkpoints,
-                     n_rec > 0, lists.n_gen, lists.n_fast};
-  hipGraphExec_t exec = nullptr;
-  {
-    std::lock_guard<std::mutex> g(p->mu);
-    for (auto& e : p->graphs)
-      if (e.key == key) exec = e.exec;
-  }
-  if (!exec) {
-    hipGraph_t graph = nullptr;
-    RSWR_HIP(hipStreamBeginCapture(d->capture, hipStreamCaptureModeThreadLocal));
-    rswr_status_t cst = enqueue(d->capture);
-    hipError_t ee = hipStreamEndCapture(d->capture, &graph);
-    if (cst != RSWR_OK) {
-      if (graph) (void)hipGraphDestroy(graph);
-      return cst;
-    }
-    if (ee != hipSuccess) return hip_fail(ee, "hipStreamEndCapture");
-    ee = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-    (void)hipGraphDestroy(graph);
-    if (ee != hipSuccess) return hip_fail(ee, "hipGraphInstantiate");
-    std::lock_guard<std::mutex> g(p->mu);
-    if (p->graphs.size() >= 8) {
-      (void)hipGraphExecDestroy(p->graphs.front().exec);
-      p->graphs.erase(p->graphs.begin());
-    }
-    p->graphs.push_back({key, exec});
-  }
-  RSWR_HIP(hipGraphLaunch(exec, s));
+rswr_status_t rswr_adjoint_workspace_size(rswr_plan_t p, int32_t n_rec, size_t* bytes) {
+  if (!p || !bytes || n_rec < 0) return fail(RSWR_ERR_INVALID_ARG, "bad argument");
+  *bytes = adj_ws_layout(*p, n_rec).total;
   return RSWR_OK;
+}
+
+rswr_status_t rswr_solve_adjoint(rswr_plan_t p, const void* checkpoints, const void* f_a,
+                                 const void* f_b, int64_t n_steps, const int64_t* rec_idx,
+                                 int32_t n_rec, const void* grad_traces, void* grad_f_a,
+                                 void* grad_f_b, double* grad_lambda, void* workspace,
+                                 size_t ws_bytes, void* stream) {
+  if (!p || !checkpoints || !f_a || !f_b || !grad_f_a || !grad_f_b || !grad_lambda)
+    return fail(RSWR_ERR_INVALID_ARG, "null pointer");
+  if (p->mode != RSWR_SPAN_FIXED)
+    return fail(RSWR_ERR_UNSUPPORTED, "rswr_solve_adjoint runs FIXED plans");
+  if (n_steps < 1 || n_rec < 0 || (n_rec > 0 && (!rec_idx || !grad_traces)))
+    return fail(RSWR_ERR_INVALID_ARG, "bad n_steps, receivers or grad_traces");
+  for (int32_t r = 0; r < n_rec; ++r)
+    if (rec_idx[r] < 0 || rec_idx[r] >= p->M)
+      return fail(RSWR_ERR_INVALID_ARG, "receiver index out of range");
+  const AdjWs L = adj_ws_layout(*p, n_rec);
+  if (!workspace || ws_bytes < L.total)
+    return fail(RSWR_ERR_NOMEM, "workspace needs " + std::to_string(L.total) + " bytes");
+  DevTables* d = nullptr;
+  int device = 0;
+  rswr_status_t st = ensure_device(p, &d, &device);
+  if (st != RSWR_OK) return st;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  char* ws = static_cast<char*>(workspace);
+  const int64_t TM = int64_t(p->threads) * p->per_thread;
+
+  // general kernel: small windows, tiles whose register region holds an
+  // interior receiver (its source), tiles storing node 1 or M-2 (dJ/df)
+  const int32_t n_all = static_cast<int32_t>(p->tiles.size());
+  std::vector<int32_t> gen, fast, ptr(1, 0), id;
+  std::vector<int64_t> node;
+  for (int32_t t = 0; t < n_all; ++t) {
+    const Tile& x = p->tiles[t];
+    std::vector<int32_t> here;
+    for (int32_t r = 0; r < n_rec; ++r) {
+      const int64_t j = rec_idx[r];
+      if (j > 0 && j < p->M - 1 && j >= x.a && j <= x.a + TM - 1) here.push_back(r);
+    }
+    const bool ends = (x.out_lo <= 1 && 1 <= x.out_hi) ||
+                      (x.out_lo <= p->M - 2 && p->M - 2 <= x.out_hi);
+    if (x.general || !here.empty() || ends) {
+      gen.push_back(t);
+      for (int32_t r : here) {
+        id.push_back(r);
+        node.push_back(rec_idx[r]);
+      }
+      ptr.push_back(static_cast<int32_t>(id.size()));
+    } else {
+      fast.push_back(t);
+    }
+  }
+  std::vector<int64_t> recs(rec_idx, rec_idx + n_rec);
+  auto up = [&](size_t off, const void* src, size_t bytes) -> rswr_status_t {
+    if (bytes) RSWR_HIP(hipMemcpyAsync(ws + off, src, bytes, hipMemcpyHostToDevice, s));
+    return RSWR_OK;
+  };
+  if ((st = up(L.gen_idx, gen.data(), gen.size() * 4)) != RSWR_OK) return st;
+  if ((st = up(L.fast_idx, fast.data(), fast.size() * 4)) != RSWR_OK) return st;
+  if ((st = up(L.src_ptr, ptr.data(), ptr.size() * 4)) != RSWR_OK) return st;
+  if ((st = up(L.src_node, node.data(), node.size() * 8)) != RSWR_OK) return st;
+  if ((st = up(L.src_id, id.data(), id.size() * 4)) != RSWR_OK) return st;
+  if ((st = up(L.rec_node, recs.data(), recs.size() * 8)) != RSWR_OK) return st;
+  AdjLists al;
+  al.n_gen = static_cast<int32_t>(gen.size());
+  al.n_fast = static_cast<int32_t>(fast.size());
+
+  auto enqueue = [&](hipStream_t q) {
+    return p->dtype == RSWR_F64
+               ? enqueue_adjoint<double>(p, *d, checkpoints, f_a, f_b, n_steps, al,
+                                         grad_traces, grad_f_a, grad_f_b, grad_lambda, ws,
+                                         L, n_rec, q)
+               : enqueue_adjoint<float>(p, *d, checkpoints, f_a, f_b, n_steps, al,
+                                        grad_traces, grad_f_a, grad_f_b, grad_lambda, ws,
+                                        L, n_rec, q);
+  };
+  const GraphKey key{2,
+                     device,
+                     reinterpret_cast<int64_t>(checkpoints),
+                     reinterpret_cast<int64_t>(f_a),
+                     reinterpret_cast<int64_t>(f_b),
+                     n_steps,
+                     n_rec,
+                     reinterpret_cast<int64_t>(grad_traces),
+                     reinterpret_cast<int64_t>(grad_f_a),
+                     reinterpret_cast<int64_t>(grad_f_b),
+                     reinterpret_cast<int64_t>(grad_lambda),
+                     reinterpret_cast<int64_t>(workspace),
+                     al.n_gen,
+                     al.n_fast};
+  return run_graph(p, d, key, enqueue, s);
 }
 
 }  // extern "C"

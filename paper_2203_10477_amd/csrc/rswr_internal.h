@@ -79,7 +79,49 @@ struct SelectArgs {
   int32_t n_rows, shat, ld, cone, mode, fixed_span;
 };
 
-// Launchers (defined in rswr_kernels.hip).  They return hipGetLastError().
+// Adjoint of the receiver misfit (see rswr_adjoint.hip).  The adjoint field
+// W runs backward in time: a span ending at level n_e starts from
+// (W^{n_e+2}, W^{n_e+1}) and ends at (W^{n_k+2}, W^{n_k+1}).
+template <typename T>
+struct AdjPredictArgs {
+  const T* w;           // [2][M]: row 0 = W^{n_e+2}, row 1 = W^{n_e+1}
+  T* flux;              // [N-1][2][ld]; sample t is taken from W^{n_e+1-t}
+  const int64_t* lo;
+  const int64_t* hi;
+  const int64_t* rec_node;  // all receivers, in receiver order
+  const T* gtr;         // dJ/dtrace [n_rec][gtr_ld], column L-1 for level L
+  int64_t gtr_ld, M, n_e;
+  int32_t N, shat, ld, n_rec;
+  T c2, k, r, q;
+};
+
+template <typename T>
+struct AdjUpdateArgs {
+  const T* w_in;        // [2][M] adjoint state at the span end
+  T* w_out;             // [2][M] adjoint state at the span start
+  const T* u_end;       // [2][M] forward state at the span end (levels n_e-1, n_e)
+  const T* u_beg;       // [2][M] forward state at the span start (row 1 = level n_k)
+  const T* ffl;         // forward fluxes of the span, sample m - n_k
+  const T* afl;         // adjoint fluxes of the span, sample n_e - L
+  const T* fa;
+  const T* fb;
+  const Tile* tiles;
+  const int32_t* tile_idx;
+  const int32_t* src_ptr;   // [n_tiles+1] CSR over this launch (general only)
+  const int64_t* src_node;
+  const int32_t* src_id;
+  const T* gtr;
+  int64_t gtr_ld;
+  T* grad_fa;           // [n_steps+1]
+  T* grad_fb;
+  double* lam_part;     // one accumulator per tile (indexed by tile number)
+  int64_t M, n_e, n_k;
+  int32_t n_tiles, span, ld, pad;
+  T c2, k, q;
+};
+
+// Launchers (defined in rswr_kernels.hip / rswr_adjoint.hip).  They return
+// hipGetLastError().
 template <typename T>
 hipError_t launch_predict(const PredictArgs<T>& a, int shmem_nodes,
                           hipStream_t s);
@@ -90,6 +132,22 @@ template <typename T>
 hipError_t launch_select(const SelectArgs<T>& a, hipStream_t s);
 template <typename T>
 hipError_t launch_copy(T* dst, const T* src, int64_t n, hipStream_t s);
+template <typename T>
+hipError_t launch_fill(T* dst, T v, int64_t n, hipStream_t s);
+template <typename T>
+hipError_t launch_adj_predict(const AdjPredictArgs<T>& a, int shmem_nodes,
+                              hipStream_t s);
+template <typename T>
+hipError_t launch_adj_update(const AdjUpdateArgs<T>& a, int threads,
+                             int per_thread, bool general, hipStream_t s);
+// grad_fa[L] += dJ/dtrace of receivers on node 0 (grad_fb: node M-1), in
+// receiver order, for L = 1..n_steps; grad_lam = 2 lam * sum(lam_part).
+template <typename T>
+hipError_t launch_adj_finish(T* grad_fa, T* grad_fb, const T* gtr, int64_t gtr_ld,
+                             const int64_t* rec_node, int32_t n_rec, int64_t M,
+                             int64_t n_steps, const double* lam_part,
+                             int32_t n_part, double lam, double* grad_lam,
+                             hipStream_t s);
 
 // Kernel shapes compiled into the library: (threads, nodes per lane).
 struct Shape {

@@ -5,57 +5,9 @@
 // u_new = fma(c2, s, t).  No packed FP32 (built with -packed-fp32-ops) and
 // no contraction (-ffp-contract=off), so every result is one fixed sequence
 // of correctly rounded IEEE operations.
-#include "rswr_internal.h"
+#include "rswr_device.h"
 
 namespace rswr {
-
-__device__ __forceinline__ float fma_(float a, float b, float c) {
-  return __builtin_fmaf(a, b, c);
-}
-__device__ __forceinline__ double fma_(double a, double b, double c) {
-  return __builtin_fma(a, b, c);
-}
-
-// Whole-wave lane shifts (DPP wave_shr:1 / wave_shl:1): a VALU move, no LDS
-// round trip.  Lane l receives lane l-1's (prev) or lane l+1's (next) value;
-// the lane at the wave's end receives its own value and is overwritten by
-// the caller.
-template <int CTRL>
-__device__ __forceinline__ uint32_t dpp32(uint32_t v) {
-  return static_cast<uint32_t>(__builtin_amdgcn_update_dpp(
-      static_cast<int>(v), static_cast<int>(v), CTRL, 0xf, 0xf, false));
-}
-constexpr int kWaveShr1 = 0x138;
-constexpr int kWaveShl1 = 0x130;
-
-template <int CTRL>
-__device__ __forceinline__ float lane_shift(float v) {
-  return __builtin_bit_cast(float, dpp32<CTRL>(__builtin_bit_cast(uint32_t, v)));
-}
-template <int CTRL>
-__device__ __forceinline__ double lane_shift(double v) {
-  const uint64_t b = __builtin_bit_cast(uint64_t, v);
-  const uint64_t lo = dpp32<CTRL>(static_cast<uint32_t>(b));
-  const uint64_t hi = dpp32<CTRL>(static_cast<uint32_t>(b >> 32));
-  return __builtin_bit_cast(double, lo | (hi << 32));
-}
-
-// Second-order leapfrog for Eq. (1) at one node.
-template <typename T>
-__device__ __forceinline__ T leap(T c2, T k, T ul, T u, T ur, T u_old) {
-  const T s = ul + ur;
-  const T t = fma_(k, u, -u_old);
-  return fma_(c2, s, t);
-}
-
-// Work-groups are dispatched to the 8 XCDs round-robin by block id.  Give
-// each XCD a contiguous run of tiles, so neighbouring tiles (which share
-// overlap nodes) meet in the same L2.
-__device__ __forceinline__ int xcd_tile(int bid, int nb) {
-  const int q = nb >> 3, r = nb & 7;
-  const int x = bid & 7, i = bid >> 3;
-  return (x < r) ? x * (q + 1) + i : r * (q + 1) + (x - r) * q + i;
-}
 
 // ---------------------------------------------------------------------------
 // Predict (Sec. 2.3, Eqs. (8)-(9)).  One wave per (interface i, side): side 0
@@ -137,86 +89,6 @@ __global__ __launch_bounds__(64) void k_predict(const PredictArgs<T> p) {
 // Loads and stores go through an LDS staging buffer so global accesses are
 // unit-stride across lanes.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ int pad32(int x) { return x + (x >> 5); }
-
-// Issue every load of a level before the first wait.  Regions fully inside
-// [0, M) read through a wave-uniform base pointer with 32-bit lane offsets;
-// edge regions clamp the index into [0, M) and replace the out-of-range
-// nodes by zero afterwards, so no load sits behind a branch either way.
-template <typename T, int NT, int MPT>
-__device__ __forceinline__ void load_level(const T* __restrict__ src, int64_t a,
-                                           int64_t M, bool inside, T (&tmp)[MPT]) {
-  const int tid = static_cast<int>(threadIdx.x);
-  if (inside) {
-    const T* __restrict__ b = src + a;
-#pragma unroll
-    for (int it = 0; it < MPT; ++it) tmp[it] = b[it * NT + tid];
-  } else {
-#pragma unroll
-    for (int it = 0; it < MPT; ++it) {
-      const int64_t j = a + it * NT + tid;
-      const int64_t jc = j < 0 ? 0 : (j >= M ? M - 1 : j);
-      tmp[it] = src[jc];
-    }
-#pragma unroll
-    for (int it = 0; it < MPT; ++it) {
-      const int64_t j = a + it * NT + tid;
-      tmp[it] = (j >= 0 && j < M) ? tmp[it] : T(0);
-    }
-  }
-}
-
-// Unit-stride (coalesced) values -> LDS -> this lane's MPT consecutive nodes.
-template <typename T, int NT, int MPT>
-__device__ __forceinline__ void transpose_in(const T (&tmp)[MPT], T* st, T (&v)[MPT]) {
-#pragma unroll
-  for (int it = 0; it < MPT; ++it) st[pad32(it * NT + static_cast<int>(threadIdx.x))] = tmp[it];
-  __syncthreads();
-#pragma unroll
-  for (int e = 0; e < MPT; ++e) v[e] = st[pad32(static_cast<int>(threadIdx.x) * MPT + e)];
-  __syncthreads();
-}
-
-// This lane's nodes -> LDS -> unit-stride stores of the stored range
-// [a + xlo, a + xhi] (offsets relative to the region start).
-template <typename T, int NT, int MPT>
-__device__ __forceinline__ void stage_out(T* __restrict__ dst, int64_t a, int xlo,
-                                          int xhi, T* st, const T (&v)[MPT]) {
-  const int tid = static_cast<int>(threadIdx.x);
-#pragma unroll
-  for (int e = 0; e < MPT; ++e) st[pad32(tid * MPT + e)] = v[e];
-  __syncthreads();
-  T tmp[MPT];
-#pragma unroll
-  for (int it = 0; it < MPT; ++it) tmp[it] = st[pad32(it * NT + tid)];
-  T* __restrict__ b = dst + a;
-#pragma unroll
-  for (int it = 0; it < MPT; ++it) {
-    const int x = it * NT + tid;
-    if (x >= xlo && x <= xhi) b[x] = tmp[it];
-  }
-  __syncthreads();
-}
-
-// Value of element d of a register array without indexing it: an indexed
-// read (or a select chain the compiler folds into one) would move the whole
-// array to scratch memory.
-template <typename T> struct Bits;
-template <> struct Bits<float> { using U = uint32_t; };
-template <> struct Bits<double> { using U = uint64_t; };
-
-template <typename T, int MPT>
-__device__ __forceinline__ T pick(const T (&v)[MPT], int64_t d) {
-  using U = typename Bits<T>::U;
-  U acc = 0;
-#pragma unroll
-  for (int e = 0; e < MPT; ++e) {
-    const U m = static_cast<U>(0) - static_cast<U>(d == e);
-    acc |= __builtin_bit_cast(U, v[e]) & m;
-  }
-  return __builtin_bit_cast(T, acc);
-}
-
 // cur = level n, old = level n-1 on entry; old = level n+1 on exit.
 // GEN: element dl takes the left-input ghost as its left neighbour and
 // element d0 is the Dirichlet node 0 (offsets relative to this lane's first
@@ -249,13 +121,6 @@ struct UpdateCtx {
   int lmode, rmode;
   bool gen;
 };
-
-// Value just outside the region: zero data, the input ghost (Eqs. (6)-(7)
-// with a centred flux), or the Dirichlet value of Eq. (3).
-template <typename T>
-__device__ __forceinline__ T end_value(int mode, T ghost, T dir) {
-  return (mode == kEndGhost) ? ghost : ((mode == kEndDirichlet) ? dir : T(0));
-}
 
 template <typename T, int NT, int MPT, bool GEN>
 __device__ __forceinline__ void one_step(const UpdateArgs<T>& p,
@@ -453,15 +318,6 @@ hipError_t launch_predict(const PredictArgs<T>& a, int shmem_nodes, hipStream_t 
   hipLaunchKernelGGL(k_predict<T>, dim3(2 * (a.N - 1)), dim3(64), shm, s, a);
   return hipGetLastError();
 }
-
-#define RSWR_SHAPES(X) \
-  X(64, 8)             \
-  X(128, 8)            \
-  X(256, 8)            \
-  X(256, 16)           \
-  X(320, 13)           \
-  X(512, 8)            \
-  X(512, 12)
 
 static const Shape kShapes[] = {
 #define RSWR_SHAPE_ENTRY(a, b) {a, b},

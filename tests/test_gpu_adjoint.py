@@ -1,0 +1,168 @@
+"""GPU adjoint of the receiver misfit against the CPU oracle's reverse mode.
+
+The GPU sweeps the adjoint field backward span by span with the method's own
+predict / update exchange and rebuilds the forward field by running the
+leapfrog backward from span checkpoints; the oracle is the plain reverse mode
+of the single-domain solve.  The two agree up to rounding: 1e-12 relative for
+dJ/df_A (FP64), 1e-9 for dJ/dlam (a sum over every node and level)."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2203_10477_amd as rs
+import workloads
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+
+
+def dev(x, dtype=torch.float64):
+    return torch.as_tensor(np.ascontiguousarray(x), dtype=dtype, device=DEV)
+
+
+def forward_gpu(plan, fa, fb, n_steps, rec, dtype=torch.float64):
+    st = torch.zeros(2, plan.M, dtype=dtype, device=DEV)
+    ck = plan.checkpoint_buffer(n_steps)
+    tr = rs.rswr_solve(plan, st, dev(fa, dtype), dev(fb, dtype), n_steps, receivers=rec,
+                       checkpoints=ck)
+    return tr, ck
+
+
+CASES = [
+    # M, N, P, tile, n_steps, receivers
+    (1001, 2, 20, None, 700, [0, 37, 489, 500, 510, 1000]),
+    (4097, 8, 64, None, 500, [3, 300, 1000, 2047, 2048, 4000, 4096]),
+    (301, 20, 20, None, 333, [1, 15, 150, 151, 299]),
+    (301, 20, 20, (64, 8), 250, [2, 100, 200, 298]),   # general tiles
+    (6000, 3, 40, (64, 8), 400, [10, 1990, 2000, 2010, 5000]),
+    (20001, 16, 64, (256, 16), 300, [5, 9000, 9001, 9001, 19990]),  # repeated receiver
+]
+
+
+@pytest.mark.parametrize("case", range(len(CASES)))
+def test_adjoint_matches_oracle(case):
+    M, N, P, tile, n_steps, rec = CASES[case]
+    say("adjoint", CASES[case])
+    plan = rs.Plan(M, N, P, tile=tile, dtype=torch.float64)
+    g = np.random.default_rng(case)
+    t = np.arange(n_steps + 1) * 0.9 / (M - 1)
+    fa = np.sin(2 * np.pi * 5 * t) * np.exp(-t) + 0.2
+    fa[0] = 0.0
+    fb = 0.3 * np.cos(2 * np.pi * 3 * t)
+    fb[0] = 0.0
+    rec = np.asarray(rec, np.int64)
+    w = g.standard_normal((len(rec), n_steps))
+    _, ck = forward_gpu(plan, fa, fb, n_steps, rec)
+    ga, gb, gl = rs.rswr_solve_adjoint(plan, ck, dev(fa), dev(fb), n_steps, rec, dev(w))
+    ra, rb, rl = oracle.adjoint(M, plan.info["lambda"], plan.info["dx"], fa, fb, n_steps, rec, w)
+    ga, gb, gl = ga.cpu().numpy(), gb.cpu().numpy(), float(gl.item())
+    assert np.abs(ga - ra).max() <= 1e-12 * np.abs(ra).max()
+    assert np.abs(gb - rb).max() <= 1e-12 * max(np.abs(rb).max(), 1e-300)
+    assert abs(gl - rl) <= 1e-9 * abs(rl), (gl, rl)
+
+
+def test_adjoint_dot_product():
+    """<A df, w> = <df, A^T w> with the GPU forward and the GPU adjoint."""
+    M, N, P, n_steps = 4097, 8, 64, 600
+    plan = rs.Plan(M, N, P, dtype=torch.float64)
+    g = np.random.default_rng(5)
+    rec = np.sort(g.choice(np.arange(1, 700), 9, replace=False))
+    df = np.concatenate([[0.0], g.standard_normal(n_steps)])
+    z = np.zeros(n_steps + 1)
+    w = g.standard_normal((len(rec), n_steps))
+    tr, ck = forward_gpu(plan, df, z, n_steps, rec)
+    ga, _, _ = rs.rswr_solve_adjoint(plan, ck, dev(df), dev(z), n_steps, rec, dev(w))
+    Adf = tr.cpu().numpy()
+    lhs = np.sum(Adf * w)
+    rhs = np.sum(df * ga.cpu().numpy())
+    assert abs(lhs - rhs) <= 1e-12 * np.sqrt(np.sum(Adf ** 2) * np.sum(w ** 2))
+
+
+@pytest.mark.parametrize("dtype", [torch.float64])
+def test_autograd_against_finite_differences(dtype):
+    """RSWRFunction: dJ/da by the adjoint against central differences of the
+    GPU forward (h = 1e-6), and dJ/df_A against the oracle."""
+    M, N, P, n_steps = 2001, 4, 40, 1500
+    t = np.arange(n_steps + 1) * 0.9 / (M - 1)
+    fa_np = np.exp(-((t - 0.1) / 0.02) ** 2)
+    fa_np[0] = 0.0
+    rec = np.array([50, 400, 900, 1300], np.int64)
+    spec = rs.ProblemSpec(M, N, P, n_steps, rec, dtype=dtype)
+    # data from a run at a = 1.1
+    with torch.no_grad():
+        d = rs.RSWRFunction.apply(dev(fa_np, dtype), torch.tensor(1.1, dtype=torch.float64),
+                                  spec)
+    fa = dev(fa_np, dtype).requires_grad_(True)
+    a = torch.tensor(1.0, dtype=torch.float64, requires_grad=True)
+    tr = rs.RSWRFunction.apply(fa, a, spec)
+    J = ((tr - d) ** 2).sum()
+    J.backward()
+
+    def J_at(av):
+        with torch.no_grad():
+            trh = rs.RSWRFunction.apply(dev(fa_np, dtype), torch.tensor(av, dtype=torch.float64),
+                                        spec)
+            return float(((trh - d) ** 2).sum().item())
+
+    h = 1e-6
+    fd = (J_at(1.0 + h) - J_at(1.0 - h)) / (2 * h)
+    assert abs(a.grad.item()) > 1e-3
+    assert abs(fd - a.grad.item()) <= 1e-6 * abs(a.grad.item()), (fd, a.grad.item())
+    # dJ/df_A against the oracle reverse mode
+    trn = tr.detach().cpu().numpy()
+    ra, _, _ = oracle.adjoint(M, 0.9, 1 / (M - 1), fa_np, np.zeros_like(fa_np), n_steps, rec,
+                              2.0 * (trn - d.cpu().numpy()))
+    gfa = fa.grad.cpu().numpy()
+    assert np.abs(gfa - ra).max() <= 1e-11 * np.abs(ra).max()
+
+
+def test_adjoint_fp32_close_to_fp64_oracle():
+    M, N, P, n_steps = 1001, 2, 20, 500
+    plan = rs.Plan(M, N, P, dtype=torch.float32)
+    g = np.random.default_rng(2)
+    t = np.arange(n_steps + 1) * 0.9 / (M - 1)
+    fa = np.sin(2 * np.pi * 4 * t)
+    fa[0] = 0
+    fb = np.zeros_like(fa)
+    rec = np.array([0, 250, 500, 750], np.int64)
+    w = g.standard_normal((4, n_steps))
+    st = torch.zeros(2, M, dtype=torch.float32, device=DEV)
+    ck = plan.checkpoint_buffer(n_steps)
+    rs.rswr_solve(plan, st, dev(fa, torch.float32), dev(fb, torch.float32), n_steps,
+                  receivers=rec, checkpoints=ck)
+    ga, _, gl = rs.rswr_solve_adjoint(plan, ck, dev(fa, torch.float32),
+                                      dev(fb, torch.float32), n_steps, rec,
+                                      dev(w, torch.float32))
+    ra, _, rl = oracle.adjoint(M, 0.9, 1 / (M - 1), fa.astype(np.float32).astype(np.float64),
+                               fb, n_steps, rec, w.astype(np.float32).astype(np.float64))
+    assert np.linalg.norm(ga.cpu().numpy() - ra) <= 1e-4 * np.linalg.norm(ra)
+    assert abs(gl.item() - rl) <= 1e-3 * abs(rl)
+
+
+def test_adjoint_full_size_fp64():
+    """The adjoint case at full size: 2^18 nodes, 128 windows, overlap 64,
+    8192 steps, 16 receivers, misfit against data from a run at a = 1.1;
+    gradient w.r.t. 8192 source samples and a against the oracle."""
+    prob = workloads.config4()
+    say("adjoint-2^18-fp64")
+    M, n_steps, rec = prob.M, prob.n_steps, prob.rec
+    fa, fb = prob.sources()
+    dx = prob.dx
+    _, d = oracle.single(M, 0.99, dx, fa, fb, n_steps, rec=rec)  # lam = 0.9 * 1.1
+    plan = rs.Plan(M, prob.N, prob.P, dtype=torch.float64)
+    assert plan.span == 35
+    tr, ck = forward_gpu(plan, fa, fb, n_steps, rec)
+    resid = 2.0 * (tr.cpu().numpy() - d)
+    ga, _, gl = rs.rswr_solve_adjoint(plan, ck, dev(fa), dev(fb), n_steps, rec, dev(resid))
+    _, tr_ref = oracle.single(M, 0.9, dx, fa, fb, n_steps, rec=rec)
+    assert np.abs(tr.cpu().numpy() - tr_ref).max() <= 1e-12 * np.abs(tr_ref).max()
+    ra, _, rl = oracle.adjoint(M, 0.9, dx, fa, fb, n_steps, rec, 2.0 * (tr_ref - d), ck=128)
+    gah = ga.cpu().numpy()
+    assert np.abs(ra).max() > 0
+    assert np.abs(gah - ra).max() <= 1e-11 * np.abs(ra).max()
+    assert abs(gl.item() - rl) <= 1e-8 * abs(rl), (gl.item(), rl)

@@ -249,13 +249,13 @@ def test_solve_graph_replay_and_checkpoints(dtype):
         rs.rswr_solve(plan, st, fa_d, fb_d, n_steps, workspace=ws)
         torch.cuda.synchronize()
         assert np.array_equal(host(st), ref), rep
-    K = -(-n_steps // plan.span)
-    ck = torch.zeros((K + 1, 2, M), dtype=dtype, device=DEV)
+    K = plan.n_spans(n_steps)
+    ck = plan.checkpoint_buffer(n_steps)
     st = dev(st0, dtype)
     rs.rswr_solve(plan, st, fa_d, fb_d, n_steps, checkpoints=ck, workspace=ws)
     torch.cuda.synchronize()
     assert np.array_equal(host(st), ref)
-    ckh = host(ck)
+    ckh = host(plan.checkpoint_states(ck, n_steps))
     assert np.array_equal(ckh[0], st0)
     for k in (1, K // 2, K):
         nk = min(k * plan.span, n_steps)
