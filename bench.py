@@ -79,6 +79,8 @@ def main():
     ap.add_argument("--kernel-reps", type=int, default=40)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--tile", default="", help="threads x nodes-per-lane, e.g. 320x13 "
+                    "(default: autotuned)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
@@ -91,11 +93,17 @@ def main():
     import paper_2203_10477_amd as rs
     import workloads
 
+    from paper_2203_10477_amd.autotune import autotune
+
     dev = "cuda:0"
     torch.cuda.set_device(0)
     prob = workloads.config5(np.float32)
     dtype = torch.float32
-    plan = rs.Plan(prob.M, prob.N, prob.P, dtype=dtype)
+    if args.tile:
+        tile, tune = tuple(int(v) for v in args.tile.split("x")), {}
+    else:
+        tile, tune = autotune(prob.M, prob.N, prob.P, dtype=dtype, reps=5)
+    plan = rs.Plan(prob.M, prob.N, prob.P, dtype=dtype, tile=tile)
     S = plan.span
     fa_np, fb_np = prob.sources()
     fa = torch.as_tensor(fa_np, device=dev)
@@ -164,7 +172,8 @@ def main():
                    "n_points": prob.M, "n_sub": prob.N, "overlap": prob.P, "span": S,
                    "n_steps": prob.n_steps, "n_spans": n_spans,
                    "tile": [plan.info["tile_threads"], plan.info["tile_per_thread"]],
-                   "n_tiles": plan.info["n_tiles"]},
+                   "n_tiles": plan.info["n_tiles"],
+                   "autotune_us": {f"{a}x{b}": round(v, 1) for (a, b), v in tune.items()}},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic, "kernel": "k_update (one span, all windows)",

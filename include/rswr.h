@@ -117,6 +117,14 @@ typedef struct {
   double dx, dt, lambda;
 } rswr_plan_info_t;
 
+/* (host) Kernel shapes built into the library: up to `cap` (threads per
+ * work-group, nodes per lane) pairs and whether FP64 may use them
+ * (fp64_ok[i] = 0 when the shape would not fit the register file in FP64).
+ * Returns the number of shapes; any of them may be given to rswr_plan as
+ * tile_threads / tile_per_thread. */
+int32_t rswr_kernel_shapes(int32_t* threads, int32_t* per_thread,
+                           int32_t* fp64_ok, int32_t cap);
+
 /* Builds a plan from the problem statement of Sec. 2.1-2.2 and Sec. 3.
  * Host only: makes no HIP call.  Errors: INVALID_ARG, UNSTABLE, LAYOUT,
  * SPAN, UNSUPPORTED, NOMEM. */

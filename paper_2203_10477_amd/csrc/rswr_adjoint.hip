@@ -163,15 +163,17 @@ __device__ __forceinline__ void adj_step(const AdjUpdateArgs<T>& p,
   T Rw = lane_shift<kWaveShl1>(wc[0]);
   T Lu = lane_shift<kWaveShr1>(uc[MPT - 1]);
   T Ru = lane_shift<kWaveShl1>(uc[0]);
-  if (c.lane == 63) {
-    c.edge[par][1][c.wv] = wc[MPT - 1];
-    c.edge[par][3][c.wv] = uc[MPT - 1];
+  if constexpr (NW > 1) {
+    if (c.lane == 63) {
+      c.edge[par][1][c.wv] = wc[MPT - 1];
+      c.edge[par][3][c.wv] = uc[MPT - 1];
+    }
+    if (c.lane == 0) {
+      c.edge[par][0][c.wv] = wc[0];
+      c.edge[par][2][c.wv] = uc[0];
+    }
+    __syncthreads();
   }
-  if (c.lane == 0) {
-    c.edge[par][0][c.wv] = wc[0];
-    c.edge[par][2][c.wv] = uc[0];
-  }
-  __syncthreads();
   if (c.lane == 0) {
     if (c.wv > 0) {
       Lw = c.edge[par][1][c.wv - 1];

@@ -144,7 +144,11 @@ __device__ __forceinline__ T end_value(int mode, T ghost, T dir) {
 // library; the update and adjoint launchers dispatch over this list.
 #define RSWR_SHAPES(X) \
   X(64, 8)             \
+  X(64, 33)            \
+  X(64, 65)            \
   X(128, 8)            \
+  X(128, 33)           \
+  X(192, 22)           \
   X(256, 8)            \
   X(256, 16)           \
   X(320, 13)           \

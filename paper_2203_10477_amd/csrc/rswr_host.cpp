@@ -181,14 +181,64 @@ bool build_tiles(const rswr_plan_s& p, int TM, int S, std::vector<Tile>& out) {
     const int32_t rmode0 = last ? rswr::kEndDirichlet : rswr::kEndGhost;
     const int64_t lb0 = (i == 0) ? 1 : lo;
     const int32_t lmode0 = (i == 0) ? rswr::kEndDirichlet : rswr::kEndGhost;
-    int64_t cur = Ohi;
-    bool first = true;
-    while (cur >= Olo) {
+    auto base_tile = [&]() {
       Tile t{};
       t.lin = rswr::kNoNode;
       t.fl = -1;
       t.fr = -1;
       t.window = i;
+      return t;
+    };
+    if (rb0 - lb0 + 1 < TM) {
+      // The window is narrower than one region.  A tile ending at the exact
+      // right end treats the window's left end as a plain stencil node: node
+      // w0 (node 0, or the left input) is wrong from the first level on, so
+      // it stores only nodes >= w0 + S.  If that misses part of the owned
+      // range, a second tile starting at the exact left end stores it; it
+      // treats the right end w1 (node M-1, or the right input) as a plain
+      // node and so stores only nodes <= w1 - S.  If the two cannot cover the
+      // owned range, one general tile.
+      const int64_t w0 = (i == 0) ? 0 : lo;
+      const int64_t w1 = last ? p.M - 1 : hi;
+      const int64_t split_lo = w0 + S;
+      const int64_t split_hi = w1 - S;
+      Tile r = base_tile();
+      r.a = rb0 - TM + 1;
+      r.rmode = rmode0;
+      if (!last) r.fr = i;
+      r.lmode = rswr::kEndZero;
+      r.out_hi = Ohi;
+      if (split_lo <= Olo) {
+        r.out_lo = Olo;
+        out.push_back(r);
+        continue;
+      }
+      if (split_lo - 1 <= split_hi && split_lo <= Ohi) {
+        r.out_lo = split_lo;
+        Tile l = base_tile();
+        l.a = lb0;
+        l.lmode = lmode0;
+        if (i > 0) l.fl = i - 1;
+        l.rmode = rswr::kEndZero;
+        l.out_lo = Olo;
+        l.out_hi = split_lo - 1;
+        out.push_back(r);
+        out.push_back(l);
+        continue;
+      }
+      r.general = 1;
+      if (i > 0) {
+        r.lin = lo;
+        r.fl = i - 1;
+      }
+      r.out_lo = Olo;
+      out.push_back(r);
+      continue;
+    }
+    int64_t cur = Ohi;
+    bool first = true;
+    while (cur >= Olo) {
+      Tile t = base_tile();
       int64_t rb;
       if (first) {
         rb = rb0;
@@ -203,18 +253,12 @@ bool build_tiles(const rswr_plan_s& p, int TM, int S, std::vector<Tile>& out) {
       t.lmode = rswr::kEndZero;
       bool exact_left = false;
       if (t.a <= lb0) {
+        // only non-first tiles get here (the window is at least one region
+        // wide): start exactly at the window's left end
         exact_left = true;
-        if (t.a == lb0 || !first) {
-          t.a = lb0;
-          t.lmode = lmode0;
-          if (i > 0) t.fl = i - 1;
-        } else {
-          t.general = 1;  // the window's left end lies inside the region
-          if (i > 0) {
-            t.lin = lo;
-            t.fl = i - 1;
-          }
-        }
+        t.a = lb0;
+        t.lmode = lmode0;
+        if (i > 0) t.fl = i - 1;
       }
       t.out_hi = cur;
       t.out_lo = exact_left ? Olo : std::max(t.a + S, Olo);
@@ -229,6 +273,10 @@ bool build_tiles(const rswr_plan_s& p, int TM, int S, std::vector<Tile>& out) {
   return true;
 }
 
+// FP64 keeps two levels of MPT doubles per lane in registers; beyond 22
+// nodes per lane that no longer fits without spilling.
+bool shape_fits_fp64(const rswr::Shape& sh) { return sh.per_thread <= 22; }
+
 // Default kernel shape: the least padded work, penalising launches too small
 // to give every one of the 256 compute units a couple of work-groups.
 bool choose_shape(rswr_plan_s& p) {
@@ -237,7 +285,8 @@ bool choose_shape(rswr_plan_s& p) {
   std::vector<Tile> tiles;
   for (int s = 0; s < rswr::n_shapes(); ++s) {
     const rswr::Shape sh = rswr::shape_at(s);
-    if (p.dtype == RSWR_F64 && sh.threads * sh.per_thread > 6144) continue;
+    if (p.dtype == RSWR_F64 && (sh.threads * sh.per_thread > 6144 || !shape_fits_fp64(sh)))
+      continue;
     const int TM = sh.threads * sh.per_thread;
     if (TM < 2 * p.S_max + 2) continue;
     if (!build_tiles(p, TM, p.S_max, tiles)) continue;
@@ -629,6 +678,18 @@ const char* rswr_status_string(rswr_status_t s) {
   return "unknown status";
 }
 
+int32_t rswr_kernel_shapes(int32_t* threads, int32_t* per_thread, int32_t* fp64_ok,
+                           int32_t cap) {
+  const int n = rswr::n_shapes();
+  for (int i = 0; i < n && i < cap; ++i) {
+    const rswr::Shape sh = rswr::shape_at(i);
+    if (threads) threads[i] = sh.threads;
+    if (per_thread) per_thread[i] = sh.per_thread;
+    if (fp64_ok) fp64_ok[i] = shape_fits_fp64(sh) ? 1 : 0;
+  }
+  return n;
+}
+
 rswr_status_t rswr_plan(const rswr_desc_t* desc, rswr_plan_t* out) {
   if (!desc || !out) return fail(RSWR_ERR_INVALID_ARG, "null descriptor or output");
   *out = nullptr;
@@ -717,9 +778,11 @@ rswr_status_t rswr_plan(const rswr_desc_t* desc, rswr_plan_t* out) {
   p->flux_ld = static_cast<int32_t>(round_up(p->S_max, 16));
 
   if (D.tile_threads > 0 || D.tile_per_thread > 0) {
-    if (!rswr::shape_built(D.tile_threads, D.tile_per_thread)) {
+    if (!rswr::shape_built(D.tile_threads, D.tile_per_thread) ||
+        (p->dtype == RSWR_F64 &&
+         !shape_fits_fp64(rswr::Shape{D.tile_threads, D.tile_per_thread}))) {
       delete p;
-      return fail(RSWR_ERR_UNSUPPORTED, "tile shape not built into the library");
+      return fail(RSWR_ERR_UNSUPPORTED, "tile shape not built for this dtype");
     }
     const int TM = D.tile_threads * D.tile_per_thread;
     if (TM < 2 * p->S_max + 2 || !build_tiles(*p, TM, p->S_max, p->tiles)) {

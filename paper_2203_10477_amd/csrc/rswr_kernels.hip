@@ -131,9 +131,11 @@ __device__ __forceinline__ void one_step(const UpdateArgs<T>& p,
   const int par = s & 1;
   T L = lane_shift<kWaveShr1>(cur[MPT - 1]);
   T R = lane_shift<kWaveShl1>(cur[0]);
-  if (c.lane == 63) c.edge[par][1][c.wv] = cur[MPT - 1];
-  if (c.lane == 0) c.edge[par][0][c.wv] = cur[0];
-  __syncthreads();
+  if constexpr (NW > 1) {
+    if (c.lane == 63) c.edge[par][1][c.wv] = cur[MPT - 1];
+    if (c.lane == 0) c.edge[par][0][c.wv] = cur[0];
+    __syncthreads();
+  }
   if (c.lane == 0)
     L = (c.wv > 0) ? c.edge[par][1][c.wv - 1]
                    : end_value(c.lmode, fma_(-p.q, c.sL[s], cur[1]), c.sA[s]);

@@ -122,6 +122,29 @@ def test_update_bitwise(dtype, case):
 
 
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_update_general_tiles_bitwise(dtype):
+    """Spans up to twice the light-cone limit (QUIET plans) over windows
+    narrower than that reach both window ends: general tiles with the left
+    input ghost and node 0 strictly inside the register region."""
+    M, N, P = 301, 20, 20
+    plan = rs.Plan(M, N, P, span_mode=rs.QUIET, tile=(64, 8), dtype=dtype)
+    assert plan.tiles()[:, 7].sum() > 0
+    lay = lay_of(plan)
+    npdt = NP[dtype]
+    for S in (plan.info["span_cone"], plan.info["span"]):
+        say("update-general", dtype, "S", S)
+        st, fa, fb = busy(M, 40 + S, seed=S)
+        st, fa, fb = st.astype(npdt), fa.astype(npdt), fb.astype(npdt)
+        flux = oracle.predict(lay, plan.info["lambda"], plan.info["dx"], fa, fb, 2, S, st,
+                              ld=plan.flux_ld)
+        ref, _ = oracle.update(lay, plan.info["lambda"], plan.info["dx"], fa, fb, 2, S, st,
+                               flux)
+        out = rs.rswr_update(plan, dev(st, dtype), dev(fa, dtype), dev(fb, dtype), 2,
+                             dev(flux, dtype), span=S)
+        assert np.array_equal(host(out), ref), S
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
 def test_quiet_loop_matches_oracle(dtype):
     """predict -> select (QUIET, on the device) -> update, span by span; the
     chosen spans and the state equal the oracle's adaptive loop."""

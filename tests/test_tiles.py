@@ -19,7 +19,13 @@ LAYOUTS = [
     dict(n_points=1201, n_sub=4, overlap=24, span_mode=rs.QUIET),
     dict(n_points=400, n_sub=4, overlap=0, windows=([0, 90, 200, 260], [110, 230, 290, 399])),
     dict(n_points=101, n_sub=2, overlap=0, windows=([0, 5], [30, 100])),
+    dict(n_points=301, n_sub=20, overlap=20, span_mode=rs.QUIET, tile=(64, 8)),
 ]
+
+
+def test_narrow_windows_under_long_spans_use_general_tiles():
+    plan = rs.Plan(301, 20, 20, span_mode=rs.QUIET, tile=(64, 8))
+    assert plan.tiles()[:, 7].sum() > 0
 
 
 def check_plan(plan):
@@ -39,8 +45,11 @@ def check_plan(plan):
         assert olo[w] <= s_lo and s_hi <= ohi[w]
         lb0 = 1 if w == 0 else lo[w]
         rb0 = M - 2 if w == plan.N - 1 else hi[w]
-        # left end: exact at the window's left end, inside it (general), or
-        # far enough from every stored node
+        w0 = 0 if w == 0 else lo[w]          # window's left special node
+        w1 = M - 1 if w == plan.N - 1 else hi[w]
+        # left end: exact at the window's left end, the window's left end
+        # strictly inside (general tile), or every stored node at least S
+        # from the first node that is treated wrongly
         if lm == 1:
             assert w > 0 and a == lo[w]
         elif lm == 2:
@@ -48,13 +57,15 @@ def check_plan(plan):
         elif gen:
             assert a < lb0
         else:
-            assert a > lb0 and s_lo >= a + S
+            first_wrong = a if a > lb0 else w0
+            assert s_lo >= first_wrong + S
         if rm == 1:
             assert w < plan.N - 1 and b == hi[w]
         elif rm == 2:
             assert w == plan.N - 1 and b == M - 2
         else:
-            assert b < rb0 and s_hi <= b - S
+            last_wrong = b if b < rb0 else w1
+            assert s_hi <= last_wrong - S
         assert s_lo >= a or (lm == 2 and s_lo == 0)
         assert s_hi <= b or (rm == 2 and s_hi == M - 1)
 
@@ -80,4 +91,8 @@ def test_random_layouts():
 def test_large_case_shape():
     plan = rs.Plan(2 ** 24, 4096, 64, dtype=__import__("torch").float32)
     assert plan.span == 35
-    assert plan.info["n_tiles"] == 4096  # one work-group per window
+    # one work-group per window, plus one for window 0 (narrower than a tile:
+    # its nodes next to the Dirichlet node come from a second, left-anchored
+    # tile); no general tiles
+    assert plan.info["n_tiles"] == 4097
+    assert plan.tiles()[:, 7].sum() == 0
