@@ -10,9 +10,9 @@ resident in HBM before the timed region; each step restores the initial state
 with a device copy and runs the recorded graph of all 572 spans.
 
 Prints one JSON line: throughput in grid-point updates per second (GLUPS,
-M * n_steps / time), the roofline of the dominant kernel (the update kernel,
-timed alone with HIP events on the stream it runs on), and the CPU oracle
-timed on a bounded sample of the same workload.
+M * n_steps / time), the roofline of the dominant kernel (the fused span
+kernel, timed alone with HIP events on the stream it runs on), and the CPU
+oracle timed on a bounded sample of the same workload.
 """
 import argparse
 import hashlib
@@ -27,25 +27,30 @@ sys.path.insert(0, ROOT)
 METRIC = "grid-point updates/sec (GLUPS) + % HBM roofline, plain vs batched vs adjoint"
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
 
-# HBM traffic of one update launch on this workload, from two rocprofv3 --pmc
-# passes (FETCH_SIZE, WRITE_SIZE; see profiles/), valid only for the kernel
-# source with this SHA-256 prefix.
-TRAFFIC = {"kernel_sha": None, "bytes": None}
+# HBM traffic of one span kernel launch on this workload, from two rocprofv3
+# --pmc passes (FETCH_SIZE, WRITE_SIZE; see profiles/), valid only for the
+# kernel sources with this SHA-256 prefix.
+TRAFFIC = {"kernel_sha": "0ce2c3abb1f70ae4", "bytes": 270230750}
 
 
 def kernel_sha():
-    path = os.path.join(ROOT, "paper_2203_10477_amd", "csrc", "rswr_kernels.hip")
-    return hashlib.sha256(open(path, "rb").read()).hexdigest()[:16]
+    """Hash of the span kernel's sources (the fused kernel and its helpers)."""
+    h = hashlib.sha256()
+    for name in ("rswr_fused.hip", "rswr_device.h", "rswr_internal.h"):
+        h.update(open(os.path.join(ROOT, "paper_2203_10477_amd", "csrc", name), "rb").read())
+    return h.hexdigest()[:16]
 
 
-def update_bytes(plan, elem):
-    """Algorithmic bytes of one update launch: every window reads its two
-    levels, the owned ranges of two levels are written, and every window reads
-    its input flux waveforms (S samples per input)."""
+def span_bytes(plan, elem):
+    """Algorithmic HBM bytes of one span: every window reads its two levels
+    and the owned ranges of two levels are written.  Where the plan cannot
+    fuse, the predicted fluxes also make a round trip through memory (S
+    samples per input end, written once and read once)."""
     lo, hi, _, _ = plan.layout()
     sum_n = int((hi - lo + 1).sum())
     N, M, S = plan.N, plan.M, plan.span
-    return elem * (2 * sum_n + 2 * M + 2 * (N - 1) * S)
+    flux = 0 if plan.info["fused"] else 2 * 2 * (N - 1) * S
+    return elem * (2 * sum_n + 2 * M + flux)
 
 
 def cpu_baseline(prob, target_s):
@@ -112,9 +117,19 @@ def main():
     st = st0.clone()
     ws = torch.empty(plan.workspace_bytes(0), dtype=torch.uint8, device=dev)
 
-    def step():
+    # each step: restore the initial state, then the solve (one recorded
+    # graph of all span launches); events around each solve give the span
+    # kernel's average duration inside the timed region
+    marks = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+             for _ in range(args.steps)]
+
+    def step(mark=None):
         st.copy_(st0)
+        if mark:
+            mark[0].record()
         rs.rswr_solve(plan, st, fa, fb, prob.n_steps, workspace=ws)
+        if mark:
+            mark[1].record()
 
     for _ in range(args.warmup):
         step()
@@ -122,45 +137,48 @@ def main():
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     t0 = time.perf_counter()
     ev0.record()
-    for _ in range(args.steps):
-        step()
+    for k in range(args.steps):
+        step(marks[k])
     ev1.record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ms_step = wall * 1e3 / args.steps
     ev_ms_step = ev0.elapsed_time(ev1) / args.steps
+    solve_ms = sum(a.elapsed_time(b) for a, b in marks)
     glups = prob.M * prob.n_steps / (ms_step * 1e-3) / 1e9
     if not torch.isfinite(st).all():
         raise RuntimeError("non-finite state after the benchmark solve")
 
-    # dominant kernel: one update launch (a full span of all windows) timed
-    # alone on the current stream
+    # dominant kernel: the span kernel (one launch per span, all windows).
+    # Its average duration in the timed region: solve time / launches.
+    n_spans = -(-prob.n_steps // S)
+    span_us = solve_ms * 1e3 / (args.steps * n_spans)
+    fused = bool(plan.info["fused"])
+
+    # The same kernel on a busy field: R spans from a smooth state that is
+    # nonzero everywhere (the Ricker run is mostly at rest), timed the same
+    # way; R even, so the recorded graph holds the span launches only.
     g = np.random.default_rng(1)
-    sm = torch.as_tensor(workloads.smooth_state(prob.M, g, shift=prob.lam * prob.dx),
-                         dtype=dtype, device=dev)
-    flux = rs.rswr_predict(plan, sm, fa, fb, 0, S)
-    out = torch.empty_like(sm)
-    for _ in range(5):
-        rs.rswr_update(plan, sm, fa, fb, 0, flux, span=S, out=out)
+    sm0 = torch.as_tensor(workloads.smooth_state(prob.M, g, shift=prob.lam * prob.dx),
+                          dtype=dtype, device=dev)
+    R = max(2, args.kernel_reps - args.kernel_reps % 2)
+    if R * S > prob.n_steps:
+        raise ValueError("kernel-reps too large for the source length")
+    sm = sm0.clone()
+    rs.rswr_solve(plan, sm, fa, fb, R * S, workspace=ws)  # records the graph
+    sm.copy_(sm0)
     torch.cuda.synchronize()
     ev0.record()
-    for _ in range(args.kernel_reps):
-        rs.rswr_update(plan, sm, fa, fb, 0, flux, span=S, out=out)
+    rs.rswr_solve(plan, sm, fa, fb, R * S, workspace=ws)
     ev1.record()
     torch.cuda.synchronize()
-    upd_us = ev0.elapsed_time(ev1) * 1e3 / args.kernel_reps
-    ev0.record()
-    for _ in range(args.kernel_reps):
-        rs.rswr_predict(plan, sm, fa, fb, 0, S, flux)
-    ev1.record()
-    torch.cuda.synchronize()
-    pred_us = ev0.elapsed_time(ev1) * 1e3 / args.kernel_reps
-    nbytes = update_bytes(plan, 4)
-    achieved = nbytes / (upd_us * 1e-6) / 1e9
+    busy_us = ev0.elapsed_time(ev1) * 1e3 / R
+    nbytes = span_bytes(plan, 4)
+    achieved = nbytes / (span_us * 1e-6) / 1e9
     sha = kernel_sha()
     traffic = TRAFFIC["bytes"] if TRAFFIC["kernel_sha"] == sha else None
-    n_spans = -(-prob.n_steps // S)
-    span_bytes = nbytes + 4 * 2 * (prob.N - 1) * S  # plus the predict's flux writes
+    kname = ("k_fused (predict + update of one span, all windows, one launch)" if fused
+             else "k_predict + k_update (one span, all windows)")
 
     line = {
         "metric": METRIC, "value": round(glups, 2), "unit": "GLUPS", "n_gpus": 1,
@@ -176,11 +194,12 @@ def main():
                    "autotune_us": {f"{a}x{b}": round(v, 1) for (a, b), v in tune.items()}},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": traffic, "kernel": "k_update (one span, all windows)",
-                     "avg_us": round(upd_us, 2), "algorithmic_bytes": nbytes},
-        "step": {"event_ms_per_step": round(ev_ms_step, 4),
-                 "predict_avg_us": round(pred_us, 2),
-                 "hbm_frac_whole_step": round(span_bytes * n_spans / (ms_step * 1e-3)
+                     "traffic": traffic, "kernel": kname,
+                     "avg_us": round(span_us, 2), "algorithmic_bytes": nbytes,
+                     "busy_field_avg_us": round(busy_us, 2),
+                     "busy_field_frac": round(nbytes / (busy_us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4)},
+        "step": {"event_ms_per_step": round(ev_ms_step, 4), "fused": fused,
+                 "hbm_frac_whole_step": round(nbytes * n_spans / (ms_step * 1e-3)
                                               / 1e9 / HBM_PEAK_GBS, 4)},
     }
     if not args.no_cpu:

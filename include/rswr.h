@@ -103,6 +103,9 @@ typedef struct {
   int32_t dtype;            /* rswr_dtype_t */
   int32_t tile_threads;     /* 0 = library choice; else a built kernel shape */
   int32_t tile_per_thread;  /* nodes per lane of that shape */
+  int32_t no_fuse;          /* 1 = rswr_solve keeps predict and update as two
+                               launches per span even where the fused span
+                               applies (see rswr_plan_info_t.fused) */
 } rswr_desc_t;
 
 typedef struct {
@@ -115,6 +118,12 @@ typedef struct {
   int32_t n_tiles;          /* update work-groups per span */
   int32_t tile_threads, tile_per_thread;
   double dx, dt, lambda;
+  int32_t fused;            /* 1: rswr_solve runs each span as one launch, the
+                               prediction of every input end carried by the
+                               wave holding that end (fixed span S <= 63,
+                               no interior inputs, nodes 0 and M-1 more than
+                               S nodes from every input end); results are
+                               identical either way */
 } rswr_plan_info_t;
 
 /* (host) Kernel shapes built into the library: up to `cap` (threads per
@@ -167,6 +176,20 @@ rswr_status_t rswr_update(rswr_plan_t plan, const void* state_in,
                           const void* f_a, const void* f_b, int64_t n0,
                           const void* flux, const int32_t* span_dev,
                           int32_t span, void* state_out, void* stream);
+
+/* One whole span of the redo loop (Sec. 2.6) with the fixed span: the
+ * predict of Sec. 2.3 and the update and gluing of Sec. 2.5 over `span`
+ * levels (1..S) from levels n0-1, n0 in `state_in` to levels n0+span-1,
+ * n0+span in `state_out` (must not overlap `state_in`).  Plans with
+ * rswr_plan_info_t.fused run it as one launch: then `flux` is optional and,
+ * when given ([N-1][2][flux_ld], device), receives the predicted flux rows of
+ * the input ends the tiles use.  Other plans predict into `flux` (required
+ * when N > 1) and update from it, two launches.  f_a, f_b as for
+ * rswr_predict.  The result is the same either way.  Errors: INVALID_ARG,
+ * SPAN, UNSUPPORTED (QUIET plans), HIP. */
+rswr_status_t rswr_span(rswr_plan_t plan, const void* state_in, const void* f_a,
+                        const void* f_b, int64_t n0, int32_t span, void* flux,
+                        void* state_out, void* stream);
 
 /* Bytes of device workspace rswr_solve needs for n_rec receivers. */
 rswr_status_t rswr_solve_workspace_size(rswr_plan_t plan, int32_t n_rec,

@@ -40,7 +40,8 @@ class _Desc(ctypes.Structure):
                 ("sub_lo", ctypes.c_void_p), ("sub_hi", ctypes.c_void_p),
                 ("span", ctypes.c_int32), ("span_mode", ctypes.c_int32),
                 ("beta", ctypes.c_double), ("dtype", ctypes.c_int32),
-                ("tile_threads", ctypes.c_int32), ("tile_per_thread", ctypes.c_int32)]
+                ("tile_threads", ctypes.c_int32), ("tile_per_thread", ctypes.c_int32),
+                ("no_fuse", ctypes.c_int32)]
 
 
 class _Info(ctypes.Structure):
@@ -50,7 +51,7 @@ class _Info(ctypes.Structure):
                 ("flux_ld", ctypes.c_int32), ("n_tiles", ctypes.c_int32),
                 ("tile_threads", ctypes.c_int32), ("tile_per_thread", ctypes.c_int32),
                 ("dx", ctypes.c_double), ("dt", ctypes.c_double),
-                ("lambda_", ctypes.c_double)]
+                ("lambda_", ctypes.c_double), ("fused", ctypes.c_int32)]
 
 
 def lib():
@@ -77,9 +78,10 @@ def lib():
     L.rswr_solve_adjoint.argtypes = [vp, vp, vp, vp, i64, vp, i32, vp, vp, vp, vp, vp, sz,
                                      vp]
     L.rswr_solve.argtypes = [vp, vp, vp, vp, i64, i64, vp, i32, vp, vp, sz, vp, vp]
+    L.rswr_span.argtypes = [vp, vp, vp, vp, i64, i32, vp, vp, vp]
     for name in ("rswr_plan", "rswr_plan_destroy", "rswr_plan_info", "rswr_plan_layout",
                  "rswr_plan_tiles",
-                 "rswr_predict", "rswr_select", "rswr_update",
+                 "rswr_predict", "rswr_select", "rswr_update", "rswr_span",
                  "rswr_solve_workspace_size", "rswr_solve", "rswr_checkpoint_size",
                  "rswr_adjoint_workspace_size", "rswr_solve_adjoint"):
         getattr(L, name).restype = ctypes.c_int
@@ -106,12 +108,14 @@ class Plan:
     intervals (Sec. 2.2 Eqs. (4)-(5), Sec. 3).  courant = a dt / dx with dt
     fixed by a_ref (default a); courant_frac = (num, den) makes the span rule
     of Eq. (10) exact in integers.  windows = (lo, hi) gives explicit windows.
+    tile = (threads, nodes per lane) picks a built kernel shape; fuse=False
+    keeps predict and update as separate launches in rswr_solve.
     """
 
     def __init__(self, n_points, n_sub, overlap, a=1.0, courant=0.9,
                  courant_frac=(9, 10), x_a=0.0, x_b=1.0, a_ref=0.0, span=0,
                  span_mode=FIXED, beta=0.1, dtype=torch.float64, windows=None,
-                 tile=None):
+                 tile=None, fuse=True):
         L = lib()
         d = _Desc()
         d.x_a, d.x_b, d.n_points = float(x_a), float(x_b), int(n_points)
@@ -130,6 +134,7 @@ class Plan:
         d.dtype = F64 if dtype == torch.float64 else F32
         if tile is not None:
             d.tile_threads, d.tile_per_thread = int(tile[0]), int(tile[1])
+        d.no_fuse = 0 if fuse else 1
         h = ctypes.c_void_p()
         _check(L.rswr_plan(ctypes.byref(d), ctypes.byref(h)), "rswr_plan")
         self._h = h
@@ -250,6 +255,24 @@ def rswr_update(plan, state_in, f_a, f_b, n0, flux, span=None, span_dev=None, ou
     return out
 
 
+def rswr_span(plan, state_in, f_a, f_b, n0, span=None, flux=None, out=None):
+    """One whole span (Sec. 2.6 loop body: predict, update, glue) of the
+    fixed span, from levels n0-1, n0 to n0+span-1, n0+span; one launch when
+    plan.info["fused"].  `flux` ([N-1, 2, flux_ld]) is optional for fused
+    plans (it then receives the input ends' predicted rows) and required for
+    the others when N > 1.  Returns the new state [2, M]."""
+    if out is None:
+        out = torch.empty_like(state_in)
+    span = plan.span if span is None else int(span)
+    fl = None if flux is None else _dev(flux, plan.dtype, plan.flux_numel, "flux")
+    _check(lib().rswr_span(plan.handle, _dev(state_in, plan.dtype, 2 * plan.M, "state_in"),
+                           _dev(f_a, plan.dtype, n0 + span + 1, "f_a"),
+                           _dev(f_b, plan.dtype, n0 + span + 1, "f_b"), int(n0), span, fl,
+                           _dev(out, plan.dtype, 2 * plan.M, "state_out"), _stream()),
+           "rswr_span")
+    return out
+
+
 def rswr_solve(plan, state, f_a, f_b, n_steps, n0=0, receivers=None, checkpoints=None,
                workspace=None, traces=None):
     """The span loop (Sec. 2.6).  `state` [2, M] is advanced in place.
@@ -364,4 +387,5 @@ class RSWRFunction(torch.autograd.Function):
 
 # Short names of the same calls.
 predict, select, update, solve = rswr_predict, rswr_select, rswr_update, rswr_solve
+span = rswr_span
 solve_adjoint = rswr_solve_adjoint

@@ -1,10 +1,11 @@
-"""Autotuner of the update kernel's tile shape.
+"""Autotuner of the span kernel's tile shape.
 
 For one problem (grid size, windows, overlap, span, dtype) every kernel shape
 built into librswr.so (rswr_kernel_shapes) that can hold the span is timed on
-the device: one update launch (one span over all windows) from a smooth state,
-repeated, with HIP events on the current stream.  The fastest shape wins; the
-result can be kept in a JSON cache keyed by device name and problem.
+the device: one whole span over all windows (rswr_span: one fused launch, or
+predict + update where the plan cannot fuse) from a smooth state, repeated,
+with HIP events on the current stream.  The fastest shape wins; the result
+can be kept in a JSON cache keyed by device name and problem.
 """
 import ctypes
 import json
@@ -13,7 +14,7 @@ import os
 import numpy as np
 import torch
 
-from . import Plan, RSWRError, lib, rswr_predict, rswr_update
+from . import Plan, RSWRError, lib, rswr_span
 
 
 def kernel_shapes():
@@ -31,8 +32,8 @@ def _key(n_points, n_sub, overlap, span, dtype):
     return f"{name}|{str(dtype)}|{n_points}|{n_sub}|{overlap}|{span}"
 
 
-def time_update(plan, reps=10, warmup=3):
-    """Average microseconds of one update launch of `plan`."""
+def time_span(plan, reps=10, warmup=3):
+    """Average microseconds of one span (rswr_span) of `plan`."""
     M = plan.M
     dev = "cuda"
     x = torch.linspace(0, 1, M, dtype=torch.float64, device=dev)
@@ -40,16 +41,16 @@ def time_update(plan, reps=10, warmup=3):
     n = plan.span + 1
     fa = torch.zeros(n + 1, dtype=plan.dtype, device=dev)
     fb = torch.zeros_like(fa)
-    flux = rswr_predict(plan, st, fa, fb, 0, plan.span)
+    flux = None if plan.info["fused"] else plan.flux_buffer(dev)
     out = torch.empty_like(st)
     for _ in range(warmup):
-        rswr_update(plan, st, fa, fb, 0, flux, span=plan.span, out=out)
+        rswr_span(plan, st, fa, fb, 0, flux=flux, out=out)
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     e0.record()
     for _ in range(reps):
-        rswr_update(plan, st, fa, fb, 0, flux, span=plan.span, out=out)
+        rswr_span(plan, st, fa, fb, 0, flux=flux, out=out)
     e1.record()
     torch.cuda.synchronize()
     return e0.elapsed_time(e1) * 1e3 / reps
@@ -74,7 +75,7 @@ def autotune(n_points, n_sub, overlap, dtype=torch.float32, span=0, reps=10,
                         **plan_kw)
         except RSWRError:
             continue  # shape cannot hold this span
-        times[(th, pt)] = time_update(plan, reps=reps)
+        times[(th, pt)] = time_span(plan, reps=reps)
     if not times:
         raise RuntimeError("no built kernel shape fits this problem")
     best = min(times, key=times.get)

@@ -2,6 +2,7 @@
 import os
 import subprocess
 import sys
+from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
@@ -16,24 +17,32 @@ FLAGS = [
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-command-line-argument",
 ]
-SOURCES = ["rswr_kernels.hip", "rswr_adjoint.hip", "rswr_host.cpp"]
+SOURCES = ["rswr_fused.hip", "rswr_kernels.hip", "rswr_adjoint.hip", "rswr_host.cpp"]
+
+
+def _compile(src, verbose):
+    obj = os.path.join(CSRC, os.path.splitext(src)[0] + ".o")
+    lang = ["-x", "hip"] if src.endswith(".hip") else []
+    cmd = [HIPCC, *FLAGS, *lang, "-c", os.path.join(CSRC, src), "-o", obj]
+    res = subprocess.run(cmd, capture_output=True, text=True)
+    err = "\n".join(l for l in res.stderr.splitlines()
+                    if "is not a recognized feature" not in l)
+    if res.returncode != 0:
+        raise RuntimeError(f"hipcc failed on {src}:\n{err}")
+    return obj, " ".join(cmd), err
 
 
 def build(verbose: bool = False) -> str:
+    # one hipcc per source, in parallel (the kernel files dominate)
+    jobs = int(os.environ.get("MAX_JOBS", "0")) or min(len(SOURCES), os.cpu_count() or 1)
+    with ThreadPoolExecutor(max_workers=max(1, jobs)) as ex:
+        results = list(ex.map(lambda src: _compile(src, verbose), SOURCES))
     objs = []
-    for src in SOURCES:
-        obj = os.path.join(CSRC, os.path.splitext(src)[0] + ".o")
-        lang = ["-x", "hip"] if src.endswith(".hip") else []
-        cmd = [HIPCC, *FLAGS, *lang, "-c", os.path.join(CSRC, src), "-o", obj]
+    for obj, cmd, err in results:
         if verbose:
-            print(" ".join(cmd), flush=True)
-        res = subprocess.run(cmd, capture_output=True, text=True)
-        err = "\n".join(l for l in res.stderr.splitlines()
-                        if "is not a recognized feature" not in l)
-        if res.returncode != 0:
-            raise RuntimeError(f"hipcc failed on {src}:\n{err}")
-        if verbose and err.strip():
-            print(err)
+            print(cmd, flush=True)
+            if err.strip():
+                print(err)
         objs.append(obj)
     tmp = LIB + ".tmp"
     cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs]

@@ -24,6 +24,33 @@ __device__ __forceinline__ uint32_t dpp32(uint32_t v) {
 constexpr int kWaveShr1 = 0x138;
 constexpr int kWaveShl1 = 0x130;
 
+// The same shifts with zero fill: the lane at the wave's end receives 0
+// (bound_ctrl), so every lane is written and no copy of the source is made.
+template <int CTRL>
+__device__ __forceinline__ uint32_t dpp32z(uint32_t v) {
+  return static_cast<uint32_t>(
+      __builtin_amdgcn_mov_dpp(static_cast<int>(v), CTRL, 0xf, 0xf, true));
+}
+template <int CTRL>
+__device__ __forceinline__ float lane_shift_z(float v) {
+  return __builtin_bit_cast(float, dpp32z<CTRL>(__builtin_bit_cast(uint32_t, v)));
+}
+template <int CTRL>
+__device__ __forceinline__ double lane_shift_z(double v) {
+  const uint64_t b = __builtin_bit_cast(uint64_t, v);
+  const uint64_t lo = dpp32z<CTRL>(static_cast<uint32_t>(b));
+  const uint64_t hi = dpp32z<CTRL>(static_cast<uint32_t>(b >> 32));
+  return __builtin_bit_cast(double, lo | (hi << 32));
+}
+
+// A wave-uniform value kept in a vector register, so an instruction may
+// combine it with a scalar operand (one scalar source per VALU instruction).
+template <typename T>
+__device__ __forceinline__ T in_vgpr(T v) {
+  asm("" : "+v"(v));
+  return v;
+}
+
 template <int CTRL>
 __device__ __forceinline__ float lane_shift(float v) {
   return __builtin_bit_cast(float, dpp32<CTRL>(__builtin_bit_cast(uint32_t, v)));
@@ -34,6 +61,25 @@ __device__ __forceinline__ double lane_shift(double v) {
   const uint64_t lo = dpp32<CTRL>(static_cast<uint32_t>(b));
   const uint64_t hi = dpp32<CTRL>(static_cast<uint32_t>(b >> 32));
   return __builtin_bit_cast(double, lo | (hi << 32));
+}
+
+// Value of lane l (wave-uniform l) in every lane: v_readlane, no LDS round
+// trip.
+__device__ __forceinline__ float rd_lane(float v, int l) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), l));
+}
+__device__ __forceinline__ double rd_lane(double v, int l) {
+  const uint64_t b = __builtin_bit_cast(uint64_t, v);
+  const uint64_t lo = static_cast<uint32_t>(
+      __builtin_amdgcn_readlane(static_cast<int>(static_cast<uint32_t>(b)), l));
+  const uint64_t hi = static_cast<uint32_t>(
+      __builtin_amdgcn_readlane(static_cast<int>(static_cast<uint32_t>(b >> 32)), l));
+  return __builtin_bit_cast(double, lo | (hi << 32));
+}
+// v with lane l's element replaced by the wave-uniform x.
+template <typename T>
+__device__ __forceinline__ T wr_lane(T x, int l, T v, int lane) {
+  return lane == l ? x : v;
 }
 
 // Second-order leapfrog for Eq. (1) at one node.
@@ -54,6 +100,18 @@ __device__ __forceinline__ int xcd_tile(int bid, int nb) {
 }
 
 __device__ __forceinline__ int pad32(int x) { return x + (x >> 5); }
+
+// LDS slot of tile node x in the staging buffer.  With an odd number of
+// nodes per lane, lane t's elements (stride MPT) already fall in distinct
+// banks, so the plain layout is conflict-free and every address is a
+// per-lane base plus a compile-time offset; even MPT pads one slot per 32.
+template <int MPT>
+__device__ __forceinline__ int lds_slot(int x) {
+  if constexpr (MPT % 2 == 1)
+    return x;
+  else
+    return pad32(x);
+}
 
 // Issue every load of a level before the first wait.  Regions fully inside
 // [0, M) read through a wave-uniform base pointer with 32-bit lane offsets;
@@ -86,30 +144,56 @@ __device__ __forceinline__ void load_level(const T* __restrict__ src, int64_t a,
 template <typename T, int NT, int MPT>
 __device__ __forceinline__ void transpose_in(const T (&tmp)[MPT], T* st, T (&v)[MPT]) {
 #pragma unroll
-  for (int it = 0; it < MPT; ++it) st[pad32(it * NT + static_cast<int>(threadIdx.x))] = tmp[it];
+  for (int it = 0; it < MPT; ++it)
+    st[lds_slot<MPT>(it * NT + static_cast<int>(threadIdx.x))] = tmp[it];
   __syncthreads();
 #pragma unroll
-  for (int e = 0; e < MPT; ++e) v[e] = st[pad32(static_cast<int>(threadIdx.x) * MPT + e)];
+  for (int e = 0; e < MPT; ++e) v[e] = st[lds_slot<MPT>(static_cast<int>(threadIdx.x) * MPT + e)];
   __syncthreads();
 }
 
+// Raw buffer stores (vector memory) through a resource that covers exactly
+// [base, base + bytes): the hardware drops every store whose offset falls
+// outside (a negative offset reads as a huge unsigned one).  Dword 3 of the
+// descriptor: 32-bit data format, as gfx9-family buffer accesses need.
+constexpr int kBufDword3 = 0x00020000;
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t range_rsrc(void* base, int bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(base, 0, bytes, kBufDword3);
+}
+__device__ __forceinline__ void range_store(float v, __amdgpu_buffer_rsrc_t r, int off) {
+  // the whole offset sits in the vector operand (no folded instruction
+  // offset), so the range check sees exactly this value
+  asm("" : "+v"(off));
+  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, off, 0, 0);
+}
+__device__ __forceinline__ void range_store(double v, __amdgpu_buffer_rsrc_t r, int off) {
+  typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+  asm("" : "+v"(off));
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, off, 0, 0);
+}
+
 // This lane's nodes -> LDS -> unit-stride stores of the stored range
-// [a + xlo, a + xhi] (offsets relative to the region start).
+// [a + xlo, a + xhi] (offsets relative to the region start).  Every row of
+// NT nodes stores unmasked through a resource covering exactly that range;
+// nodes outside it are dropped by the range check.
 template <typename T, int NT, int MPT>
 __device__ __forceinline__ void stage_out(T* __restrict__ dst, int64_t a, int xlo,
                                           int xhi, T* st, const T (&v)[MPT]) {
   const int tid = static_cast<int>(threadIdx.x);
 #pragma unroll
-  for (int e = 0; e < MPT; ++e) st[pad32(tid * MPT + e)] = v[e];
+  for (int e = 0; e < MPT; ++e) st[lds_slot<MPT>(tid * MPT + e)] = v[e];
   __syncthreads();
-  T tmp[MPT];
+  if (xlo <= xhi) {
+    const __amdgpu_buffer_rsrc_t r =
+        range_rsrc(dst + a + xlo, (xhi - xlo + 1) * static_cast<int>(sizeof(T)));
+    const int base = (tid - xlo) * static_cast<int>(sizeof(T));
+    T tmp[MPT];
 #pragma unroll
-  for (int it = 0; it < MPT; ++it) tmp[it] = st[pad32(it * NT + tid)];
-  T* __restrict__ b = dst + a;
+    for (int it = 0; it < MPT; ++it) tmp[it] = st[lds_slot<MPT>(it * NT + tid)];
 #pragma unroll
-  for (int it = 0; it < MPT; ++it) {
-    const int x = it * NT + tid;
-    if (x >= xlo && x <= xhi) b[x] = tmp[it];
+    for (int it = 0; it < MPT; ++it)
+      range_store(tmp[it], r, base + it * NT * static_cast<int>(sizeof(T)));
   }
   __syncthreads();
 }
@@ -138,6 +222,26 @@ __device__ __forceinline__ T pick(const T (&v)[MPT], int64_t d) {
 template <typename T>
 __device__ __forceinline__ T end_value(int mode, T ghost, T dir) {
   return (mode == kEndGhost) ? ghost : ((mode == kEndDirichlet) ? dir : T(0));
+}
+
+// One leapfrog step of this lane's nodes.
+// cur = level n, old = level n-1 on entry; old = level n+1 on exit.
+// GEN: element dl takes the left-input ghost as its left neighbour and
+// element d0 is the Dirichlet node 0 (offsets relative to this lane's first
+// node; out-of-range offsets match no element).
+template <typename T, int MPT, bool GEN>
+__device__ __forceinline__ void step_chunk(const T (&cur)[MPT], T (&old)[MPT],
+                                           T L, T R, T c2, T k, int dl, int d0,
+                                           T ghost, T da) {
+#pragma unroll
+  for (int e = 0; e < MPT; ++e) {
+    T ul = (e == 0) ? L : cur[e - 1];
+    const T ur = (e == MPT - 1) ? R : cur[e + 1];
+    if (GEN) ul = (e == dl) ? ghost : ul;
+    T v = leap(c2, k, ul, cur[e], ur, old[e]);
+    if (GEN) v = (e == d0) ? da : v;
+    old[e] = v;
+  }
 }
 
 // Kernel shapes (threads per work-group, nodes per lane) built into the

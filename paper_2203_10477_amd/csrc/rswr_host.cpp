@@ -72,6 +72,7 @@ struct rswr_plan_s {
   std::vector<Tile> tiles;
   std::vector<int32_t> idx;  // tile order of the launches: general ones first
   int32_t n_gen = 0;
+  bool fused = false;  // rswr_solve runs one fused launch per span
   std::mutex mu;
   std::map<int, DevTables> dev;
   std::vector<GraphEntry> graphs;
@@ -277,6 +278,31 @@ bool build_tiles(const rswr_plan_s& p, int TM, int S, std::vector<Tile>& out) {
 // nodes per lane that no longer fits without spilling.
 bool shape_fits_fp64(const rswr::Shape& sh) { return sh.per_thread <= 22; }
 
+// The fused span (predict folded into the update) takes the fixed span, at
+// most kMaxFusedSpan levels, inputs only at region ends (no interior left
+// input), and input ends o with the Dirichlet nodes outside [o-S, o+S]
+// (within S <= light-cone limit levels the sample at o sees no other end).
+bool fuse_eligible(const rswr_plan_s& p) {
+  if (p.mode != RSWR_SPAN_FIXED || p.S < 1 || p.S > rswr::kMaxFusedSpan) return false;
+  const int64_t TM = int64_t(p.threads) * p.per_thread;
+  auto frame_ok = [&](int64_t o, int32_t w) {
+    if (w < 0 || w >= p.N) return false;
+    if (o - p.S < 1 || o + p.S > p.M - 2) return false;
+    return o > p.lo[w] && o < p.hi[w];
+  };
+  for (const Tile& t : p.tiles) {
+    if (t.lin != rswr::kNoNode) return false;
+    if (t.lmode == rswr::kEndGhost &&
+        (t.fl != t.window - 1 || t.a != p.lo[t.window] || !frame_ok(t.a, t.window - 1)))
+      return false;
+    if (t.rmode == rswr::kEndGhost &&
+        (t.fr != t.window || t.a + TM - 1 != p.hi[t.window] ||
+         !frame_ok(t.a + TM - 1, t.window + 1)))
+      return false;
+  }
+  return true;
+}
+
 // Default kernel shape: the least padded work, penalising launches too small
 // to give every one of the 256 compute units a couple of work-groups.
 bool choose_shape(rswr_plan_s& p) {
@@ -376,6 +402,9 @@ rswr::UpdateArgs<T> update_args(const rswr_plan_s& p, const DevTables& d,
   a.c2 = T(c2);
   a.k = T(2.0 - 2.0 * c2);
   a.q = T(2.0 * p.dx);
+  a.r = T(1.0 / (2.0 * p.dx));
+  a.lo = d.lo;
+  a.hi = d.hi;
   return a;
 }
 
@@ -385,18 +414,20 @@ rswr::UpdateArgs<T> update_args(const rswr_plan_s& p, const DevTables& d,
 template <typename T>
 hipError_t launch_update_pair(const rswr_plan_s& p, rswr::UpdateArgs<T> a,
                               const int32_t* gen_idx, int32_t n_gen,
-                              const int32_t* fast_idx, int32_t n_fast, hipStream_t s) {
+                              const int32_t* fast_idx, int32_t n_fast, hipStream_t s,
+                              bool fused = false) {
+  auto launch = fused ? rswr::launch_fused<T> : rswr::launch_update<T>;
   if (n_gen > 0) {
     a.tile_idx = gen_idx;
     a.n_tiles = n_gen;
-    hipError_t e = rswr::launch_update<T>(a, p.threads, p.per_thread, true, s);
+    hipError_t e = launch(a, p.threads, p.per_thread, true, s);
     if (e != hipSuccess) return e;
   }
   if (n_fast > 0) {
     a.tile_idx = fast_idx;
     a.n_tiles = n_fast;
     a.rec_ptr = nullptr;
-    return rswr::launch_update<T>(a, p.threads, p.per_thread, false, s);
+    return launch(a, p.threads, p.per_thread, false, s);
   }
   return hipSuccess;
 }
@@ -472,10 +503,16 @@ rswr_status_t enqueue_solve(rswr_plan_s* p, const DevTables& d, void* state,
     const T* in = ck ? ck + k * st_elems : x;
     T* out = ck ? ck + (k + 1) * st_elems : y;
     T* const fl = ck ? ck_flux + k * fl_elems : flux;
-    rswr::PredictArgs<T> pa = predict_args<T>(*p, d, in, fa, fb, lev, S, fl);
-    RSWR_HIP(rswr::launch_predict<T>(pa, 2 * p->S_max + 1, s));
+    if (!p->fused) {
+      rswr::PredictArgs<T> pa = predict_args<T>(*p, d, in, fa, fb, lev, S, fl);
+      RSWR_HIP(rswr::launch_predict<T>(pa, 2 * p->S_max + 1, s));
+    }
     rswr::UpdateArgs<T> ua =
         update_args<T>(*p, d, in, fa, fb, lev, fl, nullptr, S, out);
+    if (p->fused) {
+      ua.flux = nullptr;
+      ua.flux_out = ck ? fl : nullptr;  // the adjoint reads the span's fluxes
+    }
     if (lists.rec_ptr) {
       ua.rec_ptr = lists.rec_ptr;
       ua.rec_node = lists.rec_node;
@@ -485,7 +522,7 @@ rswr_status_t enqueue_solve(rswr_plan_s* p, const DevTables& d, void* state,
       ua.trace_col0 = lev - n0;
     }
     RSWR_HIP(launch_update_pair<T>(*p, ua, lists.gen, lists.n_gen, lists.fast, lists.n_fast,
-                                   s));
+                                   s, p->fused));
     lev += S;
     std::swap(x, y);
   }
@@ -803,6 +840,7 @@ rswr_status_t rswr_plan(const rswr_desc_t* desc, rswr_plan_t* out) {
   p->n_gen = static_cast<int32_t>(p->idx.size());
   for (size_t t = 0; t < p->tiles.size(); ++t)
     if (!p->tiles[t].general) p->idx.push_back(static_cast<int32_t>(t));
+  p->fused = D.no_fuse == 0 && fuse_eligible(*p);
   *out = p;
   return RSWR_OK;
 }
@@ -844,6 +882,7 @@ rswr_status_t rswr_plan_info(rswr_plan_t p, rswr_plan_info_t* info) {
   info->dx = p->dx;
   info->dt = p->dt;
   info->lambda = p->lam;
+  info->fused = p->fused ? 1 : 0;
   return RSWR_OK;
 }
 
@@ -948,6 +987,45 @@ rswr_status_t rswr_update(rswr_plan_t p, const void* state_in, const void* f_a,
                                state_out),
         d->idx, p->n_gen, d->idx + p->n_gen, n_all - p->n_gen, s);
   if (e != hipSuccess) return hip_fail(e, "update launch");
+  return RSWR_OK;
+}
+
+rswr_status_t rswr_span(rswr_plan_t p, const void* state_in, const void* f_a, const void* f_b,
+                        int64_t n0, int32_t span, void* flux, void* state_out,
+                        void* stream) {
+  if (!p || !state_in || !f_a || !f_b || !state_out)
+    return fail(RSWR_ERR_INVALID_ARG, "null pointer");
+  if (!p->fused && !flux && p->N > 1)
+    return fail(RSWR_ERR_INVALID_ARG, "this plan predicts through `flux`: pass a buffer");
+  if (p->mode != RSWR_SPAN_FIXED)
+    return fail(RSWR_ERR_UNSUPPORTED, "rswr_span runs FIXED plans");
+  if (n0 < 0) return fail(RSWR_ERR_INVALID_ARG, "n0 must be >= 0");
+  if (state_in == state_out) return fail(RSWR_ERR_INVALID_ARG, "state_out aliases state_in");
+  if (span < 1 || span > p->S)
+    return fail(RSWR_ERR_SPAN, "span outside 1.." + std::to_string(p->S));
+  DevTables* d = nullptr;
+  rswr_status_t st = ensure_device(p, &d, nullptr);
+  if (st != RSWR_OK) return st;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int32_t n_all = static_cast<int32_t>(p->tiles.size());
+  auto run = [&](auto tag) -> hipError_t {
+    using T = decltype(tag);
+    if (!p->fused && p->N > 1) {
+      hipError_t e = rswr::launch_predict<T>(
+          predict_args<T>(*p, *d, state_in, f_a, f_b, n0, span, flux), 2 * p->S_max + 1, s);
+      if (e != hipSuccess) return e;
+    }
+    rswr::UpdateArgs<T> ua =
+        update_args<T>(*p, *d, state_in, f_a, f_b, n0, flux, nullptr, span, state_out);
+    if (p->fused) {
+      ua.flux = nullptr;
+      ua.flux_out = static_cast<T*>(flux);
+    }
+    return launch_update_pair<T>(*p, ua, d->idx, p->n_gen, d->idx + p->n_gen,
+                                 n_all - p->n_gen, s, p->fused);
+  };
+  const hipError_t e = p->dtype == RSWR_F64 ? run(double{}) : run(float{});
+  if (e != hipSuccess) return hip_fail(e, "span launch");
   return RSWR_OK;
 }
 

@@ -9,6 +9,9 @@ namespace rswr {
 // Largest span a kernel launch accepts (per-step boundary data is staged in
 // LDS arrays of this length).
 constexpr int kMaxSpan = 256;
+// Prediction frame of the fused span: 2 * kFrameHalf nodes, two per lane.
+constexpr int kFrameHalf = 64;
+constexpr int kMaxFusedSpan = kFrameHalf - 1;
 
 // Sentinel for "no left-input ghost in this tile".
 constexpr int64_t kNoNode = INT64_MIN;
@@ -67,9 +70,15 @@ struct UpdateArgs {
   const int64_t* rec_node;
   const int32_t* rec_id;
   T* traces;
+  // fused span only: window bounds (for the predicting neighbours) and the
+  // nullable destination of the predicted fluxes ([N-1][2][ld], the rows of
+  // the tiles' input ends)
+  const int64_t* lo;
+  const int64_t* hi;
+  T* flux_out;
   int64_t M, n0, trace_ld, trace_col0;
   int32_t n_tiles, span, ld, pad;
-  T c2, k, q;
+  T c2, k, q, r;
 };
 
 template <typename T>
@@ -128,6 +137,12 @@ hipError_t launch_predict(const PredictArgs<T>& a, int shmem_nodes,
 template <typename T>
 hipError_t launch_update(const UpdateArgs<T>& a, int threads, int per_thread,
                          bool general, hipStream_t s);
+// Fused span (rswr_fused.hip): predict folded into the update; needs
+// 1 <= span <= kMaxFusedSpan, inputs only at region ends and the Dirichlet
+// nodes more than span nodes from every input end.
+template <typename T>
+hipError_t launch_fused(const UpdateArgs<T>& a, int threads, int per_thread,
+                        bool general, hipStream_t s);
 template <typename T>
 hipError_t launch_select(const SelectArgs<T>& a, hipStream_t s);
 template <typename T>

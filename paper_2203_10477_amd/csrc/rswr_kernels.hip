@@ -89,25 +89,6 @@ __global__ __launch_bounds__(64) void k_predict(const PredictArgs<T> p) {
 // Loads and stores go through an LDS staging buffer so global accesses are
 // unit-stride across lanes.
 // ---------------------------------------------------------------------------
-// cur = level n, old = level n-1 on entry; old = level n+1 on exit.
-// GEN: element dl takes the left-input ghost as its left neighbour and
-// element d0 is the Dirichlet node 0 (offsets relative to this lane's first
-// node; out-of-range offsets match no element).
-template <typename T, int MPT, bool GEN>
-__device__ __forceinline__ void step_chunk(const T (&cur)[MPT], T (&old)[MPT],
-                                           T L, T R, T c2, T k, int dl, int d0,
-                                           T ghost, T da) {
-#pragma unroll
-  for (int e = 0; e < MPT; ++e) {
-    T ul = (e == 0) ? L : cur[e - 1];
-    const T ur = (e == MPT - 1) ? R : cur[e + 1];
-    if (GEN) ul = (e == dl) ? ghost : ul;
-    T v = leap(c2, k, ul, cur[e], ur, old[e]);
-    if (GEN) v = (e == d0) ? da : v;
-    old[e] = v;
-  }
-}
-
 template <typename T, int NT, int MPT>
 struct UpdateCtx {
   T (*edge)[2][NT / 64];

@@ -112,3 +112,53 @@ def test_compute_calls_need_a_gpu_tensor():
     st = torch.zeros(2, 1001, dtype=torch.float64)
     with pytest.raises(TypeError):
         rs.rswr_solve(plan, st, st[0], st[0], 10)
+
+
+def _fused_by_rule(plan):
+    """The fused-span rule from the plan's tiles and windows: fixed span
+    1..63, no window whose left input lies inside a region (those are the
+    general tiles of windows other than the first), and nodes 0 and M-1 more
+    than S nodes from every input end a tile uses."""
+    S, M = plan.span, plan.M
+    if plan.info["span"] < 1 or S > 63:
+        return False
+    for a, b, _, _, w, lm, rm, gen in plan.tiles():
+        if gen and w > 0:
+            return False
+        for o, mode in ((a, lm), (b, rm)):
+            if mode == 1 and not (o - S >= 1 and o + S <= M - 2):
+                return False
+    return True
+
+
+@pytest.mark.parametrize("args,kw", [
+    ((1001, 2, 20), {}),
+    ((1 << 24, 4096, 64), {"dtype": torch.float32}),
+    ((1 << 20, 64, 64), {}),
+    ((301, 20, 20), {}),
+    ((4097, 8, 64), {"tile": (128, 8)}),
+    ((20001, 16, 64), {"tile": (256, 16)}),
+    ((101, 2, 0), {"windows": ([0, 5], [30, 100])}),
+    ((2001, 2, 0), {"windows": ([0, 5], [30, 2000])}),
+    ((2001, 3, 0), {"windows": ([0, 400, 800], [700, 911, 2000]), "tile": (64, 8)}),
+    ((40001, 4, 256), {"span": 40}),
+    ((40001, 4, 256), {}),               # span 127 > 63: two launches
+])
+def test_fused_flag_follows_the_rule(args, kw):
+    plan = rs.Plan(*args, **kw)
+    assert plan.info["fused"] == int(_fused_by_rule(plan)), (args, kw)
+    off = rs.Plan(*args, fuse=False, **kw)
+    assert off.info["fused"] == 0
+
+
+def test_fused_flag_cases():
+    assert rs.Plan(1001, 2, 20).info["fused"] == 1
+    assert rs.Plan(1 << 24, 4096, 64, dtype=torch.float32).info["fused"] == 1
+    assert rs.Plan(1001, 2, 20, span_mode=rs.QUIET).info["fused"] == 0
+    # a tile starts at the second window's input end, node 5, within S of
+    # the Dirichlet node 0
+    narrow = rs.Plan(2001, 2, 0, windows=([0, 5], [30, 2000]))
+    assert narrow.span >= 5 and narrow.info["fused"] == 0
+    assert (narrow.tiles()[:, 0] == 5).any()
+    # with a narrow second window no tile uses that end
+    assert rs.Plan(101, 2, 0, windows=([0, 5], [30, 100])).info["fused"] == 1
