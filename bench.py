@@ -64,7 +64,7 @@ def cpu_baseline(prob, target_s):
     t0 = time.perf_counter()
     st, _, _ = oracle.rswr(lay, prob.lam, prob.dx, fa, fb, S, span=S, state=st)
     one = time.perf_counter() - t0
-    spans = max(1, min(40, int(target_s / max(one, 1e-3)) - 1))
+    spans = max(1, min(500, int(target_s / max(one, 1e-3)) - 1))
     t0 = time.perf_counter()
     oracle.rswr(lay, prob.lam, prob.dx, fa, fb, spans * S, span=S, state=st, n0=S)
     dt = time.perf_counter() - t0

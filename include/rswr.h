@@ -121,8 +121,7 @@ typedef struct {
   int32_t fused;            /* 1: rswr_solve runs each span as one launch, the
                                prediction of every input end carried by the
                                wave holding that end (fixed span S <= 63,
-                               no interior inputs, nodes 0 and M-1 more than
-                               S nodes from every input end); results are
+                               every input at a region end); results are
                                identical either way */
 } rswr_plan_info_t;
 

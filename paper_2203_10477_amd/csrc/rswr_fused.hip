@@ -13,8 +13,8 @@
 //
 // Over S levels the flux at o reads the state in [o-S, o+S] and nothing
 // else: the predicting window's input ends lie at least the light-cone
-// limit >= S nodes from o, and the host keeps nodes 0 and M-1 (Dirichlet)
-// out of that range.  So the frame runs the plain stencil everywhere; what
+// limit >= S nodes from o.  So the frame runs the plain stencil everywhere,
+// except at node 0 or M-1 (Dirichlet, Eq. (3)) where a frame holds one; what
 // lies outside [o-S, o+S] (the state mirrored at the window's ends, the
 // frame's cut ends, which reach o +- 1 only after kFrameHalf - 1 >= S
 // levels) cannot reach the sample in time, and F[s] equals the
@@ -35,8 +35,10 @@ struct FusedCtx {
   int64_t base;  // this lane's first node
   int d0, rb, re, lane, wv;
   bool gen;
-  bool dirL, dirR;  // this wave's lane 0 / lane 63 borders a Dirichlet node
-  bool keep;        // the caller keeps the predicted fluxes
+  bool dirL, dirR;    // this wave's lane 0 / lane 63 borders a Dirichlet node
+  bool fdirL, fdirR;  // this wave's left frame holds node 0 / right frame node M-1
+  bool fmL[2], fmR[2];  // which of this lane's frame elements is that node
+  bool keep;          // the caller keeps the predicted fluxes
 };
 
 // Frame around output node o of window w: lane l holds nodes
@@ -70,6 +72,18 @@ __device__ __forceinline__ T frame_step(const T (&cur)[2], T (&old)[2], T c2, T 
   return f;
 }
 
+// A frame of window 0 may hold node 0, one of window N-1 node M-1: those
+// nodes take the Dirichlet value of the new level (Eq. (3)) instead of the
+// stencil.  `dir` is wave-uniform; `d` is the value, `m` marks the element.
+template <typename T>
+__device__ __forceinline__ void frame_dirichlet(bool dir, const bool (&m)[2], T d,
+                                                T (&lvl)[2]) {
+  if (dir) {
+    lvl[0] = m[0] ? d : lvl[0];
+    lvl[1] = m[1] ? d : lvl[1];
+  }
+}
+
 // One step of the tile (cur = level n, old = level n-1 on entry, old = level
 // n+1 on exit) and of the frames this wave carries (HL: the left input,
 // HR: the right input).  fl / fr collect F[s] in lane s when the caller
@@ -88,11 +102,19 @@ __device__ __forceinline__ void fused_step(const UpdateArgs<T>& p,
   T R = lane_shift_z<kWaveShl1>(cur[0]);
   if constexpr (HL) {
     const T F = frame_step(lc, lo, p.c2, p.k, p.r);
+    if (c.fdirL) {
+      const T d = rd_lane(c.vA, s + 1);
+      frame_dirichlet(true, c.fmL, d, lo);
+    }
     if (c.keep) fl = wr_lane(F, s, fl, c.lane);
     L = (c.lane == 0) ? fma_(c.nq, F, cur[1]) : L;
   }
   if constexpr (HR) {
     const T F = frame_step(rc, ro, p.c2, p.k, p.r);
+    if (c.fdirR) {
+      const T d = rd_lane(c.vB, s + 1);
+      frame_dirichlet(true, c.fmR, d, ro);
+    }
     if (c.keep) fr = wr_lane(F, s, fr, c.lane);
     R = (c.lane == 63) ? fma_(c.pq, F, cur[MPT - 2]) : R;
   }
@@ -188,6 +210,19 @@ __global__ __launch_bounds__(NT) void k_fused(const UpdateArgs<T> p) {
   const bool dirL = tl.lmode == kEndDirichlet, dirR = tl.rmode == kEndDirichlet;
   c.dirL = dirL && c.wv == 0;
   c.dirR = dirR && c.wv == NW - 1;
+  // frames around the input ends (left: o = a, right: o = a + TM - 1); a
+  // frame spans [o - kFrameHalf, o + kFrameHalf - 1]
+  const int64_t oL = tl.a, oR = tl.a + TM - 1;
+  const bool fA = tl.lmode == kEndGhost && tl.window == 1 && oL - kFrameHalf <= 0;
+  const bool fB = tl.rmode == kEndGhost && oR + kFrameHalf - 1 >= p.M - 1 &&
+                  p.hi[tl.window + 1] == p.M - 1;
+  c.fdirL = fA && c.wv == 0;
+  c.fdirR = fB && c.wv == NW - 1;
+#pragma unroll
+  for (int e = 0; e < 2; ++e) {
+    c.fmL[e] = oL - kFrameHalf + 2 * c.lane + e == 0;
+    c.fmR[e] = oR - kFrameHalf + 2 * c.lane + e == p.M - 1;
+  }
   c.keep = p.flux_out != nullptr;
   c.nq = in_vgpr(-p.q);
   c.pq = in_vgpr(p.q);
@@ -195,8 +230,8 @@ __global__ __launch_bounds__(NT) void k_fused(const UpdateArgs<T> p) {
     // node 0 / M-1 at level n0 (from the state) and n0+1.. (from f_A, f_B)
     const int l = c.lane;
     T a = T(0), b = T(0);
-    if ((GEN || dirL) && l <= S) a = (l == 0) ? p.state_in[p.M] : p.fa[p.n0 + l];
-    if ((GEN || dirR) && l <= S) b = (l == 0) ? p.state_in[2 * p.M - 1] : p.fb[p.n0 + l];
+    if ((GEN || dirL || fA) && l <= S) a = (l == 0) ? p.state_in[p.M] : p.fa[p.n0 + l];
+    if ((GEN || dirR || fB) && l <= S) b = (l == 0) ? p.state_in[2 * p.M - 1] : p.fb[p.n0 + l];
     c.vA = a;
     c.vB = b;
   }

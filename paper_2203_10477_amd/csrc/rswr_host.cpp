@@ -279,15 +279,13 @@ bool build_tiles(const rswr_plan_s& p, int TM, int S, std::vector<Tile>& out) {
 bool shape_fits_fp64(const rswr::Shape& sh) { return sh.per_thread <= 22; }
 
 // The fused span (predict folded into the update) takes the fixed span, at
-// most kMaxFusedSpan levels, inputs only at region ends (no interior left
-// input), and input ends o with the Dirichlet nodes outside [o-S, o+S]
-// (within S <= light-cone limit levels the sample at o sees no other end).
+// most kMaxFusedSpan levels, and inputs only at region ends (no interior
+// left input).
 bool fuse_eligible(const rswr_plan_s& p) {
   if (p.mode != RSWR_SPAN_FIXED || p.S < 1 || p.S > rswr::kMaxFusedSpan) return false;
   const int64_t TM = int64_t(p.threads) * p.per_thread;
   auto frame_ok = [&](int64_t o, int32_t w) {
     if (w < 0 || w >= p.N) return false;
-    if (o - p.S < 1 || o + p.S > p.M - 2) return false;
     return o > p.lo[w] && o < p.hi[w];
   };
   for (const Tile& t : p.tiles) {

@@ -138,8 +138,7 @@ template <typename T>
 hipError_t launch_update(const UpdateArgs<T>& a, int threads, int per_thread,
                          bool general, hipStream_t s);
 // Fused span (rswr_fused.hip): predict folded into the update; needs
-// 1 <= span <= kMaxFusedSpan, inputs only at region ends and the Dirichlet
-// nodes more than span nodes from every input end.
+// 1 <= span <= kMaxFusedSpan and inputs only at region ends.
 template <typename T>
 hipError_t launch_fused(const UpdateArgs<T>& a, int threads, int per_thread,
                         bool general, hipStream_t s);

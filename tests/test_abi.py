@@ -115,19 +115,14 @@ def test_compute_calls_need_a_gpu_tensor():
 
 
 def _fused_by_rule(plan):
-    """The fused-span rule from the plan's tiles and windows: fixed span
-    1..63, no window whose left input lies inside a region (those are the
-    general tiles of windows other than the first), and nodes 0 and M-1 more
-    than S nodes from every input end a tile uses."""
-    S, M = plan.span, plan.M
-    if plan.info["span"] < 1 or S > 63:
+    """The fused-span rule from the plan's tiles: fixed span 1..63 and no
+    window whose left input lies inside a region (those are the general
+    tiles of windows other than the first)."""
+    if plan.info["span"] < 1 or plan.span > 63:
         return False
-    for a, b, _, _, w, lm, rm, gen in plan.tiles():
+    for _, _, _, _, w, _, _, gen in plan.tiles():
         if gen and w > 0:
             return False
-        for o, mode in ((a, lm), (b, rm)):
-            if mode == 1 and not (o - S >= 1 and o + S <= M - 2):
-                return False
     return True
 
 
@@ -155,10 +150,12 @@ def test_fused_flag_cases():
     assert rs.Plan(1001, 2, 20).info["fused"] == 1
     assert rs.Plan(1 << 24, 4096, 64, dtype=torch.float32).info["fused"] == 1
     assert rs.Plan(1001, 2, 20, span_mode=rs.QUIET).info["fused"] == 0
-    # a tile starts at the second window's input end, node 5, within S of
-    # the Dirichlet node 0
-    narrow = rs.Plan(2001, 2, 0, windows=([0, 5], [30, 2000]))
-    assert narrow.span >= 5 and narrow.info["fused"] == 0
-    assert (narrow.tiles()[:, 0] == 5).any()
-    # with a narrow second window no tile uses that end
-    assert rs.Plan(101, 2, 0, windows=([0, 5], [30, 100])).info["fused"] == 1
+    # a tile starts at the second window's input end, node 5: its frame
+    # holds the Dirichlet node 0
+    near = rs.Plan(2001, 2, 0, windows=([0, 5], [30, 2000]))
+    assert near.span >= 5 and near.info["fused"] == 1
+    assert (near.tiles()[:, 0] == 5).any()
+    # an interior left input (a general tile of a narrow window) keeps two
+    # launches
+    gen = rs.Plan(301, 20, 20)
+    assert any(g and w > 0 for *_, w, _, _, g in gen.tiles()) == (gen.info["fused"] == 0)

@@ -67,6 +67,11 @@ FUSE_CASES = [
     (2001, 3, 0, ([0, 400, 800], [700, 911, 2000]), (64, 8), 150, 0, 0),  # one wave, S 61
     (2501, 3, 0, ([0, 400, 1300], [700, 1423, 2500]), (128, 8), 150, 0, 50),  # two waves
     (4097, 8, 64, None, (64, 33), 100, 0, 63),      # the largest fused span
+    # frames holding the Dirichlet nodes: node 0 in the frame of window 1's
+    # left input, node M-1 in the frame of its right input
+    (2001, 3, 0, ([0, 5, 1970], [30, 1995, 2000]), (64, 8), 160, 0, 0),
+    (2001, 3, 0, ([0, 5, 1970], [30, 1995, 2000]), (128, 8), 120, 3, 0),
+    (2001, 2, 0, ([0, 5], [30, 2000]), None, 140, 0, 0),
 ]
 
 
