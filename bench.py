@@ -11,8 +11,12 @@ with a device copy and runs the recorded graph of all 572 spans.
 
 Prints one JSON line: throughput in grid-point updates per second (GLUPS,
 M * n_steps / time), the roofline of the dominant kernel (the fused span
-kernel, timed alone with HIP events on the stream it runs on), and the CPU
-oracle timed on a bounded sample of the same workload.
+kernel: its average duration inside the timed region, from HIP events around
+each solve on the stream it runs on), and the CPU oracle timed on a bounded
+sample of the same workload.  Beside it, in the same line: the batched form
+(512 problems of uneven size in one recorded graph) and the adjoint form
+(forward with span checkpoints plus the backward sweep, FP64), each against
+the plain single-problem solve.
 """
 import argparse
 import hashlib
@@ -76,6 +80,104 @@ def cpu_baseline(prob, target_s):
                       f"spans of {S} steps after one warm-up span; {dt:.1f} s"}
 
 
+def timed(fn, reps):
+    """Average milliseconds of fn() over reps runs after one warm-up, with
+    HIP events on the current stream."""
+    import torch
+    fn()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def batched_section(reps):
+    """The batched form: 512 problems (2^12..2^18 nodes, 4 to 256 windows,
+    overlap 32-128, a in [0.5, 2], 4096 steps, Gaussian pulses), FP32, one
+    recorded graph per solve, tile shapes autotuned per size class."""
+    import torch
+    import paper_2203_10477_amd as rs
+    import workloads
+    from paper_2203_10477_amd.autotune import autotune_batch, batch_plans
+    probs, clamped = workloads.config3()
+    t0 = time.perf_counter()
+    tiles, spans, report = autotune_batch(probs)
+    tune_s = time.perf_counter() - t0
+    plans = batch_plans(probs, torch.float32, tiles=tiles, spans=spans)
+    b = rs.Batch(plans)
+    st = [torch.zeros(2, p.M, dtype=torch.float32, device="cuda") for p in plans]
+    fa = [torch.as_tensor(q.fa, dtype=torch.float32, device="cuda") for q in probs]
+    fb = [torch.as_tensor(q.fb, dtype=torch.float32, device="cuda") for q in probs]
+    ns = [q.n_steps for q in probs]
+    ws = torch.empty(b.workspace_bytes(), dtype=torch.uint8, device="cuda")
+
+    def run():
+        for s in st:
+            s.zero_()
+        rs.rswr_batch_solve(b, st, fa, fb, ns, ws)
+
+    zero_ms = timed(lambda: [s.zero_() for s in st], reps)
+    ms = timed(run, reps) - zero_ms
+    upd = sum(q.M * q.n_steps for q in probs)
+    nbytes = 0
+    for p, q in zip(plans, probs):
+        lo, hi, _, _ = p.layout()
+        K = -(-q.n_steps // p.span)
+        nbytes += 4 * K * (2 * int((hi - lo + 1).sum()) + 2 * p.M)
+    return {"workload": "512 FP32 problems, 2^12..2^18 nodes (log-uniform), 4..256 windows, "
+                        "overlap 32-128, a in [0.5,2], 4096 steps, Gaussian pulses",
+            "value": round(upd / (ms * 1e-3) / 1e9, 2), "unit": "GLUPS", "ms": round(ms, 3),
+            "hbm_frac": round(nbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+            "algorithmic_bytes": nbytes, "nodes": sum(q.M for q in probs),
+            "rounds": max(-(-q.n_steps // s) for q, s in zip(probs, spans)),
+            "windows_clamped": clamped, "autotune_s": round(tune_s, 1),
+            "shapes": {str(c): f"{v[0][0]}x{v[0][1]}" for c, v in report.items()}}
+
+
+def adjoint_section(reps):
+    """The adjoint form: 2^18 nodes, 128 windows, overlap 64, FP64, 8192 steps,
+    16 receivers; the forward solve keeping span checkpoints, then the
+    backward sweep giving dJ/df_A and dJ/da; against the plain FP64 solve of
+    the same problem."""
+    import numpy as np
+    import torch
+    import paper_2203_10477_amd as rs
+    import workloads
+    prob = workloads.config4()
+    plan = rs.Plan(prob.M, prob.N, prob.P, dtype=torch.float64)
+    fa_np, fb_np = prob.sources()
+    fa = torch.as_tensor(fa_np, device="cuda")
+    fb = torch.as_tensor(fb_np, device="cuda")
+    st = torch.zeros(2, prob.M, dtype=torch.float64, device="cuda")
+    n = prob.n_steps
+    rec = prob.rec
+    ws = torch.empty(plan.workspace_bytes(len(rec)), dtype=torch.uint8, device="cuda")
+    ck = plan.checkpoint_buffer(n)
+    g = np.random.default_rng(7)
+    gtr = torch.as_tensor(g.standard_normal((len(rec), n)), device="cuda")
+
+    plain_ms = timed(lambda: (st.zero_(), rs.rswr_solve(plan, st, fa, fb, n, workspace=ws)),
+                     reps)
+    fwd_ms = timed(lambda: (st.zero_(), rs.rswr_solve(plan, st, fa, fb, n, receivers=rec,
+                                                      checkpoints=ck, workspace=ws)), reps)
+    adj_ms = timed(lambda: rs.rswr_solve_adjoint(plan, ck, fa, fb, n, rec, gtr), reps)
+    zero_ms = timed(lambda: st.zero_(), reps)
+    upd = prob.M * n / 1e9
+    return {"workload": f"{prob.M} nodes, {prob.N} windows, overlap {prob.P}, span "
+                        f"{plan.span}, {n} steps, FP64, {len(rec)} receivers",
+            "plain_fp64_glups": round(upd / ((plain_ms - zero_ms) * 1e-3), 2),
+            "forward_with_checkpoints_glups": round(upd / ((fwd_ms - zero_ms) * 1e-3), 2),
+            "adjoint_sweep_glups": round(upd / (adj_ms * 1e-3), 2),
+            "forward_plus_adjoint_glups": round(upd / ((fwd_ms - zero_ms + adj_ms) * 1e-3), 2),
+            "ms": {"plain": round(plain_ms - zero_ms, 3), "forward": round(fwd_ms - zero_ms, 3),
+                   "adjoint": round(adj_ms, 3)},
+            "checkpoint_bytes": ck.numel() * 8}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -84,6 +186,8 @@ def main():
     ap.add_argument("--kernel-reps", type=int, default=40)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-forms", action="store_true",
+                    help="skip the batched and adjoint sections")
     ap.add_argument("--tile", default="", help="threads x nodes-per-lane, e.g. 320x13 "
                     "(default: autotuned)")
     args = ap.parse_args()
@@ -202,6 +306,10 @@ def main():
                  "hbm_frac_whole_step": round(nbytes * n_spans / (ms_step * 1e-3)
                                               / 1e9 / HBM_PEAK_GBS, 4)},
     }
+    if not args.no_forms:
+        line["batched"] = batched_section(max(1, args.steps))
+        line["batched"]["vs_plain"] = round(line["batched"]["value"] / glups, 4)
+        line["adjoint"] = adjoint_section(max(1, args.steps))
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(prob, args.cpu_seconds)
     print(json.dumps(line), flush=True)

@@ -53,6 +53,7 @@ extern "C" {
 #endif
 
 typedef struct rswr_plan_s* rswr_plan_t;
+typedef struct rswr_batch_s* rswr_batch_t;
 
 typedef enum {
   RSWR_OK = 0,
@@ -239,6 +240,37 @@ rswr_status_t rswr_solve_adjoint(rswr_plan_t plan, const void* checkpoints,
                                  void* grad_f_a, void* grad_f_b,
                                  double* grad_lambda, void* workspace,
                                  size_t ws_bytes, void* stream);
+
+/* ---- Batched solve -------------------------------------------------------
+ * Many independent problems (each with its own grid, windows, wave speed,
+ * span, sources and length) advanced by the redo loop of Sec. 2.6 in one
+ * recorded graph: round r runs span r of every problem that has one left,
+ * one persistent launch per kernel shape walking all those problems' tiles.
+ * Results are identical to rswr_solve of each problem alone (n0 = 0, no
+ * receivers or checkpoints). */
+
+/* (host) Groups n plans of one dtype.  Every plan must run the fused span
+ * (rswr_plan_info_t.fused = 1; else UNSUPPORTED) and must outlive the batch;
+ * each keeps its own kernel shape and span.  Errors: INVALID_ARG,
+ * UNSUPPORTED, NOMEM. */
+rswr_status_t rswr_batch_plan(const rswr_plan_t* plans, int32_t n,
+                              rswr_batch_t* out);
+rswr_status_t rswr_batch_destroy(rswr_batch_t batch);
+/* Bytes of device workspace rswr_batch_solve needs: a second state buffer
+ * per problem plus the launch tables. */
+rswr_status_t rswr_batch_workspace_size(rswr_batch_t batch, size_t* bytes);
+/* Advances problem i by n_steps[i] levels from level 0: states[i] (device,
+ * [2][M_i], levels -1 and 0 on entry) is overwritten with levels
+ * n_steps[i]-1 and n_steps[i]; f_a[i], f_b[i] (device, n_steps[i]+1
+ * entries) are its boundary sources.  `states`, `f_a`, `f_b` and `n_steps`
+ * are host arrays of n entries.  Calls with the same pointers and lengths
+ * replay one recorded graph; the tables in the workspace are rewritten on
+ * every call.  Problems must not share state buffers.  Errors: INVALID_ARG,
+ * NOMEM (workspace too small), HIP. */
+rswr_status_t rswr_batch_solve(rswr_batch_t batch, void* const* states,
+                               const void* const* f_a, const void* const* f_b,
+                               const int64_t* n_steps, void* workspace,
+                               size_t ws_bytes, void* stream);
 
 const char* rswr_status_string(rswr_status_t status);
 const char* rswr_last_error(void);

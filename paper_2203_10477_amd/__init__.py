@@ -79,11 +79,16 @@ def lib():
                                      vp]
     L.rswr_solve.argtypes = [vp, vp, vp, vp, i64, i64, vp, i32, vp, vp, sz, vp, vp]
     L.rswr_span.argtypes = [vp, vp, vp, vp, i64, i32, vp, vp, vp]
+    L.rswr_batch_plan.argtypes = [vp, i32, ctypes.POINTER(vp)]
+    L.rswr_batch_destroy.argtypes = [vp]
+    L.rswr_batch_workspace_size.argtypes = [vp, ctypes.POINTER(sz)]
+    L.rswr_batch_solve.argtypes = [vp, vp, vp, vp, vp, vp, sz, vp]
     for name in ("rswr_plan", "rswr_plan_destroy", "rswr_plan_info", "rswr_plan_layout",
                  "rswr_plan_tiles",
                  "rswr_predict", "rswr_select", "rswr_update", "rswr_span",
                  "rswr_solve_workspace_size", "rswr_solve", "rswr_checkpoint_size",
-                 "rswr_adjoint_workspace_size", "rswr_solve_adjoint"):
+                 "rswr_adjoint_workspace_size", "rswr_solve_adjoint", "rswr_batch_plan",
+                 "rswr_batch_destroy", "rswr_batch_workspace_size", "rswr_batch_solve"):
         getattr(L, name).restype = ctypes.c_int
     L.rswr_status_string.argtypes = [ctypes.c_int]
     L.rswr_status_string.restype = ctypes.c_char_p
@@ -385,7 +390,57 @@ class RSWRFunction(torch.autograd.Function):
         return ga, grad_a, None
 
 
+class Batch:
+    """Many fused-span plans of one dtype solved together (rswr_batch_plan).
+    The plans are kept alive by this object."""
+
+    def __init__(self, plans):
+        self.plans = list(plans)
+        arr = (ctypes.c_void_p * max(len(self.plans), 1))(*[p.handle.value for p in self.plans])
+        h = ctypes.c_void_p()
+        _check(lib().rswr_batch_plan(arr, len(self.plans), ctypes.byref(h)), "rswr_batch_plan")
+        self._h = h
+        self.dtype = self.plans[0].dtype if self.plans else torch.float64
+
+    @property
+    def handle(self):
+        return self._h
+
+    def workspace_bytes(self):
+        b = ctypes.c_size_t()
+        _check(lib().rswr_batch_workspace_size(self._h, ctypes.byref(b)),
+               "rswr_batch_workspace_size")
+        return b.value
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and _lib is not None:
+            _lib.rswr_batch_destroy(h)
+            self._h = None
+
+
+def rswr_batch_solve(batch, states, f_a, f_b, n_steps, workspace=None):
+    """Advance problem i of `batch` by n_steps[i] levels from level 0 (states
+    [2, M_i] in place), all problems in one recorded graph."""
+    n = len(batch.plans)
+    if not (len(states) == len(f_a) == len(f_b) == len(n_steps) == n):
+        raise ValueError("one state, f_a, f_b and n_steps per problem")
+    if workspace is None:
+        workspace = torch.empty(batch.workspace_bytes(), dtype=torch.uint8,
+                                device=states[0].device)
+    ptr = lambda xs: (ctypes.c_void_p * n)(*[x.value for x in xs])
+    st = [_dev(s, p.dtype, 2 * p.M, "state") for s, p in zip(states, batch.plans)]
+    fa = [_dev(a, p.dtype, int(k) + 1, "f_a") for a, p, k in zip(f_a, batch.plans, n_steps)]
+    fb = [_dev(b, p.dtype, int(k) + 1, "f_b") for b, p, k in zip(f_b, batch.plans, n_steps)]
+    ns = np.ascontiguousarray(np.asarray(n_steps, np.int64))
+    _check(lib().rswr_batch_solve(batch.handle, ptr(st), ptr(fa), ptr(fb), ns.ctypes.data,
+                                  ctypes.c_void_p(workspace.data_ptr()), workspace.numel(),
+                                  _stream()), "rswr_batch_solve")
+    return states
+
+
 # Short names of the same calls.
 predict, select, update, solve = rswr_predict, rswr_select, rswr_update, rswr_solve
 span = rswr_span
+batch_solve = rswr_batch_solve
 solve_adjoint = rswr_solve_adjoint

@@ -86,3 +86,120 @@ def autotune(n_points, n_sub, overlap, dtype=torch.float32, span=0, reps=10,
         with open(cache, "w") as f:
             json.dump(table, f, indent=1)
     return best, times
+
+
+def _plan_for(prob, dtype, tile, span=0):
+    return Plan(prob.M, prob.N, prob.P, a=prob.a, a_ref=prob.a_ref, courant=prob.courant,
+                courant_frac=prob.courant_frac, x_a=prob.x_a, x_b=prob.x_b, span=span,
+                dtype=dtype, tile=tile)
+
+
+def batch_span(prob, dtype):
+    """Fixed span of a batched problem: the default rule (light-cone limit and
+    Eq. (10)), capped at the fused kernel's 63 levels."""
+    return min(_plan_for(prob, dtype, None).span, 63)
+
+
+def size_class(prob):
+    """Problems with windows of similar width share a tile shape."""
+    core = (prob.M - 1) / max(prob.N, 1)
+    return int(np.floor(np.log2(core + prob.P + 1)))
+
+
+def _candidates(prob, dtype, span):
+    """Shapes whose plan runs the fused span, with the nodes the tiles
+    compute per span (threads * nodes per lane * tiles)."""
+    out = {}
+    for th, pt, fp64_ok in kernel_shapes():
+        if dtype == torch.float64 and not fp64_ok:
+            continue
+        try:
+            p = _plan_for(prob, dtype, (th, pt), span)
+        except RSWRError:
+            continue
+        if p.info["fused"]:
+            out[(th, pt)] = p.info["n_tiles"] * th * pt
+    return out
+
+
+def time_batch(plans, probs, n_steps, reps=3):
+    """Microseconds of one rswr_batch_solve of `plans` (n_steps each)."""
+    from . import Batch, rswr_batch_solve
+    b = Batch(plans)
+    dev = "cuda"
+    st = [torch.zeros(2, p.M, dtype=p.dtype, device=dev) for p in plans]
+    fa = [torch.as_tensor(q.fa[:n_steps + 1], dtype=p.dtype, device=dev)
+          for q, p in zip(probs, plans)]
+    fb = [torch.zeros(n_steps + 1, dtype=p.dtype, device=dev) for p in plans]
+    ns = [n_steps] * len(plans)
+    ws = torch.empty(b.workspace_bytes(), dtype=torch.uint8, device=dev)
+    rswr_batch_solve(b, st, fa, fb, ns, ws)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        rswr_batch_solve(b, st, fa, fb, ns, ws)
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) * 1e3 / reps
+
+
+def autotune_batch(probs, dtype=torch.float32, sample=16, spans_timed=4, slack=1.5,
+                   measure=True):
+    """Tile shape per size class for a batch of problems.
+
+    Every problem gets the span batch_span().  Within a size class, the shapes
+    that run the fused span for every problem of a sample, and whose computed
+    nodes stay within `slack` times the least, are timed as one batched solve
+    of the sample over `spans_timed` spans; the fastest wins (measure=False:
+    the least computed nodes wins).  Returns (tiles per problem, spans per
+    problem, {class: (shape, {shape: microseconds})})."""
+    spans = [batch_span(p, dtype) for p in probs]
+    classes = {}
+    for i, p in enumerate(probs):
+        classes.setdefault(size_class(p), []).append(i)
+    tiles = [None] * len(probs)
+    report = {}
+    g = np.random.default_rng(0)
+    for c, idx in sorted(classes.items()):
+        pick = idx if len(idx) <= sample else sorted(g.choice(idx, sample, replace=False))
+        work = None
+        for i in pick:
+            cand = _candidates(probs[i], dtype, spans[i])
+            work = cand if work is None else {k: work[k] + v for k, v in cand.items() if k in work}
+        if not work:
+            raise RuntimeError(f"no fused shape fits size class {c}")
+        least = min(work.values())
+        shortlist = sorted(k for k, v in work.items() if v <= slack * least)
+        times = {}
+        if measure and len(shortlist) > 1:
+            n_steps = spans_timed * max(spans[i] for i in pick)
+            for sh in shortlist:
+                plans = [_plan_for(probs[i], dtype, sh, spans[i]) for i in pick]
+                times[sh] = time_batch(plans, [probs[i] for i in pick], n_steps)
+            best = min(times, key=times.get)
+        else:
+            best = min(shortlist, key=lambda k: work[k])
+        report[c] = (best, times)
+        for i in idx:
+            tiles[i] = best
+    # a shape chosen for the sample may not fuse every problem of its class
+    for i, p in enumerate(probs):
+        if not _plan_for(p, dtype, tiles[i], spans[i]).info["fused"]:
+            cand = _candidates(p, dtype, spans[i])
+            tiles[i] = min(cand, key=cand.get)
+    return tiles, spans, report
+
+
+def batch_plans(probs, dtype=torch.float32, tiles=None, spans=None):
+    """Plans of a batch: the given (or least-work) tile shapes and spans."""
+    spans = spans or [batch_span(p, dtype) for p in probs]
+    out = []
+    for i, p in enumerate(probs):
+        tile = tiles[i] if tiles else None
+        if tile is None:
+            cand = _candidates(p, dtype, spans[i])
+            tile = min(cand, key=cand.get)
+        out.append(_plan_for(p, dtype, tile, spans[i]))
+    return out

@@ -17,7 +17,8 @@ FLAGS = [
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-command-line-argument",
 ]
-SOURCES = ["rswr_fused.hip", "rswr_kernels.hip", "rswr_adjoint.hip", "rswr_host.cpp"]
+SOURCES = ["rswr_fused.hip", "rswr_batch.hip", "rswr_kernels.hip", "rswr_adjoint.hip",
+           "rswr_host.cpp"]
 
 
 def _compile(src, verbose):

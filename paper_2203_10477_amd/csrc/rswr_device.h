@@ -247,7 +247,10 @@ __device__ __forceinline__ void step_chunk(const T (&cur)[MPT], T (&old)[MPT],
 // Kernel shapes (threads per work-group, nodes per lane) built into the
 // library; the update and adjoint launchers dispatch over this list.
 #define RSWR_SHAPES(X) \
+  X(64, 2)             \
+  X(64, 4)             \
   X(64, 8)             \
+  X(64, 16)            \
   X(64, 33)            \
   X(64, 65)            \
   X(128, 8)            \

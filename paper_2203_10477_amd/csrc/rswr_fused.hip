@@ -1,292 +1,21 @@
-// rswr_fused.hip -- one launch per span: the predict of Sec. 2.3 folded into
-// the update of Sec. 2.5.
-//
-// Method: Wei & Zhao, arXiv 2203.10477.  The flux a window receives at an
-// input end is predicted by the neighbouring window at that node (Eqs.
-// (8)-(9)).  Over S levels that sample depends only on the state within S
-// nodes of the end (one node per level, Sec. 2.4), so the wave holding the
-// tile's input end carries the prediction itself: a frame of 2*kFrameHalf
-// nodes centred on the end, two nodes per lane, advanced in lockstep with
-// the tile; F[s] is read across lanes with readlane and feeds the ghost
-// node of Eqs. (6)-(7) in the same step.  No flux passes through memory
-// (it is written only when the caller keeps the span's fluxes).
-//
-// Over S levels the flux at o reads the state in [o-S, o+S] and nothing
-// else: the predicting window's input ends lie at least the light-cone
-// limit >= S nodes from o.  So the frame runs the plain stencil everywhere,
-// except at node 0 or M-1 (Dirichlet, Eq. (3)) where a frame holds one; what
-// lies outside [o-S, o+S] (the state mirrored at the window's ends, the
-// frame's cut ends, which reach o +- 1 only after kFrameHalf - 1 >= S
-// levels) cannot reach the sample in time, and F[s] equals the
-// whole-window prediction bit for bit.
-//
-// Dirichlet values of nodes 0 and M-1 for the span's levels sit one per
-// lane and are read with readlane, so a step waits on LDS only for the
-// values crossing between waves.
-#include "rswr_device.h"
+// rswr_fused.hip -- the fused span kernel of one problem: one launch per
+// span, one work-group per tile (device code in rswr_fused.h).
+#include "rswr_fused.h"
 
 namespace rswr {
-
-template <typename T, int NT, int MPT>
-struct FusedCtx {
-  T (*edge)[2][NT / 64];
-  T vA, vB;      // lane s: node 0 / node M-1 at level n0+s (or 0 where unused)
-  T nq, pq;      // -2 dx and 2 dx, in vector registers
-  int64_t base;  // this lane's first node
-  int d0, rb, re, lane, wv;
-  bool gen;
-  bool dirL, dirR;    // this wave's lane 0 / lane 63 borders a Dirichlet node
-  bool fdirL, fdirR;  // this wave's left frame holds node 0 / right frame node M-1
-  bool fmL[2], fmR[2];  // which of this lane's frame elements is that node
-  bool keep;          // the caller keeps the predicted fluxes
-};
-
-// Frame around output node o of window w: lane l holds nodes
-// o - kFrameHalf + 2l and the next one, at the span's first level (cur) and
-// the one before (old); nodes beyond the window take their mirror image
-// (clamped into the window), a value the sample never sees.
-template <typename T>
-__device__ __forceinline__ void frame_load(const UpdateArgs<T>& p, int64_t o, int w,
-                                           int lane, T (&cur)[2], T (&old)[2]) {
-  const int64_t wlo = p.lo[w], whi = p.hi[w];
-#pragma unroll
-  for (int e = 0; e < 2; ++e) {
-    int64_t j = o - kFrameHalf + 2 * lane + e;
-    j = (j < wlo) ? 2 * wlo - j : ((j > whi) ? 2 * whi - j : j);
-    j = j < wlo ? wlo : (j > whi ? whi : j);
-    cur[e] = p.state_in[p.M + j];
-    old[e] = p.state_in[j];
-  }
-}
-
-// One level of a frame: returns the centred flux at the output node (lane
-// kFrameHalf/2, element 0) at the current level and writes the next level
-// over `old`.
-template <typename T>
-__device__ __forceinline__ T frame_step(const T (&cur)[2], T (&old)[2], T c2, T k, T r) {
-  const T l1 = lane_shift_z<kWaveShr1>(cur[1]);
-  const T r0 = lane_shift_z<kWaveShl1>(cur[0]);
-  const T f = rd_lane((cur[1] - l1) * r, kFrameHalf / 2);
-  old[0] = leap(c2, k, l1, cur[0], cur[1], old[0]);
-  old[1] = leap(c2, k, cur[0], cur[1], r0, old[1]);
-  return f;
-}
-
-// A frame of window 0 may hold node 0, one of window N-1 node M-1: those
-// nodes take the Dirichlet value of the new level (Eq. (3)) instead of the
-// stencil.  `dir` is wave-uniform; `d` is the value, `m` marks the element.
-template <typename T>
-__device__ __forceinline__ void frame_dirichlet(bool dir, const bool (&m)[2], T d,
-                                                T (&lvl)[2]) {
-  if (dir) {
-    lvl[0] = m[0] ? d : lvl[0];
-    lvl[1] = m[1] ? d : lvl[1];
-  }
-}
-
-// One step of the tile (cur = level n, old = level n-1 on entry, old = level
-// n+1 on exit) and of the frames this wave carries (HL: the left input,
-// HR: the right input).  fl / fr collect F[s] in lane s when the caller
-// keeps the fluxes.  The lane shifts fill the wave's ends with zero: the
-// zero data of a cut region end; input ghosts, Dirichlet values and the
-// neighbouring wave's node replace it where they apply.
-template <typename T, int NT, int MPT, bool GEN, bool HL, bool HR>
-__device__ __forceinline__ void fused_step(const UpdateArgs<T>& p,
-                                           const FusedCtx<T, NT, MPT>& c,
-                                           const T (&cur)[MPT], T (&old)[MPT],
-                                           const T (&lc)[2], T (&lo)[2], const T (&rc)[2],
-                                           T (&ro)[2], T& fl, T& fr, int s) {
-  constexpr int NW = NT / 64;
-  const int par = s & 1;
-  T L = lane_shift_z<kWaveShr1>(cur[MPT - 1]);
-  T R = lane_shift_z<kWaveShl1>(cur[0]);
-  if constexpr (HL) {
-    const T F = frame_step(lc, lo, p.c2, p.k, p.r);
-    if (c.fdirL) {
-      const T d = rd_lane(c.vA, s + 1);
-      frame_dirichlet(true, c.fmL, d, lo);
-    }
-    if (c.keep) fl = wr_lane(F, s, fl, c.lane);
-    L = (c.lane == 0) ? fma_(c.nq, F, cur[1]) : L;
-  }
-  if constexpr (HR) {
-    const T F = frame_step(rc, ro, p.c2, p.k, p.r);
-    if (c.fdirR) {
-      const T d = rd_lane(c.vB, s + 1);
-      frame_dirichlet(true, c.fmR, d, ro);
-    }
-    if (c.keep) fr = wr_lane(F, s, fr, c.lane);
-    R = (c.lane == 63) ? fma_(c.pq, F, cur[MPT - 2]) : R;
-  }
-  if constexpr (NW > 1) {
-    if (c.lane == 63) c.edge[par][1][c.wv] = cur[MPT - 1];
-    if (c.lane == 0) c.edge[par][0][c.wv] = cur[0];
-    __syncthreads();
-    if (!HL && c.wv > 0) L = (c.lane == 0) ? c.edge[par][1][c.wv - 1] : L;
-    if (!HR && c.wv < NW - 1) R = (c.lane == 63) ? c.edge[par][0][c.wv + 1] : R;
-  }
-  // readlane reads another lane, so it runs with the whole wave active (a
-  // wave-uniform branch), never under the lane-0 / lane-63 condition
-  if (!HL && c.dirL) {
-    const T d = rd_lane(c.vA, s);
-    L = (c.lane == 0) ? d : L;
-  }
-  if (!HR && c.dirR) {
-    const T d = rd_lane(c.vB, s);
-    R = (c.lane == 63) ? d : R;
-  }
-  if (GEN && c.gen)
-    step_chunk<T, MPT, true>(cur, old, L, R, p.c2, p.k, -1000, c.d0, T(0),
-                             rd_lane(c.vA, s + 1));
-  else
-    step_chunk<T, MPT, false>(cur, old, L, R, p.c2, p.k, 0, 0, T(0), T(0));
-  if (GEN) {
-    const T da = rd_lane(c.vA, s + 1), db = rd_lane(c.vB, s + 1);
-    for (int r = c.rb; r < c.re; ++r) {
-      const int64_t d = p.rec_node[r] - c.base;
-      T* dst = p.traces + static_cast<int64_t>(p.rec_id[r]) * p.trace_ld + p.trace_col0 + s;
-      if (d >= 0 && d < MPT)
-        *dst = pick<T, MPT>(old, d);
-      else if (d == -1 && c.lane == 0 && c.wv == 0 && c.dirL)
-        *dst = da;
-      else if (d == MPT && c.lane == 63 && c.wv == NW - 1 && c.dirR)
-        *dst = db;
-    }
-  }
-}
-
-template <typename T, int NT, int MPT, bool GEN, bool HL, bool HR>
-__device__ __forceinline__ void fused_run(const UpdateArgs<T>& p, const Tile& tl,
-                                          const FusedCtx<T, NT, MPT>& c, int S,
-                                          T (&u)[MPT], T (&uo)[MPT]) {
-  constexpr int TM = NT * MPT;
-  T lc[2], lo[2], rc[2], ro[2];
-  T fl = T(0), fr = T(0);
-  if constexpr (HL) frame_load(p, tl.a, tl.window - 1, c.lane, lc, lo);
-  if constexpr (HR) frame_load(p, tl.a + TM - 1, tl.window + 1, c.lane, rc, ro);
-  int s = 0;
-  for (; s + 1 < S; s += 2) {
-    fused_step<T, NT, MPT, GEN, HL, HR>(p, c, u, uo, lc, lo, rc, ro, fl, fr, s);
-    fused_step<T, NT, MPT, GEN, HL, HR>(p, c, uo, u, lo, lc, ro, rc, fl, fr, s + 1);
-  }
-  if (s < S) fused_step<T, NT, MPT, GEN, HL, HR>(p, c, u, uo, lc, lo, rc, ro, fl, fr, s);
-  if (p.flux_out != nullptr && c.lane < S) {
-    if constexpr (HL) p.flux_out[static_cast<int64_t>(2 * tl.fl) * p.ld + c.lane] = fl;
-    if constexpr (HR) p.flux_out[static_cast<int64_t>(2 * tl.fr + 1) * p.ld + c.lane] = fr;
-  }
-}
 
 template <typename T, int NT, int MPT, bool GEN>
 __global__ __launch_bounds__(NT) void k_fused(const UpdateArgs<T> p) {
   constexpr int NW = NT / 64;
   constexpr int TM = NT * MPT;
   constexpr int TMP = TM + (TM >> 5) + 1;
-  static_assert(NT % 64 == 0 && MPT >= 2, "shape");
   __shared__ T st[TMP];
   __shared__ T edge[2][2][NW];
-
-  const int tid = threadIdx.x;
   const int slot = xcd_tile(blockIdx.x, gridDim.x);
-  const int tix = p.tile_idx[slot];
-  const Tile tl = p.tiles[tix];
+  const Tile tl = p.tiles[p.tile_idx[slot]];
   const int S = p.span;
   if (S <= 0 || S > kMaxFusedSpan) return;
-
-  const bool inside = tl.a >= 0 && tl.a + TM <= p.M;
-  T u[MPT], uo[MPT];
-  {
-    T t1[MPT], t0[MPT];
-    load_level<T, NT, MPT>(p.state_in + p.M, tl.a, p.M, inside, t1);  // level n0
-    load_level<T, NT, MPT>(p.state_in, tl.a, p.M, inside, t0);        // level n0-1
-    transpose_in<T, NT, MPT>(t1, st, u);
-    transpose_in<T, NT, MPT>(t0, st, uo);
-  }
-
-  FusedCtx<T, NT, MPT> c;
-  c.edge = edge;
-  c.lane = tid & 63;
-  c.wv = __builtin_amdgcn_readfirstlane(tid >> 6);
-  c.base = tl.a + static_cast<int64_t>(tid) * MPT;
-  const bool dirL = tl.lmode == kEndDirichlet, dirR = tl.rmode == kEndDirichlet;
-  c.dirL = dirL && c.wv == 0;
-  c.dirR = dirR && c.wv == NW - 1;
-  // frames around the input ends (left: o = a, right: o = a + TM - 1); a
-  // frame spans [o - kFrameHalf, o + kFrameHalf - 1]
-  const int64_t oL = tl.a, oR = tl.a + TM - 1;
-  const bool fA = tl.lmode == kEndGhost && tl.window == 1 && oL - kFrameHalf <= 0;
-  const bool fB = tl.rmode == kEndGhost && oR + kFrameHalf - 1 >= p.M - 1 &&
-                  p.hi[tl.window + 1] == p.M - 1;
-  c.fdirL = fA && c.wv == 0;
-  c.fdirR = fB && c.wv == NW - 1;
-#pragma unroll
-  for (int e = 0; e < 2; ++e) {
-    c.fmL[e] = oL - kFrameHalf + 2 * c.lane + e == 0;
-    c.fmR[e] = oR - kFrameHalf + 2 * c.lane + e == p.M - 1;
-  }
-  c.keep = p.flux_out != nullptr;
-  c.nq = in_vgpr(-p.q);
-  c.pq = in_vgpr(p.q);
-  {
-    // node 0 / M-1 at level n0 (from the state) and n0+1.. (from f_A, f_B)
-    const int l = c.lane;
-    T a = T(0), b = T(0);
-    if ((GEN || dirL || fA) && l <= S) a = (l == 0) ? p.state_in[p.M] : p.fa[p.n0 + l];
-    if ((GEN || dirR || fB) && l <= S) b = (l == 0) ? p.state_in[2 * p.M - 1] : p.fb[p.n0 + l];
-    c.vA = a;
-    c.vB = b;
-  }
-  c.d0 = -1000;
-  c.gen = false;
-  c.rb = 0;
-  c.re = 0;
-  if (GEN) {
-    const int64_t d = -c.base;
-    c.d0 = (d < -2 || d > MPT + 1) ? -1000 : static_cast<int>(d);
-    c.gen = __any(c.d0 >= 0 && c.d0 < MPT) != 0;
-    c.rb = p.rec_ptr ? p.rec_ptr[slot] : 0;
-    c.re = p.rec_ptr ? p.rec_ptr[slot + 1] : 0;
-  }
-
-  const bool hl = c.wv == 0 && tl.lmode == kEndGhost;
-  const bool hr = c.wv == NW - 1 && tl.rmode == kEndGhost;
-  if (hl) {
-    if (hr)
-      fused_run<T, NT, MPT, GEN, true, true>(p, tl, c, S, u, uo);
-    else
-      fused_run<T, NT, MPT, GEN, true, false>(p, tl, c, S, u, uo);
-  } else {
-    if (hr)
-      fused_run<T, NT, MPT, GEN, false, true>(p, tl, c, S, u, uo);
-    else
-      fused_run<T, NT, MPT, GEN, false, false>(p, tl, c, S, u, uo);
-  }
-
-  const int64_t rlo = tl.out_lo > tl.a ? tl.out_lo : tl.a;
-  const int64_t rhi = tl.out_hi < tl.a + TM - 1 ? tl.out_hi : tl.a + TM - 1;
-  const int xlo = static_cast<int>(rlo - tl.a);
-  const int xhi = static_cast<int>(rhi - tl.a);
-  if (S & 1) {  // uo = level n0+S, u = n0+S-1
-    stage_out<T, NT, MPT>(p.state_out, tl.a, xlo, xhi, st, u);
-    stage_out<T, NT, MPT>(p.state_out + p.M, tl.a, xlo, xhi, st, uo);
-  } else {
-    stage_out<T, NT, MPT>(p.state_out, tl.a, xlo, xhi, st, uo);
-    stage_out<T, NT, MPT>(p.state_out + p.M, tl.a, xlo, xhi, st, u);
-  }
-  // Dirichlet nodes next to the region
-  if (dirL && c.wv == 0) {
-    const T a1 = rd_lane(c.vA, S - 1), a2 = rd_lane(c.vA, S);
-    if (tid == 0) {
-      p.state_out[0] = a1;
-      p.state_out[p.M] = a2;
-    }
-  }
-  if (dirR && c.wv == NW - 1) {
-    const T b1 = rd_lane(c.vB, S - 1), b2 = rd_lane(c.vB, S);
-    if (tid == NT - 1) {
-      p.state_out[p.M - 1] = b1;
-      p.state_out[2 * p.M - 1] = b2;
-    }
-  }
+  fused_tile<T, NT, MPT, GEN>(p, tl, slot, S, st, edge);
 }
 
 template <typename T>

@@ -14,7 +14,9 @@
 #include <limits>
 #include <map>
 #include <mutex>
+#include <numeric>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "../../include/rswr.h"
@@ -528,22 +530,23 @@ rswr_status_t enqueue_solve(rswr_plan_s* p, const DevTables& d, void* state,
   return RSWR_OK;
 }
 
-// Records `enqueue` into a HIP graph once per key and replays it on `s`.
+// Records `enqueue` into a HIP graph once per key (on the capture stream
+// `cap`, kept in `graphs`, at most 8) and replays it on `s`.
 template <typename F>
-rswr_status_t run_graph(rswr_plan_s* p, DevTables* d, const GraphKey& key, F&& enqueue,
-                        hipStream_t s) {
+rswr_status_t run_graph_in(std::mutex& mu, std::vector<GraphEntry>& graphs, hipStream_t cap,
+                           const GraphKey& key, F&& enqueue, hipStream_t s) {
   if (std::getenv("RSWR_NO_GRAPH") != nullptr) return enqueue(s);
   hipGraphExec_t exec = nullptr;
   {
-    std::lock_guard<std::mutex> g(p->mu);
-    for (auto& e : p->graphs)
+    std::lock_guard<std::mutex> g(mu);
+    for (auto& e : graphs)
       if (e.key == key) exec = e.exec;
   }
   if (!exec) {
     hipGraph_t graph = nullptr;
-    RSWR_HIP(hipStreamBeginCapture(d->capture, hipStreamCaptureModeThreadLocal));
-    rswr_status_t cst = enqueue(d->capture);
-    hipError_t ee = hipStreamEndCapture(d->capture, &graph);
+    RSWR_HIP(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
+    rswr_status_t cst = enqueue(cap);
+    hipError_t ee = hipStreamEndCapture(cap, &graph);
     if (cst != RSWR_OK) {
       if (graph) (void)hipGraphDestroy(graph);
       return cst;
@@ -552,15 +555,21 @@ rswr_status_t run_graph(rswr_plan_s* p, DevTables* d, const GraphKey& key, F&& e
     ee = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
     (void)hipGraphDestroy(graph);
     if (ee != hipSuccess) return hip_fail(ee, "hipGraphInstantiate");
-    std::lock_guard<std::mutex> g(p->mu);
-    if (p->graphs.size() >= 8) {
-      (void)hipGraphExecDestroy(p->graphs.front().exec);
-      p->graphs.erase(p->graphs.begin());
+    std::lock_guard<std::mutex> g(mu);
+    if (graphs.size() >= 8) {
+      (void)hipGraphExecDestroy(graphs.front().exec);
+      graphs.erase(graphs.begin());
     }
-    p->graphs.push_back({key, exec});
+    graphs.push_back({key, exec});
   }
   RSWR_HIP(hipGraphLaunch(exec, s));
   return RSWR_OK;
+}
+
+template <typename F>
+rswr_status_t run_graph(rswr_plan_s* p, DevTables* d, const GraphKey& key, F&& enqueue,
+                        hipStream_t s) {
+  return run_graph_in(p->mu, p->graphs, d->capture, key, std::forward<F>(enqueue), s);
 }
 
 // ---------------------------------------------------------------------------
@@ -1237,6 +1246,258 @@ rswr_status_t rswr_solve_adjoint(rswr_plan_t p, const void* checkpoints, const v
                      al.n_gen,
                      al.n_fast};
   return run_graph(p, d, key, enqueue, s);
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Batched solve: many independent problems (each a fused-span plan) advanced
+// together.  Round r runs span r of every problem with spans left; per
+// kernel shape one persistent launch walks the round's tiles.  Problems are
+// ordered by span count, longest first, so a round's tiles are a prefix of
+// each shape's list.  The whole run is recorded into one HIP graph.
+// ---------------------------------------------------------------------------
+struct rswr_batch_s {
+  std::vector<rswr_plan_s*> plans;
+  int32_t dtype = 0;
+  std::vector<std::pair<int32_t, int32_t>> shapes;  // (threads, nodes per lane)
+  std::vector<int32_t> shape_of;                    // per problem
+  std::mutex mu;
+  std::vector<GraphEntry> graphs;
+  std::map<int, hipStream_t> capture;
+  std::map<int, std::vector<int32_t>> grid;  // per device: resident groups per shape
+};
+
+namespace {
+
+struct BatchWs {
+  size_t inst = 0, items = 0, jobs = 0, total = 0;
+  std::vector<size_t> state;  // per problem: its second state buffer
+};
+
+BatchWs batch_ws_layout(const rswr_batch_s& b) {
+  BatchWs w;
+  const size_t e = b.dtype == RSWR_F64 ? 8 : 4;
+  const size_t n = b.plans.size();
+  const size_t inst_bytes = b.dtype == RSWR_F64 ? sizeof(rswr::BatchInst<double>)
+                                                : sizeof(rswr::BatchInst<float>);
+  size_t n_tiles = 0;
+  for (const rswr_plan_s* p : b.plans) n_tiles += p->tiles.size();
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = off;
+    off += round_up(std::max<size_t>(bytes, 1), 256);
+    return at;
+  };
+  w.inst = take(n * inst_bytes);
+  w.items = take(n_tiles * sizeof(Tile));
+  w.jobs = take(n * (2 * sizeof(void*) + sizeof(int64_t)));
+  for (const rswr_plan_s* p : b.plans) w.state.push_back(take(2 * size_t(p->M) * e));
+  w.total = off;
+  return w;
+}
+
+template <typename T>
+rswr_status_t batch_solve(rswr_batch_s* b, void* const* states, const void* const* f_a,
+                          const void* const* f_b, const int64_t* n_steps, char* ws,
+                          const BatchWs& L, hipStream_t s) {
+  const int32_t n = static_cast<int32_t>(b->plans.size());
+  int device = 0;
+  std::vector<DevTables*> dt(n);
+  for (int32_t i = 0; i < n; ++i) {
+    rswr_status_t st = ensure_device(b->plans[i], &dt[i], &device);
+    if (st != RSWR_OK) return st;
+  }
+  hipStream_t cap = nullptr;
+  std::vector<int32_t> grid;
+  {
+    std::lock_guard<std::mutex> g(b->mu);
+    auto it = b->capture.find(device);
+    if (it == b->capture.end()) {
+      hipStream_t c = nullptr;
+      RSWR_HIP(hipStreamCreateWithFlags(&c, hipStreamNonBlocking));
+      it = b->capture.emplace(device, c).first;
+      std::vector<int32_t> gr;
+      for (const auto& sh : b->shapes)
+        gr.push_back(std::max(1, rswr::fused_batch_capacity<T>(sh.first, sh.second)));
+      b->grid[device] = gr;
+    }
+    cap = it->second;
+    grid = b->grid[device];
+  }
+
+  // spans per problem, longest first
+  std::vector<int64_t> K(n);
+  for (int32_t i = 0; i < n; ++i) K[i] = (n_steps[i] + b->plans[i]->S - 1) / b->plans[i]->S;
+  std::vector<int32_t> order(n);
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) { return K[x] > K[y]; });
+  const int64_t rounds = n > 0 ? K[order[0]] : 0;
+
+  std::vector<rswr::BatchInst<T>> inst(n);
+  std::vector<rswr::CopyJob<T>> jobs;
+  for (int32_t i = 0; i < n; ++i) {
+    const rswr_plan_s& p = *b->plans[i];
+    T* user = static_cast<T*>(states[i]);
+    T* other = reinterpret_cast<T*>(ws + L.state[i]);
+    // an odd number of spans starts from a copy, so the last span writes
+    // the caller's buffer
+    const bool odd = K[i] & 1;
+    rswr::BatchInst<T>& in = inst[i];
+    in.st_a = odd ? other : user;
+    in.st_b = odd ? user : other;
+    if (odd) jobs.push_back({other, user, 2 * p.M});
+    in.fa = static_cast<const T*>(f_a[i]);
+    in.fb = static_cast<const T*>(f_b[i]);
+    in.lo = dt[i]->lo;
+    in.hi = dt[i]->hi;
+    in.M = p.M;
+    in.n_steps = n_steps[i];
+    in.S = p.S;
+    const double c2 = p.lam * p.lam;
+    in.c2 = T(c2);
+    in.k = T(2.0 - 2.0 * c2);
+    in.q = T(2.0 * p.dx);
+    in.r = T(1.0 / (2.0 * p.dx));
+  }
+  // tiles per shape in problem order; active[c][r]: tiles of round r
+  const size_t n_shapes = b->shapes.size();
+  std::vector<std::vector<Tile>> items(n_shapes);
+  std::vector<std::vector<int32_t>> active(n_shapes, std::vector<int32_t>(rounds, 0));
+  for (int32_t i : order) {
+    const int32_t c = b->shape_of[i];
+    for (Tile t : b->plans[i]->tiles) {
+      t.inst = i;
+      items[c].push_back(t);
+    }
+    for (int64_t r = 0; r < K[i]; ++r) active[c][r] += int32_t(b->plans[i]->tiles.size());
+  }
+  std::vector<size_t> item_off(n_shapes, 0);
+  std::vector<Tile> all;
+  for (size_t c = 0; c < n_shapes; ++c) {
+    item_off[c] = all.size();
+    all.insert(all.end(), items[c].begin(), items[c].end());
+  }
+  if (n > 0)
+    RSWR_HIP(hipMemcpyAsync(ws + L.inst, inst.data(), n * sizeof(rswr::BatchInst<T>),
+                            hipMemcpyHostToDevice, s));
+  if (!all.empty())
+    RSWR_HIP(hipMemcpyAsync(ws + L.items, all.data(), all.size() * sizeof(Tile),
+                            hipMemcpyHostToDevice, s));
+  if (!jobs.empty())
+    RSWR_HIP(hipMemcpyAsync(ws + L.jobs, jobs.data(), jobs.size() * sizeof(rswr::CopyJob<T>),
+                            hipMemcpyHostToDevice, s));
+
+  const auto* inst_d = reinterpret_cast<const rswr::BatchInst<T>*>(ws + L.inst);
+  const auto* items_d = reinterpret_cast<const Tile*>(ws + L.items);
+  const auto* jobs_d = reinterpret_cast<const rswr::CopyJob<T>*>(ws + L.jobs);
+  const int32_t n_jobs = static_cast<int32_t>(jobs.size());
+  auto enqueue = [&](hipStream_t q) -> rswr_status_t {
+    RSWR_HIP(rswr::launch_copy_many<T>(jobs_d, n_jobs, q));
+    for (int64_t r = 0; r < rounds; ++r)
+      for (size_t c = 0; c < n_shapes; ++c) {
+        if (active[c][r] == 0) continue;
+        rswr::BatchArgs<T> a{};
+        a.items = items_d + item_off[c];
+        a.inst = inst_d;
+        a.n_items = active[c][r];
+        a.round = static_cast<int32_t>(r);
+        RSWR_HIP(rswr::launch_fused_batch<T>(a, b->shapes[c].first, b->shapes[c].second,
+                                             grid[c], q));
+      }
+    return RSWR_OK;
+  };
+  GraphKey key{3, reinterpret_cast<int64_t>(ws), n};
+  for (int32_t i = 0; i < n; ++i) {
+    key.push_back(reinterpret_cast<int64_t>(states[i]));
+    key.push_back(reinterpret_cast<int64_t>(f_a[i]));
+    key.push_back(reinterpret_cast<int64_t>(f_b[i]));
+    key.push_back(n_steps[i]);
+  }
+  return run_graph_in(b->mu, b->graphs, cap, key, enqueue, s);
+}
+
+}  // namespace
+
+extern "C" {
+
+rswr_status_t rswr_batch_plan(const rswr_plan_t* plans, int32_t n, rswr_batch_t* out) {
+  if (!out || (n > 0 && !plans) || n < 0) return fail(RSWR_ERR_INVALID_ARG, "bad argument");
+  *out = nullptr;
+  rswr_batch_s* b = new (std::nothrow) rswr_batch_s;
+  if (!b) return fail(RSWR_ERR_NOMEM, "batch allocation");
+  for (int32_t i = 0; i < n; ++i) {
+    rswr_plan_s* p = plans[i];
+    if (!p) {
+      delete b;
+      return fail(RSWR_ERR_INVALID_ARG, "null plan " + std::to_string(i));
+    }
+    if (i == 0) b->dtype = p->dtype;
+    if (p->dtype != b->dtype) {
+      delete b;
+      return fail(RSWR_ERR_INVALID_ARG, "plans of different dtypes");
+    }
+    if (!p->fused) {
+      delete b;
+      return fail(RSWR_ERR_UNSUPPORTED,
+                  "plan " + std::to_string(i) + " does not run the fused span");
+    }
+    const std::pair<int32_t, int32_t> sh{p->threads, p->per_thread};
+    auto it = std::find(b->shapes.begin(), b->shapes.end(), sh);
+    if (it == b->shapes.end()) {
+      b->shapes.push_back(sh);
+      it = b->shapes.end() - 1;
+    }
+    b->shape_of.push_back(static_cast<int32_t>(it - b->shapes.begin()));
+    b->plans.push_back(p);
+  }
+  *out = b;
+  return RSWR_OK;
+}
+
+rswr_status_t rswr_batch_destroy(rswr_batch_t b) {
+  if (!b) return RSWR_OK;
+  if (!b->capture.empty()) {
+    int cur = 0;
+    (void)hipGetDevice(&cur);
+    for (auto& kv : b->capture) {
+      (void)hipSetDevice(kv.first);
+      (void)hipStreamDestroy(kv.second);
+    }
+    for (auto& g : b->graphs) (void)hipGraphExecDestroy(g.exec);
+    (void)hipSetDevice(cur);
+  }
+  delete b;
+  return RSWR_OK;
+}
+
+rswr_status_t rswr_batch_workspace_size(rswr_batch_t b, size_t* bytes) {
+  if (!b || !bytes) return fail(RSWR_ERR_INVALID_ARG, "null batch or output");
+  *bytes = batch_ws_layout(*b).total;
+  return RSWR_OK;
+}
+
+rswr_status_t rswr_batch_solve(rswr_batch_t b, void* const* states, const void* const* f_a,
+                               const void* const* f_b, const int64_t* n_steps,
+                               void* workspace, size_t ws_bytes, void* stream) {
+  if (!b) return fail(RSWR_ERR_INVALID_ARG, "null batch");
+  const int32_t n = static_cast<int32_t>(b->plans.size());
+  if (n == 0) return RSWR_OK;
+  if (!states || !f_a || !f_b || !n_steps)
+    return fail(RSWR_ERR_INVALID_ARG, "null array argument");
+  for (int32_t i = 0; i < n; ++i) {
+    if (!states[i] || !f_a[i] || !f_b[i])
+      return fail(RSWR_ERR_INVALID_ARG, "null pointer for problem " + std::to_string(i));
+    if (n_steps[i] < 0) return fail(RSWR_ERR_INVALID_ARG, "negative n_steps");
+  }
+  const BatchWs L = batch_ws_layout(*b);
+  if (!workspace || ws_bytes < L.total)
+    return fail(RSWR_ERR_NOMEM, "workspace needs " + std::to_string(L.total) + " bytes");
+  char* ws = static_cast<char*>(workspace);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (b->dtype == RSWR_F64)
+    return batch_solve<double>(b, states, f_a, f_b, n_steps, ws, L, s);
+  return batch_solve<float>(b, states, f_a, f_b, n_steps, ws, L, s);
 }
 
 }  // extern "C"

@@ -39,7 +39,8 @@ struct Tile {
   int32_t fl, fr;
   int32_t lmode, rmode;
   int32_t window, general;
-  int32_t pad[2];
+  int32_t inst;  // problem index in a batched launch (0 otherwise)
+  int32_t pad;
 };
 static_assert(sizeof(Tile) == 64, "Tile layout");
 
@@ -129,8 +130,37 @@ struct AdjUpdateArgs {
   T c2, k, q;
 };
 
-// Launchers (defined in rswr_kernels.hip / rswr_adjoint.hip).  They return
-// hipGetLastError().
+// One problem of a batched launch.  Round r reads st_a (r even) or st_b
+// and writes the other; n0 = r * S.
+template <typename T>
+struct BatchInst {
+  T* st_a;
+  T* st_b;
+  const T* fa;
+  const T* fb;
+  const int64_t* lo;
+  const int64_t* hi;
+  int64_t M, n_steps;
+  int32_t S, pad;
+  T c2, k, q, r;
+};
+
+template <typename T>
+struct BatchArgs {
+  const Tile* items;  // tiles of every problem in this launch (Tile::inst set)
+  const BatchInst<T>* inst;
+  int32_t n_items, round;
+};
+
+template <typename T>
+struct CopyJob {
+  T* dst;
+  const T* src;
+  int64_t n;
+};
+
+// Launchers (defined in rswr_kernels.hip / rswr_fused.hip / rswr_batch.hip /
+// rswr_adjoint.hip).  They return hipGetLastError().
 template <typename T>
 hipError_t launch_predict(const PredictArgs<T>& a, int shmem_nodes,
                           hipStream_t s);
@@ -142,6 +172,16 @@ hipError_t launch_update(const UpdateArgs<T>& a, int threads, int per_thread,
 template <typename T>
 hipError_t launch_fused(const UpdateArgs<T>& a, int threads, int per_thread,
                         bool general, hipStream_t s);
+// Batched fused span: one persistent launch over the items with `grid`
+// work-groups (at most the items); fused_batch_capacity gives the kernel's
+// resident work-groups on the current device (0: shape not built).
+template <typename T>
+int fused_batch_capacity(int threads, int per_thread);
+template <typename T>
+hipError_t launch_fused_batch(const BatchArgs<T>& a, int threads, int per_thread, int grid,
+                              hipStream_t s);
+template <typename T>
+hipError_t launch_copy_many(const CopyJob<T>* jobs, int32_t n_jobs, hipStream_t s);
 template <typename T>
 hipError_t launch_select(const SelectArgs<T>& a, hipStream_t s);
 template <typename T>

@@ -159,3 +159,35 @@ def test_fused_flag_cases():
     # launches
     gen = rs.Plan(301, 20, 20)
     assert any(g and w > 0 for *_, w, _, _, g in gen.tiles()) == (gen.info["fused"] == 0)
+
+
+def test_batch_plan_rejections():
+    """A batch takes fused plans of one dtype only (host-side checks)."""
+    a = rs.Plan(1001, 2, 20)
+    b = rs.Plan(1001, 2, 20, dtype=torch.float32)
+    with pytest.raises(rs.RSWRError) as e:
+        rs.Batch([a, b])
+    assert e.value.status == 1
+    two = rs.Plan(1001, 2, 20, fuse=False)
+    with pytest.raises(rs.RSWRError) as e:
+        rs.Batch([a, two])
+    assert e.value.status == 8
+    ok = rs.Batch([a, rs.Plan(4097, 8, 64)])
+    # one second state buffer per problem plus tables
+    assert ok.workspace_bytes() >= 2 * (1001 + 4097) * 8
+    assert rs.Batch([]).workspace_bytes() >= 0
+
+
+def test_batch_recipe_plans_all_fuse():
+    """The batched workload's problems: span capped at 63, every plan fused,
+    windows at least one overlap wide (cores clamped)."""
+    import workloads
+    from paper_2203_10477_amd.autotune import autotune_batch, batch_plans
+    probs, clamped = workloads.config3()
+    assert len(probs) == 512 and clamped > 0
+    assert all((p.M - 1) // p.N >= p.P for p in probs)
+    tiles, spans, report = autotune_batch(probs, measure=False)
+    plans = batch_plans(probs, tiles=tiles, spans=spans)
+    assert all(p.info["fused"] for p in plans)
+    assert max(spans) == 63 and min(spans) >= 17
+    assert len(report) >= 5
