@@ -1265,6 +1265,8 @@ struct rswr_batch_s {
   std::mutex mu;
   std::vector<GraphEntry> graphs;
   std::map<int, hipStream_t> capture;
+  std::map<int, std::vector<hipStream_t>> lanes;  // per device: one stream per shape
+  std::map<int, std::vector<hipEvent_t>> events;  // per device: fork + one per shape
   std::map<int, std::vector<int32_t>> grid;  // per device: resident groups per shape
 };
 
@@ -1318,13 +1320,28 @@ rswr_status_t batch_solve(rswr_batch_s* b, void* const* states, const void* cons
       RSWR_HIP(hipStreamCreateWithFlags(&c, hipStreamNonBlocking));
       it = b->capture.emplace(device, c).first;
       std::vector<int32_t> gr;
-      for (const auto& sh : b->shapes)
+      std::vector<hipStream_t> ln;
+      std::vector<hipEvent_t> ev;
+      hipEvent_t e = nullptr;
+      RSWR_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+      ev.push_back(e);
+      for (const auto& sh : b->shapes) {
         gr.push_back(std::max(1, rswr::fused_batch_capacity<T>(sh.first, sh.second)));
+        hipStream_t q = nullptr;
+        RSWR_HIP(hipStreamCreateWithFlags(&q, hipStreamNonBlocking));
+        ln.push_back(q);
+        RSWR_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+        ev.push_back(e);
+      }
       b->grid[device] = gr;
+      b->lanes[device] = ln;
+      b->events[device] = ev;
     }
     cap = it->second;
     grid = b->grid[device];
   }
+  const std::vector<hipStream_t> lanes = b->lanes[device];
+  const std::vector<hipEvent_t> events = b->events[device];
 
   // spans per problem, longest first
   std::vector<int64_t> K(n);
@@ -1392,19 +1409,28 @@ rswr_status_t batch_solve(rswr_batch_s* b, void* const* states, const void* cons
   const auto* items_d = reinterpret_cast<const Tile*>(ws + L.items);
   const auto* jobs_d = reinterpret_cast<const rswr::CopyJob<T>*>(ws + L.jobs);
   const int32_t n_jobs = static_cast<int32_t>(jobs.size());
+  // Problems of different shapes share nothing: each shape's rounds form
+  // their own chain on a stream of their own (fork after the copies, join
+  // at the end), so the chains overlap on the device.
   auto enqueue = [&](hipStream_t q) -> rswr_status_t {
     RSWR_HIP(rswr::launch_copy_many<T>(jobs_d, n_jobs, q));
-    for (int64_t r = 0; r < rounds; ++r)
-      for (size_t c = 0; c < n_shapes; ++c) {
-        if (active[c][r] == 0) continue;
+    RSWR_HIP(hipEventRecord(events[0], q));
+    for (size_t c = 0; c < n_shapes; ++c) {
+      hipStream_t lane = lanes[c];
+      RSWR_HIP(hipStreamWaitEvent(lane, events[0], 0));
+      for (int64_t r = 0; r < rounds; ++r) {
+        if (active[c][r] == 0) break;  // later rounds have fewer problems
         rswr::BatchArgs<T> a{};
         a.items = items_d + item_off[c];
         a.inst = inst_d;
         a.n_items = active[c][r];
         a.round = static_cast<int32_t>(r);
         RSWR_HIP(rswr::launch_fused_batch<T>(a, b->shapes[c].first, b->shapes[c].second,
-                                             grid[c], q));
+                                             grid[c], lane));
       }
+      RSWR_HIP(hipEventRecord(events[c + 1], lane));
+      RSWR_HIP(hipStreamWaitEvent(q, events[c + 1], 0));
+    }
     return RSWR_OK;
   };
   GraphKey key{3, reinterpret_cast<int64_t>(ws), n};
@@ -1463,6 +1489,8 @@ rswr_status_t rswr_batch_destroy(rswr_batch_t b) {
     for (auto& kv : b->capture) {
       (void)hipSetDevice(kv.first);
       (void)hipStreamDestroy(kv.second);
+      for (hipStream_t q : b->lanes[kv.first]) (void)hipStreamDestroy(q);
+      for (hipEvent_t e : b->events[kv.first]) (void)hipEventDestroy(e);
     }
     for (auto& g : b->graphs) (void)hipGraphExecDestroy(g.exec);
     (void)hipSetDevice(cur);
