@@ -42,7 +42,25 @@ __global__ __launch_bounds__(64) void k_adj_predict(const AdjPredictArgs<T> p) {
     w0[x] = p.w[A + x];
     w1[x] = p.w[p.M + A + x];
   }
+  // receivers inside [A, B] (interior nodes), in receiver order, once
+  constexpr int kList = 64;
+  __shared__ int s_nin, s_x[kList], s_r[kList];
+  if (tid == 0) {
+    int cnt = 0;
+    for (int r = 0; r < p.n_rec; ++r) {
+      const int64_t j = p.rec_node[r];
+      if (j > 0 && j < p.M - 1 && j >= A && j <= B) {
+        if (cnt < kList) {
+          s_x[cnt] = static_cast<int>(j - A);
+          s_r[cnt] = r;
+        }
+        ++cnt;
+      }
+    }
+    s_nin = cnt;
+  }
   __syncthreads();
+  const int nin = s_nin;
   const bool lex = (A == wlo), rex = (B == whi);
   const T zero = T(0);
   T* const row = p.flux + static_cast<int64_t>(2 * i + side) * p.ld;
@@ -63,15 +81,22 @@ __global__ __launch_bounds__(64) void k_adj_predict(const AdjPredictArgs<T> p) {
       w0[x] = v;
     }
     __syncthreads();
-    if (tid == 0) {
-      const int64_t L = p.n_e - s;  // level just computed
-      for (int r = 0; r < p.n_rec; ++r) {
-        const int64_t j = p.rec_node[r];
-        if (j > 0 && j < p.M - 1 && j >= A && j <= B)
-          w0[j - A] = w0[j - A] + p.gtr[static_cast<int64_t>(r) * p.gtr_ld + (L - 1)];
+    if (nin > 0) {
+      if (tid == 0) {
+        const int64_t L = p.n_e - s;  // level just computed
+        if (nin <= kList) {
+          for (int q = 0; q < nin; ++q)
+            w0[s_x[q]] = w0[s_x[q]] + p.gtr[static_cast<int64_t>(s_r[q]) * p.gtr_ld + (L - 1)];
+        } else {
+          for (int r = 0; r < p.n_rec; ++r) {
+            const int64_t j = p.rec_node[r];
+            if (j > 0 && j < p.M - 1 && j >= A && j <= B)
+              w0[j - A] = w0[j - A] + p.gtr[static_cast<int64_t>(r) * p.gtr_ld + (L - 1)];
+          }
+        }
       }
+      __syncthreads();
     }
-    __syncthreads();
     T* t = w0;
     w0 = w1;
     w1 = t;
@@ -99,6 +124,8 @@ struct AdjCtx {
   int sb, se, lane, wv, lmode, rmode;
   uint32_t cnt;  // bit e: element e is stored and interior (enters dJ/dlam)
   bool gen, wr_fa, wr_fb;
+  RecSlots rs;          // the tile's first sources (GEN)
+  const T (*sg)[kMaxSpan];  // their dJ/dtrace samples of this span, by step
 };
 
 // W (or a reversed U) one level: old <- leap(cur) with the general tile's
@@ -207,14 +234,20 @@ __device__ __forceinline__ void adj_step(const AdjUpdateArgs<T>& p,
     adj_chunk<T, MPT, false>(wc, wp, Lw, Rw, p.c2, p.k, 0, 0, 0, T(0), T(0), T(0));
   }
   if (GEN) {
-    for (int r = c.sb; r < c.se; ++r) {
-      const int64_t d = p.src_node[r] - c.base;
+    // receiver sources in list order: the slots (samples staged in LDS),
+    // then any further ones from memory
+    auto inject = [&](int64_t node, T g) {
+      const int64_t d = node - c.base;
       if (d >= 0 && d < MPT) {
-        const T g = p.gtr[static_cast<int64_t>(p.src_id[r]) * p.gtr_ld + (L - 1)];
 #pragma unroll
         for (int e = 0; e < MPT; ++e) wp[e] = (d == e) ? wp[e] + g : wp[e];
       }
-    }
+    };
+#pragma unroll
+    for (int q = 0; q < kRecSlots; ++q)
+      if (q < c.rs.n) inject(c.rs.node[q], c.sg[q][tau]);
+    for (int r = c.sb + kRecSlots; r < c.se; ++r)
+      inject(p.src_node[r], p.gtr[static_cast<int64_t>(p.src_id[r]) * p.gtr_ld + (L - 1)]);
   }
   if (GEN && c.gen) {
     const int rn = c.dl + 1;
@@ -240,6 +273,7 @@ __global__ __launch_bounds__(NT) void k_adj_update(const AdjUpdateArgs<T> p) {
   __shared__ T sAu[kMaxSpan], sBu[kMaxSpan];
   __shared__ T edge[2][4][NW];
   __shared__ double red[NW];
+  __shared__ T sg[GEN ? kRecSlots : 1][kMaxSpan];
 
   const int tid = threadIdx.x;
   const int slot = xcd_tile(blockIdx.x, gridDim.x);
@@ -305,6 +339,17 @@ __global__ __launch_bounds__(NT) void k_adj_update(const AdjUpdateArgs<T> p) {
   }
   c.sb = (GEN && p.src_ptr) ? p.src_ptr[slot] : 0;
   c.se = (GEN && p.src_ptr) ? p.src_ptr[slot + 1] : 0;
+  c.rs = GEN ? load_slots(p.src_node, p.src_id, c.sb, c.se) : RecSlots{0, {}, {}};
+  c.sg = sg;
+  if (GEN) {
+    // dJ/dtrace of the slot sources at levels n_e-1-tau, tau = 0..S-1
+    for (int x = tid; x < kRecSlots * S; x += NT) {
+      const int q = x / S, tau = x - q * S;
+      if (q < c.rs.n)
+        sg[q][tau] = p.gtr[static_cast<int64_t>(c.rs.id[q]) * p.gtr_ld + (p.n_e - tau - 1)];
+    }
+    __syncthreads();
+  }
   uint32_t cnt = 0;
 #pragma unroll
   for (int e = 0; e < MPT; ++e) {

@@ -217,6 +217,44 @@ __device__ __forceinline__ T pick(const T (&v)[MPT], int64_t d) {
   return __builtin_bit_cast(T, acc);
 }
 
+// Up to kRecSlots receivers (or adjoint sources) of one tile, held in
+// wave-uniform registers for the whole span; any further ones are read from
+// memory each step.  Slots keep the list order.
+struct RecSlots {
+  int n;
+  int64_t node[kRecSlots];
+  int32_t id[kRecSlots];
+};
+
+__device__ __forceinline__ RecSlots load_slots(const int64_t* node, const int32_t* id, int b,
+                                               int e) {
+  RecSlots r;
+  r.n = (e - b < kRecSlots) ? e - b : kRecSlots;
+#pragma unroll
+  for (int q = 0; q < kRecSlots; ++q) {
+    const bool h = q < r.n;
+    r.node[q] = h ? node[b + q] : kNoNode;
+    r.id[q] = h ? id[b + q] : 0;
+  }
+  return r;
+}
+
+// *dst = v[e] from the lane where `mine` holds, for a wave-uniform element
+// index e in [LO, HI]: a tree of uniform branches (no per-lane select over
+// the whole array), one masked store at the leaf.
+template <int LO, int HI, typename T, int MPT>
+__device__ __forceinline__ void store_elem(const T (&v)[MPT], int e, T* dst, bool mine) {
+  if constexpr (LO == HI) {
+    if (mine) *dst = v[LO];
+  } else {
+    constexpr int MID = (LO + HI) / 2;
+    if (e <= MID)
+      store_elem<LO, MID>(v, e, dst, mine);
+    else
+      store_elem<MID + 1, HI>(v, e, dst, mine);
+  }
+}
+
 // Value just outside the region: zero data, the input ghost (Eqs. (6)-(7)
 // with a centred flux), or the Dirichlet value of Eq. (3).
 template <typename T>

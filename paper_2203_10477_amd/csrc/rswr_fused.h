@@ -36,7 +36,14 @@ struct FusedCtx {
   T vA, vB;      // lane s: node 0 / node M-1 at level n0+s (or 0 where unused)
   T nq, pq;      // -2 dx and 2 dx, in vector registers
   int64_t base;  // this lane's first node
-  int d0, rb, re, lane, wv;
+  int64_t a;     // the region's first node
+  int tid;
+  int d0, lane, wv;
+  // receivers this tile records: trace row, storing lane (-1: none) and
+  // element (-1: node 0's value, -2: node M-1's value)
+  int nrec;
+  T* rdst[kRecSlots];
+  int rlane[kRecSlots], relem[kRecSlots];
   bool gen;
   bool dirL, dirR;    // this wave's lane 0 / lane 63 borders a Dirichlet node
   bool fdirL, fdirR;  // this wave's left frame holds node 0 / right frame node M-1
@@ -93,7 +100,7 @@ __device__ __forceinline__ void frame_dirichlet(bool dir, const bool (&m)[2], T 
 // keeps the fluxes.  The lane shifts fill the wave's ends with zero: the
 // zero data of a cut region end; input ghosts, Dirichlet values and the
 // neighbouring wave's node replace it where they apply.
-template <typename T, int NT, int MPT, bool GEN, bool HL, bool HR>
+template <typename T, int NT, int MPT, bool GEN, bool REC, bool HL, bool HR>
 __device__ __forceinline__ void fused_step(const UpdateArgs<T>& p,
                                            const FusedCtx<T, NT, MPT>& c,
                                            const T (&cur)[MPT], T (&old)[MPT],
@@ -143,22 +150,23 @@ __device__ __forceinline__ void fused_step(const UpdateArgs<T>& p,
                              rd_lane(c.vA, s + 1));
   else
     step_chunk<T, MPT, false>(cur, old, L, R, p.c2, p.k, 0, 0, T(0), T(0));
-  if (GEN) {
+  if (REC && c.nrec > 0) {  // wave-uniform: this tile records receivers
     const T da = rd_lane(c.vA, s + 1), db = rd_lane(c.vB, s + 1);
-    for (int r = c.rb; r < c.re; ++r) {
-      const int64_t d = p.rec_node[r] - c.base;
-      T* dst = p.traces + static_cast<int64_t>(p.rec_id[r]) * p.trace_ld + p.trace_col0 + s;
-      if (d >= 0 && d < MPT)
-        *dst = pick<T, MPT>(old, d);
-      else if (d == -1 && c.lane == 0 && c.wv == 0 && c.dirL)
-        *dst = da;
-      else if (d == MPT && c.lane == 63 && c.wv == NW - 1 && c.dirR)
-        *dst = db;
+#pragma unroll
+    for (int q = 0; q < kRecSlots; ++q) {
+      if (q < c.nrec) {
+        T* const dst = c.rdst[q] + s;
+        const bool mine = c.tid == c.rlane[q];
+        if (c.relem[q] >= 0)
+          store_elem<0, MPT - 1>(old, c.relem[q], dst, mine);
+        else if (mine)
+          *dst = (c.relem[q] == -1) ? da : db;
+      }
     }
   }
 }
 
-template <typename T, int NT, int MPT, bool GEN, bool HL, bool HR>
+template <typename T, int NT, int MPT, bool GEN, bool REC, bool HL, bool HR>
 __device__ __forceinline__ void fused_run(const UpdateArgs<T>& p, const Tile& tl,
                                           const FusedCtx<T, NT, MPT>& c, int S,
                                           T (&u)[MPT], T (&uo)[MPT]) {
@@ -169,10 +177,10 @@ __device__ __forceinline__ void fused_run(const UpdateArgs<T>& p, const Tile& tl
   if constexpr (HR) frame_load(p, tl.a + TM - 1, tl.window + 1, c.lane, rc, ro);
   int s = 0;
   for (; s + 1 < S; s += 2) {
-    fused_step<T, NT, MPT, GEN, HL, HR>(p, c, u, uo, lc, lo, rc, ro, fl, fr, s);
-    fused_step<T, NT, MPT, GEN, HL, HR>(p, c, uo, u, lo, lc, ro, rc, fl, fr, s + 1);
+    fused_step<T, NT, MPT, GEN, REC, HL, HR>(p, c, u, uo, lc, lo, rc, ro, fl, fr, s);
+    fused_step<T, NT, MPT, GEN, REC, HL, HR>(p, c, uo, u, lo, lc, ro, rc, fl, fr, s + 1);
   }
-  if (s < S) fused_step<T, NT, MPT, GEN, HL, HR>(p, c, u, uo, lc, lo, rc, ro, fl, fr, s);
+  if (s < S) fused_step<T, NT, MPT, GEN, REC, HL, HR>(p, c, u, uo, lc, lo, rc, ro, fl, fr, s);
   if (p.flux_out != nullptr && c.lane < S) {
     if constexpr (HL) p.flux_out[static_cast<int64_t>(2 * tl.fl) * p.ld + c.lane] = fl;
     if constexpr (HR) p.flux_out[static_cast<int64_t>(2 * tl.fr + 1) * p.ld + c.lane] = fr;
@@ -181,7 +189,7 @@ __device__ __forceinline__ void fused_run(const UpdateArgs<T>& p, const Tile& tl
 
 // One tile over S levels: load, step (with the frames its waves carry),
 // store.  `st` is the LDS staging buffer, `edge` the cross-wave slots.
-template <typename T, int NT, int MPT, bool GEN>
+template <typename T, int NT, int MPT, bool GEN, bool REC>
 __device__ __forceinline__ void fused_tile(const UpdateArgs<T>& p, const Tile& tl, int slot,
                                            int S, T* st, T (*edge)[2][NT / 64]) {
   constexpr int NW = NT / 64;
@@ -203,6 +211,8 @@ __device__ __forceinline__ void fused_tile(const UpdateArgs<T>& p, const Tile& t
   c.lane = tid & 63;
   c.wv = __builtin_amdgcn_readfirstlane(tid >> 6);
   c.base = tl.a + static_cast<int64_t>(tid) * MPT;
+  c.a = tl.a;
+  c.tid = tid;
   const bool dirL = tl.lmode == kEndDirichlet, dirR = tl.rmode == kEndDirichlet;
   c.dirL = dirL && c.wv == 0;
   c.dirR = dirR && c.wv == NW - 1;
@@ -233,28 +243,50 @@ __device__ __forceinline__ void fused_tile(const UpdateArgs<T>& p, const Tile& t
   }
   c.d0 = -1000;
   c.gen = false;
-  c.rb = 0;
-  c.re = 0;
   if (GEN) {
     const int64_t d = -c.base;
     c.d0 = (d < -2 || d > MPT + 1) ? -1000 : static_cast<int>(d);
     c.gen = __any(c.d0 >= 0 && c.d0 < MPT) != 0;
-    c.rb = p.rec_ptr ? p.rec_ptr[slot] : 0;
-    c.re = p.rec_ptr ? p.rec_ptr[slot + 1] : 0;
+  }
+  // receivers this tile records (REC instantiations; at most kRecSlots)
+  c.nrec = 0;
+  if (REC && p.rec_ptr) {
+    const int rb = p.rec_ptr[slot], re = p.rec_ptr[slot + 1];
+    c.nrec = re - rb < kRecSlots ? re - rb : kRecSlots;
+#pragma unroll
+    for (int q = 0; q < kRecSlots; ++q) {
+      const bool h = q < c.nrec;
+      const int64_t x = h ? p.rec_node[rb + q] - tl.a : -1000;
+      const int32_t id = h ? p.rec_id[rb + q] : 0;
+      c.rdst[q] = p.traces + static_cast<int64_t>(id) * p.trace_ld + p.trace_col0;
+      if (x >= 0 && x < TM) {
+        c.rlane[q] = static_cast<int>(x) / MPT;
+        c.relem[q] = static_cast<int>(x) % MPT;
+      } else if (x == -1 && dirL) {
+        c.rlane[q] = 0;
+        c.relem[q] = -1;
+      } else if (x == TM && dirR) {
+        c.rlane[q] = NT - 1;
+        c.relem[q] = -2;
+      } else {
+        c.rlane[q] = -1;
+        c.relem[q] = -1;
+      }
+    }
   }
 
   const bool hl = c.wv == 0 && tl.lmode == kEndGhost;
   const bool hr = c.wv == NW - 1 && tl.rmode == kEndGhost;
   if (hl) {
     if (hr)
-      fused_run<T, NT, MPT, GEN, true, true>(p, tl, c, S, u, uo);
+      fused_run<T, NT, MPT, GEN, REC, true, true>(p, tl, c, S, u, uo);
     else
-      fused_run<T, NT, MPT, GEN, true, false>(p, tl, c, S, u, uo);
+      fused_run<T, NT, MPT, GEN, REC, true, false>(p, tl, c, S, u, uo);
   } else {
     if (hr)
-      fused_run<T, NT, MPT, GEN, false, true>(p, tl, c, S, u, uo);
+      fused_run<T, NT, MPT, GEN, REC, false, true>(p, tl, c, S, u, uo);
     else
-      fused_run<T, NT, MPT, GEN, false, false>(p, tl, c, S, u, uo);
+      fused_run<T, NT, MPT, GEN, REC, false, false>(p, tl, c, S, u, uo);
   }
 
   const int64_t rlo = tl.out_lo > tl.a ? tl.out_lo : tl.a;

@@ -4,7 +4,11 @@
 
 namespace rswr {
 
-template <typename T, int NT, int MPT, bool GEN>
+// GEN: general tiles (node 0 inside the region), receivers recorded.
+// REC: a launch whose tiles may record receivers; each work-group takes the
+// recording code path only if its tile has receivers (a uniform branch), so
+// the others run the plain step.  Neither: the plain step only.
+template <typename T, int NT, int MPT, bool GEN, bool REC>
 __global__ __launch_bounds__(NT) void k_fused(const UpdateArgs<T> p) {
   constexpr int NW = NT / 64;
   constexpr int TM = NT * MPT;
@@ -15,22 +19,34 @@ __global__ __launch_bounds__(NT) void k_fused(const UpdateArgs<T> p) {
   const Tile tl = p.tiles[p.tile_idx[slot]];
   const int S = p.span;
   if (S <= 0 || S > kMaxFusedSpan) return;
-  fused_tile<T, NT, MPT, GEN>(p, tl, slot, S, st, edge);
+  if constexpr (GEN) {
+    fused_tile<T, NT, MPT, true, true>(p, tl, slot, S, st, edge);
+  } else if constexpr (REC) {
+    if (p.rec_ptr && p.rec_ptr[slot + 1] > p.rec_ptr[slot])
+      fused_tile<T, NT, MPT, false, true>(p, tl, slot, S, st, edge);
+    else
+      fused_tile<T, NT, MPT, false, false>(p, tl, slot, S, st, edge);
+  } else {
+    fused_tile<T, NT, MPT, false, false>(p, tl, slot, S, st, edge);
+  }
 }
 
 template <typename T>
-hipError_t launch_fused(const UpdateArgs<T>& a, int threads, int per_thread, bool general,
+hipError_t launch_fused(const UpdateArgs<T>& a, int threads, int per_thread, int kind,
                         hipStream_t s) {
   if (a.n_tiles <= 0) return hipSuccess;
 #define RSWR_LAUNCH(NT_, MPT_)                                                        \
   if (threads == NT_ && per_thread == MPT_) {                                       \
     if constexpr (sizeof(T) == 8 && MPT_ > 22) return hipErrorInvalidValue;        \
     else {                                                                          \
-      if (general)                                                                  \
-        hipLaunchKernelGGL((k_fused<T, NT_, MPT_, true>), dim3(a.n_tiles), dim3(NT_), \
-                           0, s, a);                                                \
+      if (kind == kFusedGeneral)                                                    \
+        hipLaunchKernelGGL((k_fused<T, NT_, MPT_, true, true>), dim3(a.n_tiles),    \
+                           dim3(NT_), 0, s, a);                                     \
+      else if (kind == kFusedRec)                                                   \
+        hipLaunchKernelGGL((k_fused<T, NT_, MPT_, false, true>), dim3(a.n_tiles),   \
+                           dim3(NT_), 0, s, a);                                     \
       else                                                                          \
-        hipLaunchKernelGGL((k_fused<T, NT_, MPT_, false>), dim3(a.n_tiles),         \
+        hipLaunchKernelGGL((k_fused<T, NT_, MPT_, false, false>), dim3(a.n_tiles),  \
                            dim3(NT_), 0, s, a);                                     \
       return hipGetLastError();                                                     \
     }                                                                               \
@@ -40,9 +56,9 @@ hipError_t launch_fused(const UpdateArgs<T>& a, int threads, int per_thread, boo
   return hipErrorInvalidValue;
 }
 
-template hipError_t launch_fused<float>(const UpdateArgs<float>&, int, int, bool,
+template hipError_t launch_fused<float>(const UpdateArgs<float>&, int, int, int,
                                         hipStream_t);
-template hipError_t launch_fused<double>(const UpdateArgs<double>&, int, int, bool,
+template hipError_t launch_fused<double>(const UpdateArgs<double>&, int, int, int,
                                          hipStream_t);
 
 }  // namespace rswr

@@ -411,23 +411,50 @@ rswr::UpdateArgs<T> update_args(const rswr_plan_s& p, const DevTables& d,
 // The two update launches of one span: general tiles (and, in a solve, the
 // tiles holding receivers) through the general kernel, the rest through the
 // plain one.
+// The two update launches of one span on the two-launch path: general
+// tiles (and, in a solve, the tiles holding receivers) through the general
+// kernel, the rest through the plain one.
 template <typename T>
 hipError_t launch_update_pair(const rswr_plan_s& p, rswr::UpdateArgs<T> a,
                               const int32_t* gen_idx, int32_t n_gen,
-                              const int32_t* fast_idx, int32_t n_fast, hipStream_t s,
-                              bool fused = false) {
-  auto launch = fused ? rswr::launch_fused<T> : rswr::launch_update<T>;
+                              const int32_t* fast_idx, int32_t n_fast, hipStream_t s) {
   if (n_gen > 0) {
     a.tile_idx = gen_idx;
     a.n_tiles = n_gen;
-    hipError_t e = launch(a, p.threads, p.per_thread, true, s);
+    hipError_t e = rswr::launch_update<T>(a, p.threads, p.per_thread, true, s);
     if (e != hipSuccess) return e;
   }
   if (n_fast > 0) {
     a.tile_idx = fast_idx;
     a.n_tiles = n_fast;
     a.rec_ptr = nullptr;
-    return launch(a, p.threads, p.per_thread, false, s);
+    return rswr::launch_update<T>(a, p.threads, p.per_thread, false, s);
+  }
+  return hipSuccess;
+}
+
+// One fused span: the general tiles, then every other tile in one launch
+// (`a.rec_ptr`: CSR over the general list then the plain list; tiles with
+// receivers take the recording path inside that launch).
+template <typename T>
+hipError_t launch_fused_span(const rswr_plan_s& p, rswr::UpdateArgs<T> a,
+                             const int32_t* gen_idx, int32_t n_gen, const int32_t* fast_idx,
+                             int32_t n_fast, hipStream_t s) {
+  const int32_t* rec_ptr = a.rec_ptr;
+  hipError_t e = hipSuccess;
+  if (n_gen > 0) {
+    a.tile_idx = gen_idx;
+    a.n_tiles = n_gen;
+    if ((e = rswr::launch_fused<T>(a, p.threads, p.per_thread, rswr::kFusedGeneral, s)) !=
+        hipSuccess)
+      return e;
+  }
+  if (n_fast > 0) {
+    a.tile_idx = fast_idx;
+    a.n_tiles = n_fast;
+    a.rec_ptr = rec_ptr ? rec_ptr + n_gen : nullptr;
+    return rswr::launch_fused<T>(a, p.threads, p.per_thread,
+                                 rec_ptr ? rswr::kFusedRec : rswr::kFusedPlain, s);
   }
   return hipSuccess;
 }
@@ -448,12 +475,15 @@ WsLayout ws_layout(const rswr_plan_s& p, int32_t n_rec) {
   off += round_up(2 * size_t(p.M) * b, 256);
   w.flux = off;
   off += round_up(size_t(std::max(p.N - 1, 1)) * 2 * p.flux_ld * b, 256);
+  // launch lists: a tile may be listed once per group of receivers, so up
+  // to nt + n_rec entries
+  const size_t nl = nt + size_t(std::max(n_rec, 0));
   w.gen_idx = off;
-  off += round_up(std::max<size_t>(nt, 1) * sizeof(int32_t), 256);
+  off += round_up(std::max<size_t>(nl, 1) * sizeof(int32_t), 256);
   w.fast_idx = off;
-  off += round_up(std::max<size_t>(nt, 1) * sizeof(int32_t), 256);
+  off += round_up(std::max<size_t>(nl, 1) * sizeof(int32_t), 256);
   w.rec_ptr = off;
-  off += round_up((nt + 1) * sizeof(int32_t), 256);
+  off += round_up((nl + 1) * sizeof(int32_t), 256);
   w.rec_node = off;
   off += round_up(size_t(std::max(n_rec, 1)) * sizeof(int64_t), 256);
   w.rec_id = off;
@@ -521,8 +551,12 @@ rswr_status_t enqueue_solve(rswr_plan_s* p, const DevTables& d, void* state,
       ua.trace_ld = n_steps;
       ua.trace_col0 = lev - n0;
     }
-    RSWR_HIP(launch_update_pair<T>(*p, ua, lists.gen, lists.n_gen, lists.fast, lists.n_fast,
-                                   s, p->fused));
+    if (p->fused)
+      RSWR_HIP(launch_fused_span<T>(*p, ua, lists.gen, lists.n_gen, lists.fast, lists.n_fast,
+                                    s));
+    else
+      RSWR_HIP(launch_update_pair<T>(*p, ua, lists.gen, lists.n_gen, lists.fast, lists.n_fast,
+                                     s));
     lev += S;
     std::swap(x, y);
   }
@@ -1028,8 +1062,11 @@ rswr_status_t rswr_span(rswr_plan_t p, const void* state_in, const void* f_a, co
       ua.flux = nullptr;
       ua.flux_out = static_cast<T*>(flux);
     }
+    if (p->fused)
+      return launch_fused_span<T>(*p, ua, d->idx, p->n_gen, d->idx + p->n_gen,
+                                  n_all - p->n_gen, s);
     return launch_update_pair<T>(*p, ua, d->idx, p->n_gen, d->idx + p->n_gen,
-                                 n_all - p->n_gen, s, p->fused);
+                                 n_all - p->n_gen, s);
   };
   const hipError_t e = p->dtype == RSWR_F64 ? run(double{}) : run(float{});
   if (e != hipSuccess) return hip_fail(e, "span launch");
@@ -1095,17 +1132,32 @@ rswr_status_t rswr_solve(rswr_plan_t p, void* state, const void* f_a, const void
         }
     std::vector<int32_t> gen, fast, ptr(1, 0), id;
     std::vector<int64_t> node;
-    for (int32_t t = 0; t < n_all; ++t) {
-      if (p->tiles[t].general || !per[t].empty()) {
-        gen.push_back(t);
-        for (int32_t r : per[t]) {
-          id.push_back(r);
-          node.push_back(rec_idx[r]);
+    // two-launch path: receiver tiles run general, the CSR covers the
+    // general list.  Fused path: general tiles, then all others; the CSR
+    // covers both lists.
+    // a fused-path tile records at most kRecSlots receivers per launched
+    // copy: a tile holding more is listed once per group (the copies store
+    // the same state bits)
+    auto add = [&](std::vector<int32_t>& list, int32_t t) {
+      const size_t n = per[t].size();
+      const size_t g = p->fused ? size_t(rswr::kRecSlots) : std::max<size_t>(n, 1);
+      for (size_t b = 0; b == 0 || b < n; b += g) {
+        list.push_back(t);
+        for (size_t r = b; r < std::min(n, b + g); ++r) {
+          id.push_back(per[t][r]);
+          node.push_back(rec_idx[per[t][r]]);
         }
         ptr.push_back(static_cast<int32_t>(id.size()));
-      } else {
-        fast.push_back(t);
       }
+    };
+    for (int32_t t = 0; t < n_all; ++t)
+      if (p->tiles[t].general || (!p->fused && !per[t].empty())) add(gen, t);
+    for (int32_t t = 0; t < n_all; ++t) {
+      if (p->tiles[t].general) continue;
+      if (p->fused)
+        add(fast, t);
+      else if (per[t].empty())
+        fast.push_back(t);
     }
     if (!gen.empty())
       RSWR_HIP(hipMemcpyAsync(ws + L.gen_idx, gen.data(), gen.size() * sizeof(int32_t),
@@ -1119,9 +1171,9 @@ rswr_status_t rswr_solve(rswr_plan_t p, void* state, const void* f_a, const void
                             hipMemcpyHostToDevice, s));
     RSWR_HIP(hipMemcpyAsync(ws + L.rec_id, id.data(), id.size() * sizeof(int32_t),
                             hipMemcpyHostToDevice, s));
+    lists.n_gen = static_cast<int32_t>(gen.size());
     lists.gen = reinterpret_cast<const int32_t*>(ws + L.gen_idx);
     lists.fast = reinterpret_cast<const int32_t*>(ws + L.fast_idx);
-    lists.n_gen = static_cast<int32_t>(gen.size());
     lists.n_fast = static_cast<int32_t>(fast.size());
     lists.rec_ptr = reinterpret_cast<const int32_t*>(ws + L.rec_ptr);
     lists.rec_node = reinterpret_cast<const int64_t*>(ws + L.rec_node);

@@ -12,6 +12,9 @@ constexpr int kMaxSpan = 256;
 // Prediction frame of the fused span: 2 * kFrameHalf nodes, two per lane.
 constexpr int kFrameHalf = 64;
 constexpr int kMaxFusedSpan = kFrameHalf - 1;
+// Receivers one launched tile of the fused span records (the host repeats a
+// tile holding more, one copy per group); adjoint sources held in registers.
+constexpr int kRecSlots = 4;
 
 // Sentinel for "no left-input ghost in this tile".
 constexpr int64_t kNoNode = INT64_MIN;
@@ -169,9 +172,12 @@ hipError_t launch_update(const UpdateArgs<T>& a, int threads, int per_thread,
                          bool general, hipStream_t s);
 // Fused span (rswr_fused.hip): predict folded into the update; needs
 // 1 <= span <= kMaxFusedSpan and inputs only at region ends.
+// kFusedRec: a launch in which some tiles record receivers (CSR rec_ptr
+// over its slots); kFusedGeneral: general tiles.
+enum { kFusedPlain = 0, kFusedRec = 1, kFusedGeneral = 2 };
 template <typename T>
-hipError_t launch_fused(const UpdateArgs<T>& a, int threads, int per_thread,
-                        bool general, hipStream_t s);
+hipError_t launch_fused(const UpdateArgs<T>& a, int threads, int per_thread, int kind,
+                        hipStream_t s);
 // Batched fused span: one persistent launch over the items with `grid`
 // work-groups (at most the items); fused_batch_capacity gives the kernel's
 // resident work-groups on the current device (0: shape not built).

@@ -99,6 +99,7 @@ struct UpdateCtx {
   int64_t base;
   int dl, d0;
   int rb, re, lane, wv;
+  RecSlots rs;  // the tile's first receivers (GEN)
   int lmode, rmode;
   bool gen;
 };
@@ -134,16 +135,20 @@ __device__ __forceinline__ void one_step(const UpdateArgs<T>& p,
     step_chunk<T, MPT, false>(cur, old, L, R, p.c2, p.k, 0, 0, T(0), T(0));
   }
   if (GEN) {
-    for (int r = c.rb; r < c.re; ++r) {
-      const int64_t d = p.rec_node[r] - c.base;
-      T* dst = p.traces + static_cast<int64_t>(p.rec_id[r]) * p.trace_ld + p.trace_col0 + s;
+    auto record = [&](int64_t node, int32_t id) {
+      const int64_t d = node - c.base;
+      T* dst = p.traces + static_cast<int64_t>(id) * p.trace_ld + p.trace_col0 + s;
       if (d >= 0 && d < MPT)
         *dst = pick<T, MPT>(old, d);
       else if (d == -1 && c.lane == 0 && c.wv == 0 && c.lmode == kEndDirichlet)
         *dst = c.sA[s + 1];
       else if (d == MPT && c.lane == 63 && c.wv == NW - 1 && c.rmode == kEndDirichlet)
         *dst = c.sB[s + 1];
-    }
+    };
+#pragma unroll
+    for (int q = 0; q < kRecSlots; ++q)
+      if (q < c.rs.n) record(c.rs.node[q], c.rs.id[q]);
+    for (int r = c.rb + kRecSlots; r < c.re; ++r) record(p.rec_node[r], p.rec_id[r]);
   }
 }
 
@@ -216,6 +221,7 @@ __global__ __launch_bounds__(NT) void k_update(const UpdateArgs<T> p) {
     c.rb = p.rec_ptr ? p.rec_ptr[slot] : 0;
     c.re = p.rec_ptr ? p.rec_ptr[slot + 1] : 0;
   }
+  c.rs = GEN ? load_slots(p.rec_node, p.rec_id, c.rb, c.re) : RecSlots{0, {}, {}};
   const int64_t rlo = tl.out_lo > tl.a ? tl.out_lo : tl.a;
   const int64_t rhi = tl.out_hi < tl.a + TM - 1 ? tl.out_hi : tl.a + TM - 1;
   const int xlo = static_cast<int>(rlo - tl.a);

@@ -204,3 +204,27 @@ def test_large_fp32_fused_span_every_shape():
         gf = host(fl).reshape(-1, plan.flux_ld)
         assert np.array_equal(gf[rows, :S], ref_flux.reshape(-1, base.flux_ld)[rows, :S])
     assert n_fused >= 8
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_fused_many_receivers_in_one_tile(dtype):
+    """Eleven receivers inside one tile (the tile is launched once per group
+    of four), a repeated receiver and both Dirichlet nodes: traces and state
+    bitwise against the oracle."""
+    M, N, P, n_steps = 4097, 8, 64, 300
+    say("many-receivers", dtype)
+    plan = rs.Plan(M, N, P, dtype=dtype)
+    assert plan.info["fused"] == 1
+    lay = lay_of(plan)
+    npdt = NP[dtype]
+    st0, fa, fb = busy(M, n_steps, seed=21)
+    st0, fa, fb = st0.astype(npdt), fa.astype(npdt), fb.astype(npdt)
+    rec = np.array([0, 100, 101, 102, 103, 104, 105, 106, 107, 108, 109, 104, 2500,
+                    M - 1], np.int64)
+    ref, tr_ref, _ = oracle.rswr(lay, plan.info["lambda"], plan.info["dx"], fa, fb, n_steps,
+                                 span=plan.span, state=st0, rec=rec)
+    st = dev(st0, dtype)
+    tr = rs.rswr_solve(plan, st, dev(fa, dtype), dev(fb, dtype), n_steps, receivers=rec)
+    torch.cuda.synchronize()
+    assert np.array_equal(host(st), ref)
+    assert np.array_equal(host(tr), tr_ref)
