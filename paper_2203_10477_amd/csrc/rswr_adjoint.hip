@@ -17,13 +17,136 @@
 namespace rswr {
 
 // ---------------------------------------------------------------------------
-// Adjoint predict: the light-cone trapezoid of W around each output node,
-// zero input flux at the window's own inputs, receiver sources injected in
-// receiver order after each level (the order the single-domain reverse sweep
-// uses).
+// Adjoint predict: W's flux at each output node over shat levels, zero input
+// flux at the window's own inputs, receiver sources injected in receiver
+// order after each level (the order the single-domain reverse sweep uses).
+// One wave per (interface, side) carries a 128-node frame around the output
+// node o, two nodes per lane, in registers: the sample at o over shat <=
+// light-cone-limit levels reads only [o-shat, o+shat] (the window's input
+// ends lie farther away), so the frame runs the plain stencil with the data
+// mirrored into the window, W = 0 on nodes 0 and M-1, and the sources of
+// [o-shat, o+shat] inside the window: the same samples as the whole-window
+// prediction, bit for bit.  Each source's samples for the span sit one per
+// lane (kAdjFrameSrc of them in registers, further ones read each step).
 // ---------------------------------------------------------------------------
+constexpr int kAdjFrameSrc = 8;
+
 template <typename T>
-__global__ __launch_bounds__(64) void k_adj_predict(const AdjPredictArgs<T> p) {
+__global__ __launch_bounds__(64) void k_adj_predict_frame(const AdjPredictArgs<T> p) {
+  const int i = blockIdx.x >> 1, side = blockIdx.x & 1;
+  const int w = i + side;
+  const int64_t o = (side == 0) ? p.lo[i + 1] : p.hi[i];
+  const int64_t wlo = p.lo[w], whi = p.hi[w];
+  const int shat = p.shat;
+  const int lane = threadIdx.x;
+  const int64_t A = (o - shat > wlo) ? o - shat : wlo;
+  const int64_t B = (o + shat < whi) ? o + shat : whi;
+  const int64_t base = o - kFrameHalf;
+  // frame: cur = W^{L+1}, old = W^{L+2}, lane holds base + 2 lane + e
+  T cur[2], old[2];
+  bool dir[2];
+#pragma unroll
+  for (int e = 0; e < 2; ++e) {
+    const int64_t x = base + 2 * lane + e;
+    int64_t j = (x < wlo) ? 2 * wlo - x : ((x > whi) ? 2 * whi - x : x);
+    j = j < wlo ? wlo : (j > whi ? whi : j);
+    cur[e] = p.w[p.M + j];
+    old[e] = p.w[j];
+    dir[e] = (x == 0) || (x == p.M - 1);
+  }
+  // sources in [A, B] (interior nodes), in receiver order: frame offset and
+  // the span's samples (lane s: level n_e - s, column n_e - s - 1)
+  // (64 receivers checked at once, one per lane; the hits taken in order)
+  int nsrc = 0;
+  int sx[kAdjFrameSrc];
+  T sg[kAdjFrameSrc];
+#pragma unroll
+  for (int q = 0; q < kAdjFrameSrc; ++q) {
+    sx[q] = 0;
+    sg[q] = T(0);
+  }
+  int first_extra = p.n_rec;
+  for (int r0 = 0; r0 < p.n_rec && first_extra == p.n_rec; r0 += 64) {
+    const int r = r0 + lane;
+    const int64_t j = (r < p.n_rec) ? p.rec_node[r] : int64_t(-1);
+    const bool hit = j > 0 && j < p.M - 1 && j >= A && j <= B;
+    uint64_t m = __ballot(hit);
+    while (m != 0) {
+      const int b = __builtin_ctzll(m);
+      m &= m - 1;
+      if (nsrc == kAdjFrameSrc) {
+        first_extra = r0 + b;
+        break;
+      }
+      const int x = __builtin_amdgcn_readlane(static_cast<int>(j - base), b);
+      const T* g = p.gtr + static_cast<int64_t>(r0 + b) * p.gtr_ld + (p.n_e - 1);
+      const T gs = (lane < shat) ? g[-lane] : T(0);
+#pragma unroll
+      for (int q = 0; q < kAdjFrameSrc; ++q) {
+        if (q == nsrc) {
+          sx[q] = x;
+          sg[q] = gs;
+        }
+      }
+      ++nsrc;
+    }
+  }
+#pragma unroll
+  for (int e = 0; e < 2; ++e) {
+    cur[e] = in_vgpr(cur[e]);
+    old[e] = in_vgpr(old[e]);
+  }
+#pragma unroll
+  for (int q = 0; q < kAdjFrameSrc; ++q) sg[q] = in_vgpr(sg[q]);
+
+  T fl = T(0);
+  for (int s = 0; s < shat; ++s) {
+    const T l1 = lane_shift_z<kWaveShr1>(cur[1]);
+    const T r0 = lane_shift_z<kWaveShl1>(cur[0]);
+    const T f = rd_lane((cur[1] - l1) * p.r, kFrameHalf / 2);
+    fl = (lane == s) ? f : fl;
+    if (s == shat - 1) break;
+    T n0 = leap(p.c2, p.k, l1, cur[0], cur[1], old[0]);
+    T n1 = leap(p.c2, p.k, cur[0], cur[1], r0, old[1]);
+    n0 = dir[0] ? T(0) : n0;
+    n1 = dir[1] ? T(0) : n1;
+#pragma unroll
+    for (int q = 0; q < kAdjFrameSrc; ++q) {
+      if (q < nsrc) {
+        const T g = rd_lane(sg[q], s);
+        const int sl = sx[q] >> 1;
+        if (sx[q] & 1)
+          n1 = (lane == sl) ? n1 + g : n1;
+        else
+          n0 = (lane == sl) ? n0 + g : n0;
+      }
+    }
+    if (first_extra < p.n_rec) {
+      const int64_t L = p.n_e - s;  // level just computed
+      for (int r = first_extra; r < p.n_rec; ++r) {
+        const int64_t j = p.rec_node[r];
+        if (j > 0 && j < p.M - 1 && j >= A && j <= B) {
+          const T g = p.gtr[static_cast<int64_t>(r) * p.gtr_ld + (L - 1)];
+          const int x = static_cast<int>(j - base);
+          if (x & 1)
+            n1 = (lane == (x >> 1)) ? n1 + g : n1;
+          else
+            n0 = (lane == (x >> 1)) ? n0 + g : n0;
+        }
+      }
+    }
+    old[0] = cur[0];
+    old[1] = cur[1];
+    cur[0] = n0;
+    cur[1] = n1;
+  }
+  if (lane < shat) p.flux[static_cast<int64_t>(2 * i + side) * p.ld + lane] = fl;
+}
+
+// The same prediction for spans beyond the frame: the light-cone trapezoid
+// around o in LDS (window ends inside it keep their exact treatment).
+template <typename T>
+__global__ __launch_bounds__(64) void k_adj_predict_lds(const AdjPredictArgs<T> p) {
   extern __shared__ unsigned char smem_raw[];
   T* const sm = reinterpret_cast<T*>(smem_raw);
   const int i = blockIdx.x >> 1, side = blockIdx.x & 1;
@@ -42,25 +165,7 @@ __global__ __launch_bounds__(64) void k_adj_predict(const AdjPredictArgs<T> p) {
     w0[x] = p.w[A + x];
     w1[x] = p.w[p.M + A + x];
   }
-  // receivers inside [A, B] (interior nodes), in receiver order, once
-  constexpr int kList = 64;
-  __shared__ int s_nin, s_x[kList], s_r[kList];
-  if (tid == 0) {
-    int cnt = 0;
-    for (int r = 0; r < p.n_rec; ++r) {
-      const int64_t j = p.rec_node[r];
-      if (j > 0 && j < p.M - 1 && j >= A && j <= B) {
-        if (cnt < kList) {
-          s_x[cnt] = static_cast<int>(j - A);
-          s_r[cnt] = r;
-        }
-        ++cnt;
-      }
-    }
-    s_nin = cnt;
-  }
   __syncthreads();
-  const int nin = s_nin;
   const bool lex = (A == wlo), rex = (B == whi);
   const T zero = T(0);
   T* const row = p.flux + static_cast<int64_t>(2 * i + side) * p.ld;
@@ -81,22 +186,15 @@ __global__ __launch_bounds__(64) void k_adj_predict(const AdjPredictArgs<T> p) {
       w0[x] = v;
     }
     __syncthreads();
-    if (nin > 0) {
-      if (tid == 0) {
-        const int64_t L = p.n_e - s;  // level just computed
-        if (nin <= kList) {
-          for (int q = 0; q < nin; ++q)
-            w0[s_x[q]] = w0[s_x[q]] + p.gtr[static_cast<int64_t>(s_r[q]) * p.gtr_ld + (L - 1)];
-        } else {
-          for (int r = 0; r < p.n_rec; ++r) {
-            const int64_t j = p.rec_node[r];
-            if (j > 0 && j < p.M - 1 && j >= A && j <= B)
-              w0[j - A] = w0[j - A] + p.gtr[static_cast<int64_t>(r) * p.gtr_ld + (L - 1)];
-          }
-        }
+    if (tid == 0) {
+      const int64_t L = p.n_e - s;  // level just computed
+      for (int r = 0; r < p.n_rec; ++r) {
+        const int64_t j = p.rec_node[r];
+        if (j > 0 && j < p.M - 1 && j >= A && j <= B)
+          w0[j - A] = w0[j - A] + p.gtr[static_cast<int64_t>(r) * p.gtr_ld + (L - 1)];
       }
-      __syncthreads();
     }
+    __syncthreads();
     T* t = w0;
     w0 = w1;
     w1 = t;
@@ -343,10 +441,12 @@ __global__ __launch_bounds__(NT) void k_adj_update(const AdjUpdateArgs<T> p) {
   c.sg = sg;
   if (GEN) {
     // dJ/dtrace of the slot sources at levels n_e-1-tau, tau = 0..S-1
-    for (int x = tid; x < kRecSlots * S; x += NT) {
-      const int q = x / S, tau = x - q * S;
-      if (q < c.rs.n)
-        sg[q][tau] = p.gtr[static_cast<int64_t>(c.rs.id[q]) * p.gtr_ld + (p.n_e - tau - 1)];
+#pragma unroll
+    for (int q = 0; q < kRecSlots; ++q) {
+      if (q < c.rs.n) {
+        const T* g = p.gtr + static_cast<int64_t>(c.rs.id[q]) * p.gtr_ld + (p.n_e - 1);
+        for (int tau = tid; tau < S; tau += NT) sg[q][tau] = g[-tau];
+      }
     }
     __syncthreads();
   }
@@ -438,8 +538,12 @@ __global__ __launch_bounds__(256) void k_fill(T* __restrict__ dst, T v, int64_t 
 template <typename T>
 hipError_t launch_adj_predict(const AdjPredictArgs<T>& a, int shmem_nodes, hipStream_t s) {
   if (a.N < 2) return hipSuccess;
-  const size_t shm = static_cast<size_t>(2 * shmem_nodes) * sizeof(T);
-  hipLaunchKernelGGL(k_adj_predict<T>, dim3(2 * (a.N - 1)), dim3(64), shm, s, a);
+  if (a.shat <= kMaxFusedSpan) {
+    hipLaunchKernelGGL(k_adj_predict_frame<T>, dim3(2 * (a.N - 1)), dim3(64), 0, s, a);
+  } else {
+    const size_t shm = static_cast<size_t>(2 * shmem_nodes) * sizeof(T);
+    hipLaunchKernelGGL(k_adj_predict_lds<T>, dim3(2 * (a.N - 1)), dim3(64), shm, s, a);
+  }
   return hipGetLastError();
 }
 

@@ -69,6 +69,15 @@ __device__ __forceinline__ void frame_load(const UpdateArgs<T>& p, int64_t o, in
   }
 }
 
+// Complete loads issued before the step loop: a wait inside the loop would
+// also wait for every store issued there (the vector memory counter counts
+// both), so the values are settled in registers first.
+template <typename T>
+__device__ __forceinline__ void settle(T (&v)[2]) {
+  v[0] = in_vgpr(v[0]);
+  v[1] = in_vgpr(v[1]);
+}
+
 // One level of a frame: returns the centred flux at the output node (lane
 // kFrameHalf/2, element 0) at the current level and writes the next level
 // over `old`.
@@ -175,6 +184,16 @@ __device__ __forceinline__ void fused_run(const UpdateArgs<T>& p, const Tile& tl
   T fl = T(0), fr = T(0);
   if constexpr (HL) frame_load(p, tl.a, tl.window - 1, c.lane, lc, lo);
   if constexpr (HR) frame_load(p, tl.a + TM - 1, tl.window + 1, c.lane, rc, ro);
+  if constexpr (GEN || REC) {  // these step loops store: see settle()
+    if constexpr (HL) {
+      settle(lc);
+      settle(lo);
+    }
+    if constexpr (HR) {
+      settle(rc);
+      settle(ro);
+    }
+  }
   int s = 0;
   for (; s + 1 < S; s += 2) {
     fused_step<T, NT, MPT, GEN, REC, HL, HR>(p, c, u, uo, lc, lo, rc, ro, fl, fr, s);
@@ -238,8 +257,8 @@ __device__ __forceinline__ void fused_tile(const UpdateArgs<T>& p, const Tile& t
     T a = T(0), b = T(0);
     if ((GEN || dirL || fA) && l <= S) a = (l == 0) ? p.state_in[p.M] : p.fa[p.n0 + l];
     if ((GEN || dirR || fB) && l <= S) b = (l == 0) ? p.state_in[2 * p.M - 1] : p.fb[p.n0 + l];
-    c.vA = a;
-    c.vB = b;
+    c.vA = (GEN || REC) ? in_vgpr(a) : a;  // see settle()
+    c.vB = (GEN || REC) ? in_vgpr(b) : b;
   }
   c.d0 = -1000;
   c.gen = false;
