@@ -123,15 +123,16 @@ def _candidates(prob, dtype, span):
 
 
 def time_batch(plans, probs, n_steps, reps=3):
-    """Microseconds of one rswr_batch_solve of `plans` (n_steps each)."""
+    """Microseconds of one rswr_batch_solve of `plans` (n_steps each: an int
+    or one per problem)."""
     from . import Batch, rswr_batch_solve
     b = Batch(plans)
     dev = "cuda"
+    ns = list(n_steps) if hasattr(n_steps, "__len__") else [int(n_steps)] * len(plans)
     st = [torch.zeros(2, p.M, dtype=p.dtype, device=dev) for p in plans]
-    fa = [torch.as_tensor(q.fa[:n_steps + 1], dtype=p.dtype, device=dev)
-          for q, p in zip(probs, plans)]
-    fb = [torch.zeros(n_steps + 1, dtype=p.dtype, device=dev) for p in plans]
-    ns = [n_steps] * len(plans)
+    fa = [torch.as_tensor(q.fa[:n + 1], dtype=p.dtype, device=dev)
+          for q, p, n in zip(probs, plans, ns)]
+    fb = [torch.zeros(n + 1, dtype=p.dtype, device=dev) for p, n in zip(plans, ns)]
     ws = torch.empty(b.workspace_bytes(), dtype=torch.uint8, device=dev)
     rswr_batch_solve(b, st, fa, fb, ns, ws)
     torch.cuda.synchronize()
@@ -146,22 +147,32 @@ def time_batch(plans, probs, n_steps, reps=3):
 
 
 def autotune_batch(probs, dtype=torch.float32, sample=16, spans_timed=4, slack=1.5,
-                   measure=True):
+                   measure=True, refine=True):
     """Tile shape per size class for a batch of problems.
 
     Every problem gets the span batch_span().  Within a size class, the shapes
     that run the fused span for every problem of a sample, and whose computed
     nodes stay within `slack` times the least, are timed as one batched solve
     of the sample over `spans_timed` spans; the fastest wins (measure=False:
-    the least computed nodes wins).  Returns (tiles per problem, spans per
-    problem, {class: (shape, {shape: microseconds})})."""
+    the least computed nodes wins).  With `refine`, each class's shortlist is
+    then tried again in the complete batched solve (classes run side by side
+    there), class by class, keeping a change only if the whole solve gets
+    faster.  Returns (tiles per problem, spans per problem, {class: (shape,
+    {shape: microseconds})})."""
     spans = [batch_span(p, dtype) for p in probs]
     classes = {}
     for i, p in enumerate(probs):
         classes.setdefault(size_class(p), []).append(i)
     tiles = [None] * len(probs)
-    report = {}
+    report, shortlists = {}, {}
     g = np.random.default_rng(0)
+
+    def fix_unfused(tl):
+        # a shape chosen for a sample may not fuse every problem of its class
+        for i, p in enumerate(probs):
+            if not _plan_for(p, dtype, tl[i], spans[i]).info["fused"]:
+                cand = _candidates(p, dtype, spans[i])
+                tl[i] = min(cand, key=cand.get)
     for c, idx in sorted(classes.items()):
         pick = idx if len(idx) <= sample else sorted(g.choice(idx, sample, replace=False))
         work = None
@@ -182,13 +193,31 @@ def autotune_batch(probs, dtype=torch.float32, sample=16, spans_timed=4, slack=1
         else:
             best = min(shortlist, key=lambda k: work[k])
         report[c] = (best, times)
+        shortlists[c] = shortlist
         for i in idx:
             tiles[i] = best
-    # a shape chosen for the sample may not fuse every problem of its class
-    for i, p in enumerate(probs):
-        if not _plan_for(p, dtype, tiles[i], spans[i]).info["fused"]:
-            cand = _candidates(p, dtype, spans[i])
-            tiles[i] = min(cand, key=cand.get)
+    fix_unfused(tiles)
+    if measure and refine:
+        n_steps = [p.n_steps for p in probs]
+
+        def whole(tl):
+            plans = [_plan_for(p, dtype, tl[i], spans[i]) for i, p in enumerate(probs)]
+            return min(time_batch(plans, probs, n_steps, reps=2) for _ in range(2))
+
+        cur = whole(tiles)
+        order = sorted(classes, key=lambda c: -sum(probs[i].M for i in classes[c]))
+        for c in order:
+            for sh in shortlists[c]:
+                if sh == report[c][0]:
+                    continue
+                trial = list(tiles)
+                for i in classes[c]:
+                    trial[i] = sh
+                fix_unfused(trial)
+                tt = whole(trial)
+                if tt < cur:
+                    cur, tiles = tt, trial
+                    report[c] = (sh, report[c][1])
     return tiles, spans, report
 
 
