@@ -222,8 +222,12 @@ struct AdjCtx {
   int sb, se, lane, wv, lmode, rmode;
   uint32_t cnt;  // bit e: element e is stored and interior (enters dJ/dlam)
   bool gen, wr_fa, wr_fb;
-  RecSlots rs;          // the tile's first sources (GEN)
+  RecSlots rs;          // the tile's first sources (GEN, SRC)
   const T (*sg)[kMaxSpan];  // their dJ/dtrace samples of this span, by step
+  // SRC, all wave-uniform: the slot sources' wave, lane and element, and
+  // those of nodes 1 and M-2 (index 0 / 1; wave -1: not in this tile)
+  int swv[kRecSlots], slane[kRecSlots], selem[kRecSlots];
+  int gwv[2], glane[2], gelem[2];
 };
 
 // W (or a reversed U) one level: old <- leap(cur) with the general tile's
@@ -274,12 +278,15 @@ __device__ __forceinline__ void lap_and_reverse(const T (&wn)[MPT], const T (&uc
   }
 }
 
-template <typename T, int NT, int MPT, bool GEN>
+// GEN: general tiles (per-element treatments at the window's own ends).
+// SRC: plain tiles holding sources or storing nodes 1 / M-2.  Both inject
+// the sources and write dJ/df; neither: the plain step.
+template <typename T, int NT, int MPT, bool GEN, bool SRC>
 __device__ __forceinline__ void adj_step(const AdjUpdateArgs<T>& p,
                                          const AdjCtx<T, NT, MPT>& c,
                                          const T (&wc)[MPT], T (&wp)[MPT],
-                                         const T (&uc)[MPT], T (&up)[MPT], int tau,
-                                         int S, double& acc) {
+                                         const T (&uc)[MPT], T (&up)[MPT], T (&gf)[2],
+                                         int tau, int S, double& acc) {
   constexpr int NW = NT / 64;
   const int par = tau & 1;
   const int64_t L = p.n_e - tau;  // adjoint level computed now
@@ -317,10 +324,18 @@ __device__ __forceinline__ void adj_step(const AdjUpdateArgs<T>& p,
       Ru = end_value(c.rmode, fma_(p.q, c.sRu[mi], uc[MPT - 2]), c.sBu[mi]);
     }
   }
+  // dJ/df at level L from W^{L+1} next to the Dirichlet nodes
   if (GEN) {
-    // dJ/df at level L from W^{L+1} next to the Dirichlet nodes
     if (c.wr_fa && c.d1 >= 0 && c.d1 < MPT) p.grad_fa[L] = p.c2 * pick<T, MPT>(wc, c.d1);
     if (c.wr_fb && c.dM2 >= 0 && c.dM2 < MPT) p.grad_fb[L] = p.c2 * pick<T, MPT>(wc, c.dM2);
+  } else if (SRC) {  // into lane tau of gf, stored after the loop
+#pragma unroll
+    for (int g = 0; g < 2; ++g) {
+      if (c.gwv[g] == c.wv) {
+        const T x = rd_lane(elem_at(wc, c.gelem[g]), c.glane[g]);
+        gf[g] = wr_lane(p.c2 * x, tau, gf[g], c.lane);
+      }
+    }
   }
   const bool rev = tau < S - 1;
   if (GEN && c.gen) {
@@ -331,7 +346,7 @@ __device__ __forceinline__ void adj_step(const AdjUpdateArgs<T>& p,
   } else {
     adj_chunk<T, MPT, false>(wc, wp, Lw, Rw, p.c2, p.k, 0, 0, 0, T(0), T(0), T(0));
   }
-  if (GEN) {
+  if (GEN || SRC) {
     // receiver sources in list order: the slots (samples staged in LDS),
     // then any further ones from memory
     auto inject = [&](int64_t node, T g) {
@@ -342,8 +357,13 @@ __device__ __forceinline__ void adj_step(const AdjUpdateArgs<T>& p,
       }
     };
 #pragma unroll
-    for (int q = 0; q < kRecSlots; ++q)
-      if (q < c.rs.n) inject(c.rs.node[q], c.sg[q][tau]);
+    for (int q = 0; q < kRecSlots; ++q) {
+      if (GEN) {
+        if (q < c.rs.n) inject(c.rs.node[q], c.sg[q][tau]);
+      } else if (q < c.rs.n && c.swv[q] == c.wv) {
+        add_at(wp, c.selem[q], c.sg[q][tau], c.lane == c.slane[q]);
+      }
+    }
     for (int r = c.sb + kRecSlots; r < c.se; ++r)
       inject(p.src_node[r], p.gtr[static_cast<int64_t>(p.src_id[r]) * p.gtr_ld + (L - 1)]);
   }
@@ -361,7 +381,30 @@ __device__ __forceinline__ void adj_step(const AdjUpdateArgs<T>& p,
   }
 }
 
-template <typename T, int NT, int MPT, bool GEN>
+// The span's S steps; returns tau (tau < S: the last step left W^{n_k+1}
+// in wp, else in wc).
+template <typename T, int NT, int MPT, bool GEN, bool SRC>
+__device__ __forceinline__ int adj_run(const AdjUpdateArgs<T>& p, const AdjCtx<T, NT, MPT>& c,
+                                       T (&wc)[MPT], T (&wp)[MPT], T (&uc)[MPT],
+                                       T (&up)[MPT], int S, double& acc) {
+  T gf[2] = {T(0), T(0)};
+  int tau = 0;
+  for (; tau + 1 < S; tau += 2) {
+    adj_step<T, NT, MPT, GEN, SRC>(p, c, wc, wp, uc, up, gf, tau, S, acc);
+    adj_step<T, NT, MPT, GEN, SRC>(p, c, wp, wc, up, uc, gf, tau + 1, S, acc);
+  }
+  if (tau < S) adj_step<T, NT, MPT, GEN, SRC>(p, c, wc, wp, uc, up, gf, tau, S, acc);
+  if (SRC && c.lane < S) {  // dJ/df of levels n_e - lane
+    if (c.gwv[0] == c.wv) p.grad_fa[p.n_e - c.lane] = gf[0];
+    if (c.gwv[1] == c.wv) p.grad_fb[p.n_e - c.lane] = gf[1];
+  }
+  return tau;
+}
+
+// GEN: general tiles.  MIX: every other tile; those holding sources or
+// nodes 1 / M-2 take the SRC step, the rest the plain one (a uniform branch
+// per work-group).
+template <typename T, int NT, int MPT, bool GEN, bool MIX>
 __global__ __launch_bounds__(NT) void k_adj_update(const AdjUpdateArgs<T> p) {
   constexpr int NW = NT / 64;
   constexpr int TM = NT * MPT;
@@ -371,7 +414,7 @@ __global__ __launch_bounds__(NT) void k_adj_update(const AdjUpdateArgs<T> p) {
   __shared__ T sAu[kMaxSpan], sBu[kMaxSpan];
   __shared__ T edge[2][4][NW];
   __shared__ double red[NW];
-  __shared__ T sg[GEN ? kRecSlots : 1][kMaxSpan];
+  __shared__ T sg[(GEN || MIX) ? kRecSlots : 1][kMaxSpan];
 
   const int tid = threadIdx.x;
   const int slot = xcd_tile(blockIdx.x, gridDim.x);
@@ -435,11 +478,28 @@ __global__ __launch_bounds__(NT) void k_adj_update(const AdjUpdateArgs<T> p) {
                       (c.dM >= 0 && c.dM < MPT);
     c.gen = GEN && (__any(mine) != 0);
   }
-  c.sb = (GEN && p.src_ptr) ? p.src_ptr[slot] : 0;
-  c.se = (GEN && p.src_ptr) ? p.src_ptr[slot + 1] : 0;
-  c.rs = GEN ? load_slots(p.src_node, p.src_id, c.sb, c.se) : RecSlots{0, {}, {}};
+  c.sb = ((GEN || MIX) && p.src_ptr) ? p.src_ptr[slot] : 0;
+  c.se = ((GEN || MIX) && p.src_ptr) ? p.src_ptr[slot + 1] : 0;
+  c.rs = (GEN || MIX) ? load_slots(p.src_node, p.src_id, c.sb, c.se) : RecSlots{0, {}, {}};
   c.sg = sg;
-  if (GEN) {
+  {
+    // wave-uniform positions: tile offset x lies in thread x / MPT,
+    // element x % MPT
+    auto place = [&](bool use, int64_t node, int& w, int& l, int& e) {
+      const int64_t x = node - tl.a;
+      const bool in = use && x >= 0 && x < TM;
+      const int th = in ? static_cast<int>(x) / MPT : 0;
+      w = __builtin_amdgcn_readfirstlane(in ? th >> 6 : -1);
+      l = __builtin_amdgcn_readfirstlane(th & 63);
+      e = __builtin_amdgcn_readfirstlane(in ? static_cast<int>(x) % MPT : 0);
+    };
+#pragma unroll
+    for (int q = 0; q < kRecSlots; ++q)
+      place(q < c.rs.n, c.rs.node[q], c.swv[q], c.slane[q], c.selem[q]);
+    place(c.wr_fa, 1, c.gwv[0], c.glane[0], c.gelem[0]);
+    place(c.wr_fb, M - 2, c.gwv[1], c.glane[1], c.gelem[1]);
+  }
+  if (GEN || MIX) {
     // dJ/dtrace of the slot sources at levels n_e-1-tau, tau = 0..S-1
 #pragma unroll
     for (int q = 0; q < kRecSlots; ++q) {
@@ -460,17 +520,22 @@ __global__ __launch_bounds__(NT) void k_adj_update(const AdjUpdateArgs<T> p) {
   c.cnt = cnt;
 
   double acc = 0.0;
-  int tau = 0;
-  for (; tau + 1 < S; tau += 2) {
-    adj_step<T, NT, MPT, GEN>(p, c, wc, wp, uc, up, tau, S, acc);
-    adj_step<T, NT, MPT, GEN>(p, c, wp, wc, up, uc, tau + 1, S, acc);
+  int tau;
+  if constexpr (GEN) {
+    tau = adj_run<T, NT, MPT, true, false>(p, c, wc, wp, uc, up, S, acc);
+  } else if constexpr (MIX) {
+    if (c.se > c.sb || c.wr_fa || c.wr_fb)
+      tau = adj_run<T, NT, MPT, false, true>(p, c, wc, wp, uc, up, S, acc);
+    else
+      tau = adj_run<T, NT, MPT, false, false>(p, c, wc, wp, uc, up, S, acc);
+  } else {
+    tau = adj_run<T, NT, MPT, false, false>(p, c, wc, wp, uc, up, S, acc);
   }
   const int64_t rlo = tl.out_lo > tl.a ? tl.out_lo : tl.a;
   const int64_t rhi = tl.out_hi < tl.a + TM - 1 ? tl.out_hi : tl.a + TM - 1;
   const int xlo = static_cast<int>(rlo - tl.a);
   const int xhi = static_cast<int>(rhi - tl.a);
   if (tau < S) {
-    adj_step<T, NT, MPT, GEN>(p, c, wc, wp, uc, up, tau, S, acc);
     stage_out<T, NT, MPT>(p.w_out, tl.a, xlo, xhi, st, wc);      // W^{n_k+2}
     stage_out<T, NT, MPT>(p.w_out + M, tl.a, xlo, xhi, st, wp);  // W^{n_k+1}
   } else {
@@ -554,10 +619,10 @@ hipError_t launch_adj_update(const AdjUpdateArgs<T>& a, int threads, int per_thr
 #define RSWR_ADJ_LAUNCH(NT_, MPT_)                                                  \
   if (threads == NT_ && per_thread == MPT_) {                                     \
     if (general)                                                                  \
-      hipLaunchKernelGGL((k_adj_update<T, NT_, MPT_, true>), dim3(a.n_tiles),     \
+      hipLaunchKernelGGL((k_adj_update<T, NT_, MPT_, true, false>), dim3(a.n_tiles), \
                          dim3(NT_), 0, s, a);                                     \
     else                                                                          \
-      hipLaunchKernelGGL((k_adj_update<T, NT_, MPT_, false>), dim3(a.n_tiles),    \
+      hipLaunchKernelGGL((k_adj_update<T, NT_, MPT_, false, true>), dim3(a.n_tiles), \
                          dim3(NT_), 0, s, a);                                     \
     return hipGetLastError();                                                     \
   }

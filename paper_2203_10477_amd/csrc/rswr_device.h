@@ -239,20 +239,64 @@ __device__ __forceinline__ RecSlots load_slots(const int64_t* node, const int32_
   return r;
 }
 
-// *dst = v[e] from the lane where `mine` holds, for a wave-uniform element
-// index e in [LO, HI]: a tree of uniform branches (no per-lane select over
-// the whole array), one masked store at the leaf.
-template <int LO, int HI, typename T, int MPT>
-__device__ __forceinline__ void store_elem(const T (&v)[MPT], int e, T* dst, bool mine) {
-  if constexpr (LO == HI) {
-    if (mine) *dst = v[LO];
+// Element access with a wave-uniform runtime index e.  The array is viewed
+// as a vector of registers and read or written in the GPU's register
+// indexing mode (a few instructions, no branches, no scratch memory).  A
+// vector longer than 32 dwords cannot be indexed that way, so longer arrays
+// split into halves first (one uniform branch per level; each leaf ends in
+// an empty asm statement naming its range, which keeps the compiler from
+// merging the leaves into one runtime-indexed access to the array).
+template <typename T, int N>
+struct RegVec {
+  typedef T type __attribute__((ext_vector_type(N)));
+};
+
+template <int OFF, int LEN, typename T, int MPT>
+__device__ __forceinline__ T elem_range(const T (&v)[MPT], int e) {
+  if constexpr (LEN * sizeof(T) <= 128) {
+    typename RegVec<T, LEN>::type t;
+#pragma unroll
+    for (int i = 0; i < LEN; ++i) t[i] = v[OFF + i];
+    const T x = t[e - OFF];
+    asm volatile("; elem %0" ::"n"(OFF));
+    return x;
   } else {
-    constexpr int MID = (LO + HI) / 2;
-    if (e <= MID)
-      store_elem<LO, MID>(v, e, dst, mine);
-    else
-      store_elem<MID + 1, HI>(v, e, dst, mine);
+    constexpr int H = LEN / 2;
+    if (e < OFF + H) return elem_range<OFF, H>(v, e);
+    return elem_range<OFF + H, LEN - H>(v, e);
   }
+}
+
+template <int OFF, int LEN, typename T, int MPT>
+__device__ __forceinline__ void add_range(T (&v)[MPT], int e, T g, bool mine) {
+  if constexpr (LEN * sizeof(T) <= 128) {
+    typename RegVec<T, LEN>::type t;
+#pragma unroll
+    for (int i = 0; i < LEN; ++i) t[i] = v[OFF + i];
+    const T x = t[e - OFF];
+    t[e - OFF] = mine ? x + g : x;
+#pragma unroll
+    for (int i = 0; i < LEN; ++i) v[OFF + i] = t[i];
+    asm volatile("; add %0" ::"n"(OFF));
+  } else {
+    constexpr int H = LEN / 2;
+    if (e < OFF + H)
+      add_range<OFF, H>(v, e, g, mine);
+    else
+      add_range<OFF + H, LEN - H>(v, e, g, mine);
+  }
+}
+
+// v[e], e wave-uniform in [0, MPT).
+template <typename T, int MPT>
+__device__ __forceinline__ T elem_at(const T (&v)[MPT], int e) {
+  return elem_range<0, MPT>(v, e);
+}
+
+// v[e] += g in the lanes where `mine` holds, e wave-uniform in [0, MPT).
+template <typename T, int MPT>
+__device__ __forceinline__ void add_at(T (&v)[MPT], int e, T g, bool mine) {
+  add_range<0, MPT>(v, e, g, mine);
 }
 
 // Value just outside the region: zero data, the input ghost (Eqs. (6)-(7)

@@ -39,11 +39,12 @@ struct FusedCtx {
   int64_t a;     // the region's first node
   int tid;
   int d0, lane, wv;
-  // receivers this tile records: trace row, storing lane (-1: none) and
-  // element (-1: node 0's value, -2: node M-1's value)
+  // receivers this tile records (all wave-uniform): trace row, the wave
+  // and lane holding the node (wave -1: none), and its element (-1: node
+  // 0's value, -2: node M-1's value)
   int nrec;
   T* rdst[kRecSlots];
-  int rlane[kRecSlots], relem[kRecSlots];
+  int rwv[kRecSlots], rlane[kRecSlots], relem[kRecSlots];
   bool gen;
   bool dirL, dirR;    // this wave's lane 0 / lane 63 borders a Dirichlet node
   bool fdirL, fdirR;  // this wave's left frame holds node 0 / right frame node M-1
@@ -67,15 +68,6 @@ __device__ __forceinline__ void frame_load(const UpdateArgs<T>& p, int64_t o, in
     cur[e] = p.state_in[p.M + j];
     old[e] = p.state_in[j];
   }
-}
-
-// Complete loads issued before the step loop: a wait inside the loop would
-// also wait for every store issued there (the vector memory counter counts
-// both), so the values are settled in registers first.
-template <typename T>
-__device__ __forceinline__ void settle(T (&v)[2]) {
-  v[0] = in_vgpr(v[0]);
-  v[1] = in_vgpr(v[1]);
 }
 
 // One level of a frame: returns the centred flux at the output node (lane
@@ -114,7 +106,8 @@ __device__ __forceinline__ void fused_step(const UpdateArgs<T>& p,
                                            const FusedCtx<T, NT, MPT>& c,
                                            const T (&cur)[MPT], T (&old)[MPT],
                                            const T (&lc)[2], T (&lo)[2], const T (&rc)[2],
-                                           T (&ro)[2], T& fl, T& fr, int s) {
+                                           T (&ro)[2], T& fl, T& fr, T (&tr)[kRecSlots],
+                                           int s) {
   constexpr int NW = NT / 64;
   const int par = s & 1;
   T L = lane_shift_z<kWaveShr1>(cur[MPT - 1]);
@@ -159,17 +152,19 @@ __device__ __forceinline__ void fused_step(const UpdateArgs<T>& p,
                              rd_lane(c.vA, s + 1));
   else
     step_chunk<T, MPT, false>(cur, old, L, R, p.c2, p.k, 0, 0, T(0), T(0));
-  if (REC && c.nrec > 0) {  // wave-uniform: this tile records receivers
+  if (REC && c.nrec > 0) {
+    // receivers: the sample of level n+1 goes to lane s of tr[q] (all
+    // branches wave-uniform)
     const T da = rd_lane(c.vA, s + 1), db = rd_lane(c.vB, s + 1);
 #pragma unroll
     for (int q = 0; q < kRecSlots; ++q) {
-      if (q < c.nrec) {
-        T* const dst = c.rdst[q] + s;
-        const bool mine = c.tid == c.rlane[q];
+      if (q < c.nrec && c.rwv[q] == c.wv) {
+        T x;
         if (c.relem[q] >= 0)
-          store_elem<0, MPT - 1>(old, c.relem[q], dst, mine);
-        else if (mine)
-          *dst = (c.relem[q] == -1) ? da : db;
+          x = rd_lane(elem_at(old, c.relem[q]), c.rlane[q]);
+        else
+          x = (c.relem[q] == -1) ? da : db;
+        tr[q] = wr_lane(x, s, tr[q], c.lane);
       }
     }
   }
@@ -182,27 +177,27 @@ __device__ __forceinline__ void fused_run(const UpdateArgs<T>& p, const Tile& tl
   constexpr int TM = NT * MPT;
   T lc[2], lo[2], rc[2], ro[2];
   T fl = T(0), fr = T(0);
+  T tr[kRecSlots];
+#pragma unroll
+  for (int q = 0; q < kRecSlots; ++q) tr[q] = T(0);
   if constexpr (HL) frame_load(p, tl.a, tl.window - 1, c.lane, lc, lo);
   if constexpr (HR) frame_load(p, tl.a + TM - 1, tl.window + 1, c.lane, rc, ro);
-  if constexpr (GEN || REC) {  // these step loops store: see settle()
-    if constexpr (HL) {
-      settle(lc);
-      settle(lo);
-    }
-    if constexpr (HR) {
-      settle(rc);
-      settle(ro);
-    }
-  }
   int s = 0;
   for (; s + 1 < S; s += 2) {
-    fused_step<T, NT, MPT, GEN, REC, HL, HR>(p, c, u, uo, lc, lo, rc, ro, fl, fr, s);
-    fused_step<T, NT, MPT, GEN, REC, HL, HR>(p, c, uo, u, lo, lc, ro, rc, fl, fr, s + 1);
+    fused_step<T, NT, MPT, GEN, REC, HL, HR>(p, c, u, uo, lc, lo, rc, ro, fl, fr, tr, s);
+    fused_step<T, NT, MPT, GEN, REC, HL, HR>(p, c, uo, u, lo, lc, ro, rc, fl, fr, tr, s + 1);
   }
-  if (s < S) fused_step<T, NT, MPT, GEN, REC, HL, HR>(p, c, u, uo, lc, lo, rc, ro, fl, fr, s);
+  if (s < S)
+    fused_step<T, NT, MPT, GEN, REC, HL, HR>(p, c, u, uo, lc, lo, rc, ro, fl, fr, tr, s);
+  // per-span results, one value per lane and step: no stores in the loop
   if (p.flux_out != nullptr && c.lane < S) {
     if constexpr (HL) p.flux_out[static_cast<int64_t>(2 * tl.fl) * p.ld + c.lane] = fl;
     if constexpr (HR) p.flux_out[static_cast<int64_t>(2 * tl.fr + 1) * p.ld + c.lane] = fr;
+  }
+  if (REC && c.nrec > 0) {
+#pragma unroll
+    for (int q = 0; q < kRecSlots; ++q)
+      if (q < c.nrec && c.rwv[q] == c.wv && c.lane < S) c.rdst[q][c.lane] = tr[q];
   }
 }
 
@@ -257,8 +252,8 @@ __device__ __forceinline__ void fused_tile(const UpdateArgs<T>& p, const Tile& t
     T a = T(0), b = T(0);
     if ((GEN || dirL || fA) && l <= S) a = (l == 0) ? p.state_in[p.M] : p.fa[p.n0 + l];
     if ((GEN || dirR || fB) && l <= S) b = (l == 0) ? p.state_in[2 * p.M - 1] : p.fb[p.n0 + l];
-    c.vA = (GEN || REC) ? in_vgpr(a) : a;  // see settle()
-    c.vB = (GEN || REC) ? in_vgpr(b) : b;
+    c.vA = a;
+    c.vB = b;
   }
   c.d0 = -1000;
   c.gen = false;
@@ -278,20 +273,22 @@ __device__ __forceinline__ void fused_tile(const UpdateArgs<T>& p, const Tile& t
       const int64_t x = h ? p.rec_node[rb + q] - tl.a : -1000;
       const int32_t id = h ? p.rec_id[rb + q] : 0;
       c.rdst[q] = p.traces + static_cast<int64_t>(id) * p.trace_ld + p.trace_col0;
+      int th = -1, el = -1;  // thread of the tile holding the node, element
       if (x >= 0 && x < TM) {
-        c.rlane[q] = static_cast<int>(x) / MPT;
-        c.relem[q] = static_cast<int>(x) % MPT;
+        th = static_cast<int>(x) / MPT;
+        el = static_cast<int>(x) % MPT;
       } else if (x == -1 && dirL) {
-        c.rlane[q] = 0;
-        c.relem[q] = -1;
+        th = 0;
+        el = -1;
       } else if (x == TM && dirR) {
-        c.rlane[q] = NT - 1;
-        c.relem[q] = -2;
-      } else {
-        c.rlane[q] = -1;
-        c.relem[q] = -1;
+        th = NT - 1;
+        el = -2;
       }
+      c.rwv[q] = __builtin_amdgcn_readfirstlane(th < 0 ? -1 : th >> 6);
+      c.rlane[q] = __builtin_amdgcn_readfirstlane(th & 63);
+      c.relem[q] = __builtin_amdgcn_readfirstlane(el);
     }
+    c.nrec = __builtin_amdgcn_readfirstlane(c.nrec);
   }
 
   const bool hl = c.wv == 0 && tl.lmode == kEndGhost;

@@ -724,6 +724,9 @@ rswr_status_t enqueue_adjoint(rswr_plan_s* p, const DevTables& d, const void* ck
       rswr::AdjUpdateArgs<T> f = ua;
       f.tile_idx = reinterpret_cast<const int32_t*>(ws + L.fast_idx);
       f.n_tiles = al.n_fast;
+      f.src_ptr = reinterpret_cast<const int32_t*>(ws + L.src_ptr) + al.n_gen;
+      f.src_node = reinterpret_cast<const int64_t*>(ws + L.src_node);
+      f.src_id = reinterpret_cast<const int32_t*>(ws + L.src_id);
       RSWR_HIP(rswr::launch_adj_update<T>(f, p->threads, p->per_thread, false, s));
     }
     std::swap(w_cur, w_nxt);
@@ -1234,29 +1237,24 @@ rswr_status_t rswr_solve_adjoint(rswr_plan_t p, const void* checkpoints, const v
   char* ws = static_cast<char*>(workspace);
   const int64_t TM = int64_t(p->threads) * p->per_thread;
 
-  // general kernel: small windows, tiles whose register region holds an
-  // interior receiver (its source), tiles storing node 1 or M-2 (dJ/df)
+  // general kernel: the general tiles; every other tile in the second
+  // launch.  Sources (interior receivers in a tile's register region) as one
+  // CSR over the general list, then the other.
   const int32_t n_all = static_cast<int32_t>(p->tiles.size());
   std::vector<int32_t> gen, fast, ptr(1, 0), id;
   std::vector<int64_t> node;
-  for (int32_t t = 0; t < n_all; ++t) {
-    const Tile& x = p->tiles[t];
-    std::vector<int32_t> here;
-    for (int32_t r = 0; r < n_rec; ++r) {
-      const int64_t j = rec_idx[r];
-      if (j > 0 && j < p->M - 1 && j >= x.a && j <= x.a + TM - 1) here.push_back(r);
-    }
-    const bool ends = (x.out_lo <= 1 && 1 <= x.out_hi) ||
-                      (x.out_lo <= p->M - 2 && p->M - 2 <= x.out_hi);
-    if (x.general || !here.empty() || ends) {
-      gen.push_back(t);
-      for (int32_t r : here) {
-        id.push_back(r);
-        node.push_back(rec_idx[r]);
+  for (int32_t t = 0; t < n_all; ++t) (p->tiles[t].general ? gen : fast).push_back(t);
+  for (const std::vector<int32_t>* list : {&gen, &fast}) {
+    for (int32_t t : *list) {
+      const Tile& x = p->tiles[t];
+      for (int32_t r = 0; r < n_rec; ++r) {
+        const int64_t j = rec_idx[r];
+        if (j > 0 && j < p->M - 1 && j >= x.a && j <= x.a + TM - 1) {
+          id.push_back(r);
+          node.push_back(rec_idx[r]);
+        }
       }
       ptr.push_back(static_cast<int32_t>(id.size()));
-    } else {
-      fast.push_back(t);
     }
   }
   std::vector<int64_t> recs(rec_idx, rec_idx + n_rec);
