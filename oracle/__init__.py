@@ -46,18 +46,20 @@ def _load():
     lib.oracle_span_paper.restype = i32
     for suf in ("_f64", "_f32"):
         f = getattr(lib, "oracle_single" + suf)
-        f.argtypes = [i64, dbl, dbl, vp, vp, i64, i64, vp, i32, vp, vp, i64]
+        f.argtypes = [i64, dbl, dbl, vp, vp, i64, i64, vp, i32, vp, vp, i64, i32, vp, vp,
+                      i64]
         f.restype = None
         f = getattr(lib, "oracle_predict" + suf)
-        f.argtypes = [i64, i32, vp, vp, dbl, dbl, vp, vp, i64, i32, vp, vp, i32, vp]
+        f.argtypes = [i64, i32, vp, vp, dbl, dbl, vp, vp, i64, i32, vp, vp, i32, vp, i32,
+                      vp, vp, i64]
         f.restype = None
         f = getattr(lib, "oracle_update" + suf)
         f.argtypes = [i64, i32, vp, vp, vp, vp, dbl, dbl, vp, vp, i64, i32, vp, vp,
-                      i32, vp, i32, vp, i32, vp, vp, i64, i64]
+                      i32, vp, i32, vp, i32, vp, vp, i64, i64, i32, vp, vp, i64]
         f.restype = None
         f = getattr(lib, "oracle_rswr" + suf)
         f.argtypes = [i64, i32, vp, vp, vp, vp, dbl, dbl, vp, vp, i64, i64, vp, i32,
-                      i32, i32, i32, dbl, i32, vp, vp, i64, vp, i32]
+                      i32, i32, i32, dbl, i32, vp, vp, i64, vp, i32, i32, vp, vp, i64]
         f.restype = ctypes.c_int
     lib.oracle_adjoint_f64.argtypes = [i64, dbl, dbl, vp, vp, i64, i32, vp, vp, i64,
                                        i32, vp, vp, vp]
@@ -81,6 +83,17 @@ def _suffix(dtype):
 
 def _c(a, dtype=None):
     return np.ascontiguousarray(a, dtype=dtype)
+
+
+def _src(src, dtype):
+    """Interior point sources: None, or (nodes[n_src], amp[n_src, ld]) where
+    amp[q, n] is added to node nodes[q] by the step from level n to n+1.
+    Returns (arrays kept alive, n_src, node pointer, amp pointer, ld)."""
+    if src is None:
+        return None, 0, None, None, 0
+    nodes = _c(np.asarray(src[0], np.int64).reshape(-1))
+    amp = _c(np.asarray(src[1]).reshape(len(nodes), -1), dtype)
+    return (nodes, amp), len(nodes), _ptr(nodes), _ptr(amp), amp.shape[1]
 
 
 class Layout:
@@ -124,8 +137,9 @@ def span_paper(P, lam, frac=None):
     return int(_load().oracle_span_paper(P, float(lam), num, den))
 
 
-def single(M, lam, dx, fa, fb, n_steps, state=None, n0=0, rec=()):
-    """Single-domain leapfrog; returns (state, traces[n_rec, n_steps])."""
+def single(M, lam, dx, fa, fb, n_steps, state=None, n0=0, rec=(), src=None):
+    """Single-domain leapfrog; returns (state, traces[n_rec, n_steps]).
+    src: interior point sources, see _src."""
     fa = _c(fa)
     dtype = fa.dtype
     fb = _c(fb, dtype)
@@ -133,13 +147,15 @@ def single(M, lam, dx, fa, fb, n_steps, state=None, n0=0, rec=()):
     rec = _c(np.asarray(rec, np.int64).reshape(-1))
     tr = np.zeros((len(rec), max(n_steps, 1)), dtype)
     assert fa.shape[0] >= n0 + n_steps + 1 and fb.shape[0] >= n0 + n_steps + 1
+    keep, ns, sn, sa, sld = _src(src, dtype)
+    assert ns == 0 or sld >= n0 + n_steps
     getattr(_load(), "oracle_single" + _suffix(dtype))(
         M, lam, dx, _ptr(fa), _ptr(fb), n0, n_steps, _ptr(st), len(rec), _ptr(rec),
-        _ptr(tr), tr.shape[1])
+        _ptr(tr), tr.shape[1], ns, sn, sa, sld)
     return st, tr[:, :n_steps]
 
 
-def predict(lay, lam, dx, fa, fb, n0, shat, state, ld=None, hist=False):
+def predict(lay, lam, dx, fa, fb, n0, shat, state, ld=None, hist=False, src=None):
     """Literal prediction of every window; returns flux (N-1, 2, ld) [, hist]."""
     fa = _c(fa)
     dtype = fa.dtype
@@ -152,14 +168,16 @@ def predict(lay, lam, dx, fa, fb, n0, shat, state, ld=None, hist=False):
     if hist:
         hld = max([int(lay.hi[i] - lay.lo[i + 1] + 1) for i in range(N - 1)] + [1])
         h = np.zeros((max(N - 1, 1), 2, shat + 1, hld), dtype)
+    keep, ns, sn, sa, sld = _src(src, dtype)
+    assert ns == 0 or sld >= n0 + shat
     getattr(_load(), "oracle_predict" + _suffix(dtype))(
         lay.M, N, _ptr(lay.lo), _ptr(lay.hi), lam, dx, _ptr(fa), _ptr(fb), n0, shat,
-        _ptr(state), _ptr(flux), ld, _ptr(h))
+        _ptr(state), _ptr(flux), ld, _ptr(h), ns, sn, sa, sld)
     return (flux, h) if hist else flux
 
 
 def update(lay, lam, dx, fa, fb, n0, S, state, flux, windows=None, rec=(),
-           traces=None, trace_level0=0, out=None):
+           traces=None, trace_level0=0, out=None, src=None):
     """Literal update + gluing; returns (state_out, traces)."""
     fa = _c(fa)
     dtype = fa.dtype
@@ -172,16 +190,18 @@ def update(lay, lam, dx, fa, fb, n0, S, state, flux, windows=None, rec=(),
     if traces is None:
         traces = np.zeros((len(rec), max(n0 + S - trace_level0, 1)), dtype)
     sel = None if windows is None else _c(windows, np.int32)
+    keep, ns, sn, sa, sld = _src(src, dtype)
+    assert ns == 0 or sld >= n0 + S
     getattr(_load(), "oracle_update" + _suffix(dtype))(
         lay.M, lay.N, _ptr(lay.lo), _ptr(lay.hi), _ptr(lay.own_lo), _ptr(lay.own_hi),
         lam, dx, _ptr(fa), _ptr(fb), n0, S, _ptr(state), _ptr(flux), ld, _ptr(out),
         0 if sel is None else len(sel), _ptr(sel), len(rec), _ptr(rec), _ptr(traces),
-        traces.shape[1], trace_level0)
+        traces.shape[1], trace_level0, ns, sn, sa, sld)
     return out, traces
 
 
 def rswr(lay, lam, dx, fa, fb, n_steps, mode=FIXED, span=None, beta=0.1,
-         state=None, n0=0, rec=(), tau_hat=0):
+         state=None, n0=0, rec=(), tau_hat=0, src=None):
     """The whole span loop; returns (state, traces[n_rec, n_steps], spans).
 
     tau_hat is the first predictive span of the adaptive modes (Sec. 2.3);
@@ -198,12 +218,14 @@ def rswr(lay, lam, dx, fa, fb, n_steps, mode=FIXED, span=None, beta=0.1,
         raise ValueError("FIXED mode needs a span")
     cap = n_steps + 1
     spans = np.zeros(cap, np.int32)
+    keep, ns, sn, sa, sld = _src(src, dtype)
+    assert ns == 0 or sld >= n0 + n_steps
     k = getattr(_load(), "oracle_rswr" + _suffix(dtype))(
         M, lay.N, _ptr(lay.lo), _ptr(lay.hi), _ptr(lay.own_lo), _ptr(lay.own_hi), lam,
         dx, _ptr(fa), _ptr(fb), n0, n_steps, _ptr(st), mode,
         0 if span is None else int(span), min(cone, 2**31 - 1), int(tau_hat), beta,
         len(rec),
-        _ptr(rec), _ptr(tr), tr.shape[1], _ptr(spans), cap)
+        _ptr(rec), _ptr(tr), tr.shape[1], _ptr(spans), cap, ns, sn, sa, sld)
     if k < 0:
         raise ValueError(f"oracle_rswr failed ({k})")
     return st, tr[:, :n_steps], spans[:k]
@@ -228,7 +250,7 @@ def adjoint(M, lam, dx, fa, fb, n_steps, rec, grad_traces, ck=64):
     return ga, gb, gl.value
 
 
-def point_values(M, lam, dx, fa, fb, n_steps, state, nodes, n0=0):
+def point_values(M, lam, dx, fa, fb, n_steps, state, nodes, n0=0, src=None):
     """Values of the single-domain solution at `nodes` after n_steps.
 
     Each contiguous group of requested nodes is computed by oracle_single on
@@ -257,8 +279,13 @@ def point_values(M, lam, dx, fa, fb, n_steps, state, nodes, n0=0):
         Ms = B - A + 1
         sfa = fa if A == 0 else np.zeros_like(fa)
         sfb = fb if B == M - 1 else np.zeros_like(fb)
+        ssrc = None
+        if src is not None:
+            sn = np.asarray(src[0], np.int64)
+            keep = (sn > A) & (sn < B)
+            ssrc = (sn[keep] - A, np.asarray(src[1])[keep])
         st, _ = single(Ms, lam, dx, sfa, sfb, n_steps, state=state[:, A:B + 1].copy(),
-                       n0=n0)
+                       n0=n0, src=ssrc)
         for idx in g:
             out[:, idx] = st[:, nodes[idx] - A]
     return out

@@ -21,7 +21,12 @@
  *   centred flux F = (U_{o+1} - U_{o-1}) * r, r = T(1/(2dx)); a Neumann
  *   input at a right end b uses the ghost U_{b+1} = fma(q, F, U_{b-1}), at a
  *   left end U_{b-1} = fma(-q, F, U_{b+1}), q = T(2dx) (Sec. 2.2, Eqs.
- *   (6)-(7)).
+ *   (6)-(7));
+ *   interior point sources (the pulse sources of Sec. 4, u_tt = a^2 u_xx +
+ *   s): the step from level n to n+1 adds amp[q][n] (the caller's samples of
+ *   dt^2 s at node node[q]) to the updated value at node[q], after the
+ *   leapfrog, sources in list order, in every window holding the node; the
+ *   Dirichlet nodes 0 and M-1 take no source.
  *
  * Every real-valued function exists twice: suffix _f64 (double) and _f32
  * (float), compiled from the same source with -ffp-contract=off.
@@ -58,11 +63,15 @@ int32_t oracle_span_paper(int32_t P, double lam, int32_t num, int32_t den);
   void oracle_single##SUF(int64_t M, double lam, double dx, const T* fa,       \
                           const T* fb, int64_t n0, int64_t n_steps, T* state,  \
                           int32_t n_rec, const int64_t* rec, T* traces,        \
-                          int64_t trace_ld);                                   \
+                          int64_t trace_ld, int32_t n_src,                     \
+                          const int64_t* src_node, const T* src_amp,           \
+                          int64_t src_ld);                                     \
   void oracle_predict##SUF(int64_t M, int32_t N, const int64_t* lo,            \
                            const int64_t* hi, double lam, double dx,           \
                            const T* fa, const T* fb, int64_t n0, int32_t Shat, \
-                           const T* state, T* flux, int32_t ld, T* hist);      \
+                           const T* state, T* flux, int32_t ld, T* hist,       \
+                           int32_t n_src, const int64_t* src_node,             \
+                           const T* src_amp, int64_t src_ld);                  \
   void oracle_update##SUF(int64_t M, int32_t N, const int64_t* lo,             \
                           const int64_t* hi, const int64_t* own_lo,            \
                           const int64_t* own_hi, double lam, double dx,        \
@@ -71,7 +80,9 @@ int32_t oracle_span_paper(int32_t P, double lam, int32_t num, int32_t den);
                           T* state_out, int32_t n_win_sel,                     \
                           const int32_t* win_sel, int32_t n_rec,               \
                           const int64_t* rec, T* traces, int64_t trace_ld,     \
-                          int64_t trace_level0);                               \
+                          int64_t trace_level0, int32_t n_src,                 \
+                          const int64_t* src_node, const T* src_amp,           \
+                          int64_t src_ld);                                     \
   int oracle_rswr##SUF(int64_t M, int32_t N, const int64_t* lo,                \
                        const int64_t* hi, const int64_t* own_lo,               \
                        const int64_t* own_hi, double lam, double dx,           \
@@ -79,7 +90,9 @@ int32_t oracle_span_paper(int32_t P, double lam, int32_t num, int32_t den);
                        T* state, int32_t mode, int32_t S_fixed,                \
                        int32_t S_cone, int32_t tau_hat, double beta,           \
                        int32_t n_rec, const int64_t* rec, T* traces,           \
-                       int64_t trace_ld, int32_t* spans, int32_t spans_cap);
+                       int64_t trace_ld, int32_t* spans, int32_t spans_cap,    \
+                       int32_t n_src, const int64_t* src_node,                 \
+                       const T* src_amp, int64_t src_ld);
 
 ORACLE_DECLARE(double, _f64)
 ORACLE_DECLARE(float, _f32)

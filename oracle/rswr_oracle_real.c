@@ -34,6 +34,16 @@ typedef struct {
   real c2, k, r, q;
 } coef_t;
 
+/* Interior point sources (the pulse sources of Sec. 4): the step from level
+ * n to n+1 adds amp[q*ld + n] to node node[q] after the leapfrog update, in
+ * list order.  NULL or n == 0: no sources. */
+typedef struct {
+  int32_t n;
+  const int64_t* node;
+  const real* amp;
+  int64_t ld;
+} src_t;
+
 /* Leapfrog and flux constants, formed in double and rounded once. */
 static coef_t make_coef(double lam, double dx) {
   coef_t c;
@@ -68,7 +78,8 @@ static real flux_at(const coef_t* c, const real* u, int64_t i) {
  */
 static void window_step(const coef_t* c, int64_t M, int64_t lo, int64_t hi,
                         const real* u_old, const real* u, real* u_new,
-                        real fin_l, real fin_r, real fa_next, real fb_next) {
+                        real fin_l, real fin_r, real fa_next, real fb_next,
+                        const src_t* src, int64_t level) {
   const int64_t n = hi - lo + 1;
   for (int64_t i = 0; i < n; ++i) {
     const int64_t j = lo + i;
@@ -84,6 +95,14 @@ static void window_step(const coef_t* c, int64_t M, int64_t lo, int64_t hi,
     const real ur = (i == n - 1) ? FMA(c->q, fin_r, u[n - 2]) : u[i + 1];
     u_new[i] = leap(c, ul, u[i], ur, u_old[i]);
   }
+  /* sources of the PDE inside this window (every window holding the node
+   * carries them); the Dirichlet nodes keep their data */
+  if (src)
+    for (int32_t q = 0; q < src->n; ++q) {
+      const int64_t j = src->node[q];
+      if (j >= lo && j <= hi && j > 0 && j < M - 1)
+        u_new[j - lo] = u_new[j - lo] + src->amp[(int64_t)q * src->ld + level];
+    }
 }
 
 static int64_t trace_col(int64_t level, int64_t level0) {
@@ -97,8 +116,11 @@ static int64_t trace_col(int64_t level, int64_t level0) {
 void SFX(oracle_single)(int64_t M, double lam, double dx, const real* fa,
                         const real* fb, int64_t n0, int64_t n_steps,
                         real* state, int32_t n_rec, const int64_t* rec,
-                        real* traces, int64_t trace_ld) {
+                        real* traces, int64_t trace_ld, int32_t n_src,
+                        const int64_t* src_node, const real* src_amp,
+                        int64_t src_ld) {
   const coef_t c = make_coef(lam, dx);
+  const src_t src = {n_src, src_node, src_amp, src_ld};
   real* b0 = (real*)malloc(sizeof(real) * (size_t)M);
   real* b1 = (real*)malloc(sizeof(real) * (size_t)M);
   real* b2 = (real*)malloc(sizeof(real) * (size_t)M);
@@ -106,7 +128,7 @@ void SFX(oracle_single)(int64_t M, double lam, double dx, const real* fa,
   memcpy(b1, state + M, sizeof(real) * (size_t)M);
   for (int64_t s = 0; s < n_steps; ++s) {
     const int64_t n = n0 + s;
-    window_step(&c, M, 0, M - 1, b0, b1, b2, 0, 0, fa[n + 1], fb[n + 1]);
+    window_step(&c, M, 0, M - 1, b0, b1, b2, 0, 0, fa[n + 1], fb[n + 1], &src, n);
     real* t = b0;
     b0 = b1;
     b1 = b2;
@@ -133,7 +155,7 @@ static void predict_impl(int64_t M, int32_t N, const int64_t* lo,
                          const int64_t* hi, double lam, double dx,
                          const real* fa, const real* fb, int64_t n0,
                          int32_t Shat, const real* state, real* flux,
-                         int32_t ld, real* hist, int64_t hld) {
+                         int32_t ld, real* hist, int64_t hld, const src_t* src) {
   const coef_t c = make_coef(lam, dx);
 #pragma omp parallel for schedule(dynamic, 1)
   for (int32_t w = 0; w < N; ++w) {
@@ -164,7 +186,7 @@ static void predict_impl(int64_t M, int32_t N, const int64_t* lo,
       if (s == Shat) break;
       const int64_t n = n0 + s;
       window_step(&c, M, lo[w], hi[w], b0, b1, b2, (real)0, (real)0, fa[n + 1],
-                  fb[n + 1]);
+                  fb[n + 1], src, n);
       real* t = b0;
       b0 = b1;
       b1 = b2;
@@ -180,12 +202,15 @@ void SFX(oracle_predict)(int64_t M, int32_t N, const int64_t* lo,
                          const int64_t* hi, double lam, double dx,
                          const real* fa, const real* fb, int64_t n0,
                          int32_t Shat, const real* state, real* flux,
-                         int32_t ld, real* hist) {
+                         int32_t ld, real* hist, int32_t n_src,
+                         const int64_t* src_node, const real* src_amp,
+                         int64_t src_ld) {
+  const src_t src = {n_src, src_node, src_amp, src_ld};
   int64_t hld = 1;
   for (int32_t i = 0; i + 1 < N; ++i)
     if (hi[i] - lo[i + 1] + 1 > hld) hld = hi[i] - lo[i + 1] + 1;
   predict_impl(M, N, lo, hi, lam, dx, fa, fb, n0, Shat, state, flux, ld, hist,
-               hld);
+               hld, &src);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -202,8 +227,11 @@ void SFX(oracle_update)(int64_t M, int32_t N, const int64_t* lo,
                         real* state_out, int32_t n_win_sel,
                         const int32_t* win_sel, int32_t n_rec,
                         const int64_t* rec, real* traces, int64_t trace_ld,
-                        int64_t trace_level0) {
+                        int64_t trace_level0, int32_t n_src,
+                        const int64_t* src_node, const real* src_amp,
+                        int64_t src_ld) {
   const coef_t c = make_coef(lam, dx);
+  const src_t src = {n_src, src_node, src_amp, src_ld};
   const int32_t nsel = win_sel ? n_win_sel : N;
 #pragma omp parallel for schedule(dynamic, 1)
   for (int32_t ws = 0; ws < nsel; ++ws) {
@@ -222,7 +250,7 @@ void SFX(oracle_update)(int64_t M, int32_t N, const int64_t* lo,
       const real fin_l = (w > 0) ? flux[(int64_t)(2 * (w - 1) + 0) * ld + s] : (real)0;
       const real fin_r = (w < N - 1) ? flux[(int64_t)(2 * w + 1) * ld + s] : (real)0;
       window_step(&c, M, lo[w], hi[w], b0, b1, b2, fin_l, fin_r, fa[n + 1],
-                  fb[n + 1]);
+                  fb[n + 1], &src, n);
       real* t = b0;
       b0 = b1;
       b1 = b2;
@@ -263,7 +291,10 @@ int SFX(oracle_rswr)(int64_t M, int32_t N, const int64_t* lo,
                      int32_t S_fixed, int32_t S_cone, int32_t tau_hat,
                      double beta, int32_t n_rec, const int64_t* rec,
                      real* traces, int64_t trace_ld, int32_t* spans,
-                     int32_t spans_cap) {
+                     int32_t spans_cap, int32_t n_src,
+                     const int64_t* src_node, const real* src_amp,
+                     int64_t src_ld) {
+  const src_t src = {n_src, src_node, src_amp, src_ld};
   if (mode < 0 || mode > 2) return -1;
   if (mode == 0 && S_fixed < 1) return -2;
   int64_t hld = 1;
@@ -294,7 +325,7 @@ int SFX(oracle_rswr)(int64_t M, int32_t N, const int64_t* lo,
       hist = (real*)realloc(hist, sizeof(real) * (size_t)((int64_t)(N - 1) * 2 *
                                                           (Shat + 1) * hld));
     predict_impl(M, N, lo, hi, lam, dx, fa, fb, n0, Shat, state, flux, ld,
-                 (mode == 2 && N > 1) ? hist : NULL, hld);
+                 (mode == 2 && N > 1) ? hist : NULL, hld, &src);
 
     int64_t S = Shat;
     if (mode == 1 && N > 1) {
@@ -331,7 +362,8 @@ int SFX(oracle_rswr)(int64_t M, int32_t N, const int64_t* lo,
 
     SFX(oracle_update)(M, N, lo, hi, own_lo, own_hi, lam, dx, fa, fb, n0,
                        (int32_t)S, state, flux, ld, other, 0, NULL, n_rec, rec,
-                       traces, trace_ld, level0);
+                       traces, trace_ld, level0, n_src, src_node, src_amp,
+                       src_ld);
     memcpy(state, other, sizeof(real) * 2 * (size_t)M);
     if (k < spans_cap && spans) spans[k] = (int32_t)S;
     S_prev = (int32_t)S;
@@ -395,7 +427,7 @@ int oracle_adjoint_f64(int64_t M, double lam, double dx, const double* fa,
         memcpy(ckpt + (n / ck) * 2 * M, b0, sizeof(double) * (size_t)M);
         memcpy(ckpt + (n / ck) * 2 * M + M, b1, sizeof(double) * (size_t)M);
       }
-      window_step(&c, M, 0, M - 1, b0, b1, b2, 0, 0, fa[n + 1], fb[n + 1]);
+      window_step(&c, M, 0, M - 1, b0, b1, b2, 0, 0, fa[n + 1], fb[n + 1], NULL, n);
       double* t = b0;
       b0 = b1;
       b1 = b2;
@@ -443,7 +475,7 @@ int oracle_adjoint_f64(int64_t M, double lam, double dx, const double* fa,
       for (int64_t L = seg_base; L < top; ++L) {
         const int64_t t = L - seg_base + 1; /* seg[t] = U^L */
         window_step(&c, M, 0, M - 1, seg + (t - 1) * M, seg + t * M,
-                    seg + (t + 1) * M, 0, 0, fa[L + 1], fb[L + 1]);
+                    seg + (t + 1) * M, 0, 0, fa[L + 1], fb[L + 1], NULL, L);
       }
     }
     const double* U = seg + (m - seg_base + 1) * M;

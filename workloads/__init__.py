@@ -111,6 +111,31 @@ def ricker_source(M, n_steps, g, courant=0.9, a_ref=1.0, t0_range=None):
     return ricker(t, f, t0, amp)
 
 
+def pulse_sources(M, N, n_steps, g, courant=0.9, a_ref=1.0, count=None):
+    """Interior pulse sources standing in for the "N pulse sources" of the
+    paper's experiments (Sec. 4): `count` (default N) Ricker pulses, one in
+    each of `count` equal stretches of the interior, at a uniformly drawn
+    node; peak frequency 40 over the run, delay 1.2..3 periods, amplitude
+    A in [0.5, 2].  Returns (nodes[count] int64, amp[count, n_steps + 1])
+    with amp[q, n] = A pi f dt ricker(t_n): the value the step from level n
+    to n+1 adds at nodes[q] (of the order of dt^2 times a point source of
+    strength A f / dt, which radiates a pulse of order A)."""
+    count = N if count is None else count
+    t = time_grid(M, n_steps, courant, a_ref)
+    dt = t[1] - t[0]
+    f = 40.0 / t[-1]
+    edges = np.linspace(1, M - 2, count + 1)
+    nodes = np.empty(count, np.int64)
+    amp = np.empty((count, n_steps + 1))
+    for q in range(count):
+        lo, hi = int(np.ceil(edges[q])), int(np.floor(edges[q + 1]))
+        nodes[q] = g.integers(lo, max(hi, lo) + 1)
+        A = g.uniform(0.5, 2.0)
+        t0 = g.uniform(1.2, 3.0) / f
+        amp[q] = np.pi * f * dt * ricker(t, f, t0, A)
+    return nodes, amp
+
+
 def config2(dtype=np.float64, M=2 ** 20, N=64, P=64, n_steps=10 ** 4,
             smooth=False) -> Problem:
     """Plain throughput case: 2^20 nodes, 64 windows, overlap 64, 10^4 steps,
