@@ -107,6 +107,19 @@ typedef struct {
   int32_t no_fuse;          /* 1 = rswr_solve keeps predict and update as two
                                launches per span even where the fused span
                                applies (see rswr_plan_info_t.fused) */
+  /* Interior point sources, the pulse sources of Sec. 4 (u_tt = a^2 u_xx +
+   * s): the step from level n to n+1 adds src_amp[q][n] (the caller's
+   * samples of dt^2 s at the node, dtype of the plan) to node src_node[q]
+   * after the leapfrog update, sources in list order, in every window that
+   * holds the node (prediction and update alike).  n_src = 0: none.  Nodes
+   * must lie in 1..M-2.  Plans with sources must take the fused span
+   * (rswr_plan_info_t.fused; else UNSUPPORTED) and run rswr_span and
+   * rswr_solve only; the device array must stay valid while the plan is
+   * used, and a call must end at a level <= src_ld. */
+  int32_t n_src;
+  const int64_t* src_node;  /* (host) copied by rswr_plan */
+  const void* src_amp;      /* (device) [n_src][src_ld] */
+  int64_t src_ld;
 } rswr_desc_t;
 
 typedef struct {

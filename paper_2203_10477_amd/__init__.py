@@ -41,7 +41,9 @@ class _Desc(ctypes.Structure):
                 ("span", ctypes.c_int32), ("span_mode", ctypes.c_int32),
                 ("beta", ctypes.c_double), ("dtype", ctypes.c_int32),
                 ("tile_threads", ctypes.c_int32), ("tile_per_thread", ctypes.c_int32),
-                ("no_fuse", ctypes.c_int32)]
+                ("no_fuse", ctypes.c_int32), ("n_src", ctypes.c_int32),
+                ("src_node", ctypes.c_void_p), ("src_amp", ctypes.c_void_p),
+                ("src_ld", ctypes.c_int64)]
 
 
 class _Info(ctypes.Structure):
@@ -115,12 +117,16 @@ class Plan:
     of Eq. (10) exact in integers.  windows = (lo, hi) gives explicit windows.
     tile = (threads, nodes per lane) picks a built kernel shape; fuse=False
     keeps predict and update as separate launches in rswr_solve.
+    sources = (nodes, amp): interior point sources (the pulse sources of
+    Sec. 4): nodes in 1..M-2 (host), amp a device tensor [n_src, ld] of the
+    plan's dtype; the step from level n to n+1 adds amp[q, n] at nodes[q].
+    The plan keeps a reference to amp.
     """
 
     def __init__(self, n_points, n_sub, overlap, a=1.0, courant=0.9,
                  courant_frac=(9, 10), x_a=0.0, x_b=1.0, a_ref=0.0, span=0,
                  span_mode=FIXED, beta=0.1, dtype=torch.float64, windows=None,
-                 tile=None, fuse=True):
+                 tile=None, fuse=True, sources=None):
         L = lib()
         d = _Desc()
         d.x_a, d.x_b, d.n_points = float(x_a), float(x_b), int(n_points)
@@ -140,6 +146,21 @@ class Plan:
         if tile is not None:
             d.tile_threads, d.tile_per_thread = int(tile[0]), int(tile[1])
         d.no_fuse = 0 if fuse else 1
+        self._src = None
+        if sources is not None:
+            nodes = np.ascontiguousarray(np.asarray(sources[0], np.int64).reshape(-1))
+            amp = sources[1]
+            want = torch.float64 if d.dtype == F64 else torch.float32
+            if not (isinstance(amp, torch.Tensor) and amp.is_cuda and amp.dtype == want
+                    and amp.dim() == 2 and amp.shape[0] == len(nodes)
+                    and amp.is_contiguous()):
+                raise RSWRError(1, "sources: amp must be a contiguous device tensor "
+                                "[n_src, ld] of the plan's dtype")
+            self._src = (nodes, amp)
+            d.n_src = len(nodes)
+            d.src_node = nodes.ctypes.data
+            d.src_amp = amp.data_ptr()
+            d.src_ld = amp.shape[1]
         h = ctypes.c_void_p()
         _check(L.rswr_plan(ctypes.byref(d), ctypes.byref(h)), "rswr_plan")
         self._h = h

@@ -45,6 +45,16 @@ struct FusedCtx {
   int nrec;
   T* rdst[kRecSlots];
   int rwv[kRecSlots], rlane[kRecSlots], relem[kRecSlots];
+  // interior sources this tile injects (all but the samples wave-uniform):
+  // region slots as (wave << 16) | (lane << 8) | element, frame slots as the
+  // frame offset 2 lane + element; samp / famp hold the span's samples, one
+  // per lane; [sfb, sfe) and [ffb, ffe) are the sources read from memory
+  int nsrc, sfb, sfe;
+  int scode[kSrcSlots];
+  T samp[kSrcSlots];
+  int nfs[2], ffb[2], ffe[2];
+  int fcode[2][kFrameSrc];
+  T famp[2][kFrameSrc];
   bool gen;
   bool dirL, dirR;    // this wave's lane 0 / lane 63 borders a Dirichlet node
   bool fdirL, fdirR;  // this wave's left frame holds node 0 / right frame node M-1
@@ -95,13 +105,41 @@ __device__ __forceinline__ void frame_dirichlet(bool dir, const bool (&m)[2], T 
   }
 }
 
+// Sources of the frame on side `sd` (0 left, 1 right) into its new level
+// (after the frame's step, as every window adds its sources after the
+// leapfrog): slots from registers, the rest from memory.  o0 is the frame's
+// first node.
+template <typename T, int NT, int MPT>
+__device__ __forceinline__ void frame_sources(const UpdateArgs<T>& p,
+                                             const FusedCtx<T, NT, MPT>& c, int sd,
+                                             int64_t o0, int s, T (&lvl)[2]) {
+#pragma unroll
+  for (int q = 0; q < kFrameSrc; ++q) {
+    if (q < c.nfs[sd]) {
+      const int x = c.fcode[sd][q];
+      const T g = rd_lane(c.famp[sd][q], s);
+      const bool mine = c.lane == (x >> 1);
+      if (x & 1)
+        lvl[1] = mine ? lvl[1] + g : lvl[1];
+      else
+        lvl[0] = mine ? lvl[0] + g : lvl[0];
+    }
+  }
+  for (int r = c.ffb[sd]; r < c.ffe[sd]; ++r) {
+    const int64_t x = p.src_node[r] - o0 - 2 * c.lane;
+    const T g = p.src_amp[static_cast<int64_t>(p.src_id[r]) * p.src_ld + p.n0 + s];
+    lvl[0] = (x == 0) ? lvl[0] + g : lvl[0];
+    lvl[1] = (x == 1) ? lvl[1] + g : lvl[1];
+  }
+}
+
 // One step of the tile (cur = level n, old = level n-1 on entry, old = level
 // n+1 on exit) and of the frames this wave carries (HL: the left input,
 // HR: the right input).  fl / fr collect F[s] in lane s when the caller
 // keeps the fluxes.  The lane shifts fill the wave's ends with zero: the
 // zero data of a cut region end; input ghosts, Dirichlet values and the
 // neighbouring wave's node replace it where they apply.
-template <typename T, int NT, int MPT, bool GEN, bool REC, bool HL, bool HR>
+template <typename T, int NT, int MPT, bool GEN, bool EXT, bool HL, bool HR>
 __device__ __forceinline__ void fused_step(const UpdateArgs<T>& p,
                                            const FusedCtx<T, NT, MPT>& c,
                                            const T (&cur)[MPT], T (&old)[MPT],
@@ -118,6 +156,8 @@ __device__ __forceinline__ void fused_step(const UpdateArgs<T>& p,
       const T d = rd_lane(c.vA, s + 1);
       frame_dirichlet(true, c.fmL, d, lo);
     }
+    if (EXT && (c.nfs[0] > 0 || c.ffe[0] > c.ffb[0]))
+      frame_sources(p, c, 0, c.a - kFrameHalf, s, lo);
     if (c.keep) fl = wr_lane(F, s, fl, c.lane);
     L = (c.lane == 0) ? fma_(c.nq, F, cur[1]) : L;
   }
@@ -127,6 +167,8 @@ __device__ __forceinline__ void fused_step(const UpdateArgs<T>& p,
       const T d = rd_lane(c.vB, s + 1);
       frame_dirichlet(true, c.fmR, d, ro);
     }
+    if (EXT && (c.nfs[1] > 0 || c.ffe[1] > c.ffb[1]))
+      frame_sources(p, c, 1, c.a + NT * MPT - 1 - kFrameHalf, s, ro);
     if (c.keep) fr = wr_lane(F, s, fr, c.lane);
     R = (c.lane == 63) ? fma_(c.pq, F, cur[MPT - 2]) : R;
   }
@@ -152,7 +194,22 @@ __device__ __forceinline__ void fused_step(const UpdateArgs<T>& p,
                              rd_lane(c.vA, s + 1));
   else
     step_chunk<T, MPT, false>(cur, old, L, R, p.c2, p.k, 0, 0, T(0), T(0));
-  if (REC && c.nrec > 0) {
+  if (EXT && (c.nsrc > 0 || c.sfe > c.sfb)) {
+    // interior sources of level n+1, in source order
+#pragma unroll
+    for (int q = 0; q < kSrcSlots; ++q) {
+      if (q < c.nsrc && (c.scode[q] >> 16) == c.wv)
+        add_at(old, c.scode[q] & 255, rd_lane(c.samp[q], s),
+               c.lane == ((c.scode[q] >> 8) & 255));
+    }
+    for (int r = c.sfb; r < c.sfe; ++r) {
+      const int64_t d = p.src_node[r] - c.base;
+      const T g = p.src_amp[static_cast<int64_t>(p.src_id[r]) * p.src_ld + p.n0 + s];
+#pragma unroll
+      for (int e = 0; e < MPT; ++e) old[e] = (d == e) ? old[e] + g : old[e];
+    }
+  }
+  if (EXT && c.nrec > 0) {
     // receivers: the sample of level n+1 goes to lane s of tr[q] (all
     // branches wave-uniform)
     const T da = rd_lane(c.vA, s + 1), db = rd_lane(c.vB, s + 1);
@@ -170,7 +227,7 @@ __device__ __forceinline__ void fused_step(const UpdateArgs<T>& p,
   }
 }
 
-template <typename T, int NT, int MPT, bool GEN, bool REC, bool HL, bool HR>
+template <typename T, int NT, int MPT, bool GEN, bool EXT, bool HL, bool HR>
 __device__ __forceinline__ void fused_run(const UpdateArgs<T>& p, const Tile& tl,
                                           const FusedCtx<T, NT, MPT>& c, int S,
                                           T (&u)[MPT], T (&uo)[MPT]) {
@@ -184,17 +241,17 @@ __device__ __forceinline__ void fused_run(const UpdateArgs<T>& p, const Tile& tl
   if constexpr (HR) frame_load(p, tl.a + TM - 1, tl.window + 1, c.lane, rc, ro);
   int s = 0;
   for (; s + 1 < S; s += 2) {
-    fused_step<T, NT, MPT, GEN, REC, HL, HR>(p, c, u, uo, lc, lo, rc, ro, fl, fr, tr, s);
-    fused_step<T, NT, MPT, GEN, REC, HL, HR>(p, c, uo, u, lo, lc, ro, rc, fl, fr, tr, s + 1);
+    fused_step<T, NT, MPT, GEN, EXT, HL, HR>(p, c, u, uo, lc, lo, rc, ro, fl, fr, tr, s);
+    fused_step<T, NT, MPT, GEN, EXT, HL, HR>(p, c, uo, u, lo, lc, ro, rc, fl, fr, tr, s + 1);
   }
   if (s < S)
-    fused_step<T, NT, MPT, GEN, REC, HL, HR>(p, c, u, uo, lc, lo, rc, ro, fl, fr, tr, s);
+    fused_step<T, NT, MPT, GEN, EXT, HL, HR>(p, c, u, uo, lc, lo, rc, ro, fl, fr, tr, s);
   // per-span results, one value per lane and step: no stores in the loop
   if (p.flux_out != nullptr && c.lane < S) {
     if constexpr (HL) p.flux_out[static_cast<int64_t>(2 * tl.fl) * p.ld + c.lane] = fl;
     if constexpr (HR) p.flux_out[static_cast<int64_t>(2 * tl.fr + 1) * p.ld + c.lane] = fr;
   }
-  if (REC && c.nrec > 0) {
+  if (EXT && c.nrec > 0) {
 #pragma unroll
     for (int q = 0; q < kRecSlots; ++q)
       if (q < c.nrec && c.rwv[q] == c.wv && c.lane < S) c.rdst[q][c.lane] = tr[q];
@@ -203,7 +260,7 @@ __device__ __forceinline__ void fused_run(const UpdateArgs<T>& p, const Tile& tl
 
 // One tile over S levels: load, step (with the frames its waves carry),
 // store.  `st` is the LDS staging buffer, `edge` the cross-wave slots.
-template <typename T, int NT, int MPT, bool GEN, bool REC>
+template <typename T, int NT, int MPT, bool GEN, bool EXT>
 __device__ __forceinline__ void fused_tile(const UpdateArgs<T>& p, const Tile& tl, int slot,
                                            int S, T* st, T (*edge)[2][NT / 64]) {
   constexpr int NW = NT / 64;
@@ -264,7 +321,7 @@ __device__ __forceinline__ void fused_tile(const UpdateArgs<T>& p, const Tile& t
   }
   // receivers this tile records (REC instantiations; at most kRecSlots)
   c.nrec = 0;
-  if (REC && p.rec_ptr) {
+  if (EXT && p.rec_ptr) {
     const int rb = p.rec_ptr[slot], re = p.rec_ptr[slot + 1];
     c.nrec = re - rb < kRecSlots ? re - rb : kRecSlots;
 #pragma unroll
@@ -290,19 +347,63 @@ __device__ __forceinline__ void fused_tile(const UpdateArgs<T>& p, const Tile& t
     }
     c.nrec = __builtin_amdgcn_readfirstlane(c.nrec);
   }
+  // interior sources (EXT instantiations)
+  c.nsrc = 0;
+  c.sfb = c.sfe = 0;
+#pragma unroll
+  for (int sd = 0; sd < 2; ++sd) c.nfs[sd] = c.ffb[sd] = c.ffe[sd] = 0;
+  if (EXT && p.src_ptr) {
+    const int t3 = 3 * p.tile_idx[slot];
+    const int b0 = p.src_ptr[t3], b1 = p.src_ptr[t3 + 1];
+    const int b2 = p.src_ptr[t3 + 2], b3 = p.src_ptr[t3 + 3];
+    auto sample = [&](int r) -> T {
+      return (c.lane < S)
+                 ? p.src_amp[static_cast<int64_t>(p.src_id[r]) * p.src_ld + p.n0 + c.lane]
+                 : T(0);
+    };
+    c.nsrc = __builtin_amdgcn_readfirstlane(b1 - b0 < kSrcSlots ? b1 - b0 : kSrcSlots);
+    c.sfb = __builtin_amdgcn_readfirstlane(b0 + kSrcSlots < b1 ? b0 + kSrcSlots : b1);
+    c.sfe = __builtin_amdgcn_readfirstlane(b1);
+#pragma unroll
+    for (int q = 0; q < kSrcSlots; ++q) {
+      const bool h = q < c.nsrc;
+      const int x = h ? static_cast<int>(p.src_node[b0 + q] - tl.a) : 0;
+      const int th = x / MPT;
+      c.scode[q] = __builtin_amdgcn_readfirstlane(h ? ((th >> 6) << 16) | ((th & 63) << 8) |
+                                                          (x % MPT)
+                                                    : -1);
+      c.samp[q] = h ? sample(b0 + q) : T(0);
+    }
+    const int fb[2] = {b1, b2}, fe[2] = {b2, b3};
+    const int64_t o0[2] = {tl.a - kFrameHalf, tl.a + TM - 1 - kFrameHalf};
+#pragma unroll
+    for (int sd = 0; sd < 2; ++sd) {
+      const int n = fe[sd] - fb[sd];
+      c.nfs[sd] = __builtin_amdgcn_readfirstlane(n < kFrameSrc ? n : kFrameSrc);
+      c.ffb[sd] = __builtin_amdgcn_readfirstlane(n > kFrameSrc ? fb[sd] + kFrameSrc : fe[sd]);
+      c.ffe[sd] = __builtin_amdgcn_readfirstlane(fe[sd]);
+#pragma unroll
+      for (int q = 0; q < kFrameSrc; ++q) {
+        const bool h = q < c.nfs[sd];
+        c.fcode[sd][q] = __builtin_amdgcn_readfirstlane(
+            h ? static_cast<int>(p.src_node[fb[sd] + q] - o0[sd]) : 0);
+        c.famp[sd][q] = h ? sample(fb[sd] + q) : T(0);
+      }
+    }
+  }
 
   const bool hl = c.wv == 0 && tl.lmode == kEndGhost;
   const bool hr = c.wv == NW - 1 && tl.rmode == kEndGhost;
   if (hl) {
     if (hr)
-      fused_run<T, NT, MPT, GEN, REC, true, true>(p, tl, c, S, u, uo);
+      fused_run<T, NT, MPT, GEN, EXT, true, true>(p, tl, c, S, u, uo);
     else
-      fused_run<T, NT, MPT, GEN, REC, true, false>(p, tl, c, S, u, uo);
+      fused_run<T, NT, MPT, GEN, EXT, true, false>(p, tl, c, S, u, uo);
   } else {
     if (hr)
-      fused_run<T, NT, MPT, GEN, REC, false, true>(p, tl, c, S, u, uo);
+      fused_run<T, NT, MPT, GEN, EXT, false, true>(p, tl, c, S, u, uo);
     else
-      fused_run<T, NT, MPT, GEN, REC, false, false>(p, tl, c, S, u, uo);
+      fused_run<T, NT, MPT, GEN, EXT, false, false>(p, tl, c, S, u, uo);
   }
 
   const int64_t rlo = tl.out_lo > tl.a ? tl.out_lo : tl.a;

@@ -4,11 +4,12 @@
 
 namespace rswr {
 
-// GEN: general tiles (node 0 inside the region), receivers recorded.
-// REC: a launch whose tiles may record receivers; each work-group takes the
-// recording code path only if its tile has receivers (a uniform branch), so
-// the others run the plain step.  Neither: the plain step only.
-template <typename T, int NT, int MPT, bool GEN, bool REC>
+// GEN: general tiles (node 0 inside the region), receivers recorded and
+// sources injected.  EXT: a launch whose tiles may record receivers or
+// inject interior sources; each work-group takes that code path only if its
+// tile has any (a uniform branch), so the others run the plain step.
+// Neither: the plain step only.
+template <typename T, int NT, int MPT, bool GEN, bool EXT>
 __global__ __launch_bounds__(NT) void k_fused(const UpdateArgs<T> p) {
   constexpr int NW = NT / 64;
   constexpr int TM = NT * MPT;
@@ -21,8 +22,10 @@ __global__ __launch_bounds__(NT) void k_fused(const UpdateArgs<T> p) {
   if (S <= 0 || S > kMaxFusedSpan) return;
   if constexpr (GEN) {
     fused_tile<T, NT, MPT, true, true>(p, tl, slot, S, st, edge);
-  } else if constexpr (REC) {
-    if (p.rec_ptr && p.rec_ptr[slot + 1] > p.rec_ptr[slot])
+  } else if constexpr (EXT) {
+    const int t3 = 3 * p.tile_idx[slot];
+    if ((p.rec_ptr && p.rec_ptr[slot + 1] > p.rec_ptr[slot]) ||
+        (p.src_ptr && p.src_ptr[t3 + 3] > p.src_ptr[t3]))
       fused_tile<T, NT, MPT, false, true>(p, tl, slot, S, st, edge);
     else
       fused_tile<T, NT, MPT, false, false>(p, tl, slot, S, st, edge);
@@ -42,7 +45,7 @@ hipError_t launch_fused(const UpdateArgs<T>& a, int threads, int per_thread, int
       if (kind == kFusedGeneral)                                                    \
         hipLaunchKernelGGL((k_fused<T, NT_, MPT_, true, true>), dim3(a.n_tiles),    \
                            dim3(NT_), 0, s, a);                                     \
-      else if (kind == kFusedRec)                                                   \
+      else if (kind == kFusedExt)                                                   \
         hipLaunchKernelGGL((k_fused<T, NT_, MPT_, false, true>), dim3(a.n_tiles),   \
                            dim3(NT_), 0, s, a);                                     \
       else                                                                          \

@@ -50,6 +50,9 @@ struct DevTables {
   int32_t* idx = nullptr;  // general tiles first, then the plain ones
   int64_t* lo = nullptr;
   int64_t* hi = nullptr;
+  int32_t* src_ptr = nullptr;  // per-tile interior sources (plans with sources)
+  int64_t* src_node = nullptr;
+  int32_t* src_id = nullptr;
   hipStream_t capture = nullptr;
 };
 
@@ -75,6 +78,15 @@ struct rswr_plan_s {
   std::vector<int32_t> idx;  // tile order of the launches: general ones first
   int32_t n_gen = 0;
   bool fused = false;  // rswr_solve runs one fused launch per span
+  // interior point sources (the pulse sources of Sec. 4): nodes, the
+  // caller's device samples [n][src_ld], and per tile three runs of
+  // (node, source id) -- register region, left frame, right frame
+  std::vector<int64_t> src_node;
+  const void* src_amp = nullptr;
+  int64_t src_ld = 0;
+  std::vector<int32_t> src_ptr;  // [3 * n_tiles + 1]
+  std::vector<int64_t> src_tnode;
+  std::vector<int32_t> src_tid;
   std::mutex mu;
   std::map<int, DevTables> dev;
   std::vector<GraphEntry> graphs;
@@ -329,6 +341,50 @@ bool choose_shape(rswr_plan_s& p) {
   return found;
 }
 
+// Interior point sources of a plan: checked, then listed per tile in three
+// runs -- sources of the tile's window inside its register region, sources
+// of the left neighbour window inside the left prediction frame, those of
+// the right neighbour inside the right frame -- each in source order (the
+// order of the additions at one node).  Sources run on the fused span only.
+rswr_status_t plan_sources(rswr_plan_s& p, const rswr_desc_t& D) {
+  if (D.n_src < 0) return fail(RSWR_ERR_INVALID_ARG, "n_src < 0");
+  if (D.n_src == 0) return RSWR_OK;
+  if (!D.src_node || !D.src_amp || D.src_ld < 1)
+    return fail(RSWR_ERR_INVALID_ARG, "sources need src_node, src_amp and src_ld >= 1");
+  if (!p.fused)
+    return fail(RSWR_ERR_UNSUPPORTED,
+                "interior sources run on the fused span (FIXED mode, span <= " +
+                    std::to_string(rswr::kMaxFusedSpan) + ", fusion not disabled)");
+  for (int32_t q = 0; q < D.n_src; ++q)
+    if (D.src_node[q] < 1 || D.src_node[q] > p.M - 2)
+      return fail(RSWR_ERR_INVALID_ARG, "source node outside 1..M-2");
+  p.src_node.assign(D.src_node, D.src_node + D.n_src);
+  p.src_amp = D.src_amp;
+  p.src_ld = D.src_ld;
+  const int64_t TM = int64_t(p.threads) * p.per_thread;
+  const int64_t H = rswr::kFrameHalf;
+  p.src_ptr.assign(1, 0);
+  auto run = [&](int32_t w, int64_t a, int64_t b) {
+    if (w >= 0 && w < p.N) {
+      a = std::max({a, p.lo[w], int64_t(1)});
+      b = std::min({b, p.hi[w], p.M - 2});
+      for (int32_t q = 0; q < D.n_src; ++q)
+        if (p.src_node[q] >= a && p.src_node[q] <= b) {
+          p.src_tnode.push_back(p.src_node[q]);
+          p.src_tid.push_back(q);
+        }
+    }
+    p.src_ptr.push_back(static_cast<int32_t>(p.src_tnode.size()));
+  };
+  for (const Tile& x : p.tiles) {
+    run(x.window, x.a, x.a + TM - 1);
+    const bool fl = x.lmode == rswr::kEndGhost, fr = x.rmode == rswr::kEndGhost;
+    run(fl ? x.window - 1 : -1, x.a - H, x.a + H - 1);
+    run(fr ? x.window + 1 : -1, x.a + TM - 1 - H, x.a + TM - 1 + H - 1);
+  }
+  return RSWR_OK;
+}
+
 rswr_status_t ensure_device(rswr_plan_s* p, DevTables** out, int* device) {
   int dev = 0;
   RSWR_HIP(hipGetDevice(&dev));
@@ -349,6 +405,20 @@ rswr_status_t ensure_device(rswr_plan_s* p, DevTables** out, int* device) {
     }
     RSWR_HIP(hipMemcpy(t.lo, p->lo.data(), p->N * sizeof(int64_t), hipMemcpyHostToDevice));
     RSWR_HIP(hipMemcpy(t.hi, p->hi.data(), p->N * sizeof(int64_t), hipMemcpyHostToDevice));
+    if (!p->src_node.empty()) {
+      const size_t ne = std::max<size_t>(p->src_tnode.size(), 1);
+      RSWR_HIP(hipMalloc(&t.src_ptr, p->src_ptr.size() * sizeof(int32_t)));
+      RSWR_HIP(hipMalloc(&t.src_node, ne * sizeof(int64_t)));
+      RSWR_HIP(hipMalloc(&t.src_id, ne * sizeof(int32_t)));
+      RSWR_HIP(hipMemcpy(t.src_ptr, p->src_ptr.data(), p->src_ptr.size() * sizeof(int32_t),
+                         hipMemcpyHostToDevice));
+      if (!p->src_tnode.empty()) {
+        RSWR_HIP(hipMemcpy(t.src_node, p->src_tnode.data(),
+                           p->src_tnode.size() * sizeof(int64_t), hipMemcpyHostToDevice));
+        RSWR_HIP(hipMemcpy(t.src_id, p->src_tid.data(), p->src_tid.size() * sizeof(int32_t),
+                           hipMemcpyHostToDevice));
+      }
+    }
     RSWR_HIP(hipStreamCreateWithFlags(&t.capture, hipStreamNonBlocking));
     it = p->dev.emplace(dev, t).first;
   }
@@ -405,6 +475,13 @@ rswr::UpdateArgs<T> update_args(const rswr_plan_s& p, const DevTables& d,
   a.r = T(1.0 / (2.0 * p.dx));
   a.lo = d.lo;
   a.hi = d.hi;
+  if (!p.src_node.empty()) {
+    a.src_ptr = d.src_ptr;
+    a.src_node = d.src_node;
+    a.src_id = d.src_id;
+    a.src_amp = static_cast<const T*>(p.src_amp);
+    a.src_ld = p.src_ld;
+  }
   return a;
 }
 
@@ -435,7 +512,7 @@ hipError_t launch_update_pair(const rswr_plan_s& p, rswr::UpdateArgs<T> a,
 
 // One fused span: the general tiles, then every other tile in one launch
 // (`a.rec_ptr`: CSR over the general list then the plain list; tiles with
-// receivers take the recording path inside that launch).
+// receivers or interior sources take the extended path inside that launch).
 template <typename T>
 hipError_t launch_fused_span(const rswr_plan_s& p, rswr::UpdateArgs<T> a,
                              const int32_t* gen_idx, int32_t n_gen, const int32_t* fast_idx,
@@ -454,7 +531,9 @@ hipError_t launch_fused_span(const rswr_plan_s& p, rswr::UpdateArgs<T> a,
     a.n_tiles = n_fast;
     a.rec_ptr = rec_ptr ? rec_ptr + n_gen : nullptr;
     return rswr::launch_fused<T>(a, p.threads, p.per_thread,
-                                 rec_ptr ? rswr::kFusedRec : rswr::kFusedPlain, s);
+                                 (rec_ptr || a.src_ptr) ? rswr::kFusedExt
+                                                        : rswr::kFusedPlain,
+                                 s);
   }
   return hipSuccess;
 }
@@ -885,6 +964,10 @@ rswr_status_t rswr_plan(const rswr_desc_t* desc, rswr_plan_t* out) {
   for (size_t t = 0; t < p->tiles.size(); ++t)
     if (!p->tiles[t].general) p->idx.push_back(static_cast<int32_t>(t));
   p->fused = D.no_fuse == 0 && fuse_eligible(*p);
+  if ((st = plan_sources(*p, D)) != RSWR_OK) {
+    delete p;
+    return st;
+  }
   *out = p;
   return RSWR_OK;
 }
@@ -901,6 +984,9 @@ rswr_status_t rswr_plan_destroy(rswr_plan_t p) {
     (void)hipSetDevice(kv.first);
     (void)hipFree(kv.second.tiles);
     (void)hipFree(kv.second.idx);
+    (void)hipFree(kv.second.src_ptr);
+    (void)hipFree(kv.second.src_node);
+    (void)hipFree(kv.second.src_id);
     (void)hipFree(kv.second.lo);
     (void)hipFree(kv.second.hi);
     if (kv.second.capture) (void)hipStreamDestroy(kv.second.capture);
@@ -965,6 +1051,8 @@ rswr_status_t rswr_predict(rswr_plan_t p, const void* state, const void* f_a,
                            void* stream) {
   if (!p || !state || !f_a || !f_b || !flux)
     return fail(RSWR_ERR_INVALID_ARG, "null pointer");
+  if (!p->src_node.empty())
+    return fail(RSWR_ERR_UNSUPPORTED, "plans with interior sources run rswr_span / rswr_solve");
   if (n0 < 0) return fail(RSWR_ERR_INVALID_ARG, "n0 must be >= 0");
   if (span_hat < 1 || span_hat > p->S_max)
     return fail(RSWR_ERR_SPAN, "span_hat outside 1.." + std::to_string(p->S_max));
@@ -1010,6 +1098,8 @@ rswr_status_t rswr_update(rswr_plan_t p, const void* state_in, const void* f_a,
                           void* stream) {
   if (!p || !state_in || !f_a || !f_b || !state_out || (!flux && p->N > 1))
     return fail(RSWR_ERR_INVALID_ARG, "null pointer");
+  if (!p->src_node.empty())
+    return fail(RSWR_ERR_UNSUPPORTED, "plans with interior sources run rswr_span / rswr_solve");
   if (n0 < 0) return fail(RSWR_ERR_INVALID_ARG, "n0 must be >= 0");
   if (state_in == state_out) return fail(RSWR_ERR_INVALID_ARG, "state_out aliases state_in");
   if (!span_dev && (span < 1 || span > p->S_max))
@@ -1047,6 +1137,8 @@ rswr_status_t rswr_span(rswr_plan_t p, const void* state_in, const void* f_a, co
   if (state_in == state_out) return fail(RSWR_ERR_INVALID_ARG, "state_out aliases state_in");
   if (span < 1 || span > p->S)
     return fail(RSWR_ERR_SPAN, "span outside 1.." + std::to_string(p->S));
+  if (!p->src_node.empty() && n0 + span > p->src_ld)
+    return fail(RSWR_ERR_INVALID_ARG, "the span runs past the source samples (src_ld)");
   DevTables* d = nullptr;
   rswr_status_t st = ensure_device(p, &d, nullptr);
   if (st != RSWR_OK) return st;
@@ -1102,6 +1194,8 @@ rswr_status_t rswr_solve(rswr_plan_t p, void* state, const void* f_a, const void
     return fail(RSWR_ERR_INVALID_ARG, "negative n0, n_steps or n_rec");
   if (n_rec > 0 && (!rec_idx || !traces))
     return fail(RSWR_ERR_INVALID_ARG, "receivers need rec_idx and traces");
+  if (!p->src_node.empty() && n0 + n_steps > p->src_ld)
+    return fail(RSWR_ERR_INVALID_ARG, "the solve runs past the source samples (src_ld)");
   if (n_steps == 0) return RSWR_OK;
   const WsLayout L = ws_layout(*p, n_rec);
   if (!workspace || ws_bytes < L.total)
@@ -1221,6 +1315,8 @@ rswr_status_t rswr_solve_adjoint(rswr_plan_t p, const void* checkpoints, const v
     return fail(RSWR_ERR_INVALID_ARG, "null pointer");
   if (p->mode != RSWR_SPAN_FIXED)
     return fail(RSWR_ERR_UNSUPPORTED, "rswr_solve_adjoint runs FIXED plans");
+  if (!p->src_node.empty())
+    return fail(RSWR_ERR_UNSUPPORTED, "rswr_solve_adjoint: plans with interior sources");
   if (n_steps < 1 || n_rec < 0 || (n_rec > 0 && (!rec_idx || !grad_traces)))
     return fail(RSWR_ERR_INVALID_ARG, "bad n_steps, receivers or grad_traces");
   for (int32_t r = 0; r < n_rec; ++r)
@@ -1507,6 +1603,10 @@ rswr_status_t rswr_batch_plan(const rswr_plan_t* plans, int32_t n, rswr_batch_t*
     if (!p) {
       delete b;
       return fail(RSWR_ERR_INVALID_ARG, "null plan " + std::to_string(i));
+    }
+    if (!p->src_node.empty()) {
+      delete b;
+      return fail(RSWR_ERR_UNSUPPORTED, "batched plans take no interior sources");
     }
     if (i == 0) b->dtype = p->dtype;
     if (p->dtype != b->dtype) {

@@ -15,6 +15,11 @@ constexpr int kMaxFusedSpan = kFrameHalf - 1;
 // Receivers one launched tile of the fused span records (the host repeats a
 // tile holding more, one copy per group); adjoint sources held in registers.
 constexpr int kRecSlots = 4;
+// Interior sources a fused tile injects from registers: kSrcSlots in its
+// region, kFrameSrc in each prediction frame; further ones are read from
+// memory every step.
+constexpr int kSrcSlots = 4;
+constexpr int kFrameSrc = 2;
 
 // Sentinel for "no left-input ghost in this tile".
 constexpr int64_t kNoNode = INT64_MIN;
@@ -80,6 +85,15 @@ struct UpdateArgs {
   const int64_t* lo;
   const int64_t* hi;
   T* flux_out;
+  // interior point sources (nullable; fused span only): for tile number t,
+  // entries src_ptr[3t] .. src_ptr[3t+3) of (src_node, src_id) in three runs
+  // -- the tile's register region, its left frame, its right frame -- each
+  // in source order; the step from level n adds src_amp[id * src_ld + n]
+  const int32_t* src_ptr;
+  const int64_t* src_node;
+  const int32_t* src_id;
+  const T* src_amp;
+  int64_t src_ld;
   int64_t M, n0, trace_ld, trace_col0;
   int32_t n_tiles, span, ld, pad;
   T c2, k, q, r;
@@ -172,9 +186,10 @@ hipError_t launch_update(const UpdateArgs<T>& a, int threads, int per_thread,
                          bool general, hipStream_t s);
 // Fused span (rswr_fused.hip): predict folded into the update; needs
 // 1 <= span <= kMaxFusedSpan and inputs only at region ends.
-// kFusedRec: a launch in which some tiles record receivers (CSR rec_ptr
-// over its slots); kFusedGeneral: general tiles.
-enum { kFusedPlain = 0, kFusedRec = 1, kFusedGeneral = 2 };
+// kFusedExt: a launch in which some tiles record receivers (CSR rec_ptr
+// over its slots) or inject interior sources (src_ptr); kFusedGeneral:
+// general tiles.
+enum { kFusedPlain = 0, kFusedExt = 1, kFusedGeneral = 2 };
 template <typename T>
 hipError_t launch_fused(const UpdateArgs<T>& a, int threads, int per_thread, int kind,
                         hipStream_t s);

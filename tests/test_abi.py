@@ -191,3 +191,42 @@ def test_batch_recipe_plans_all_fuse():
     assert all(p.info["fused"] for p in plans)
     assert max(spans) == 63 and min(spans) >= 17
     assert len(report) >= 5
+
+
+def raw_plan(M, N, P, nodes, ld=100, amp_ptr=0x1000, **kw):
+    """rswr_plan through the raw C-ABI with interior sources; the sample
+    pointer is only stored by the host code, never read here."""
+    L = rs.lib()
+    d = rs._Desc()
+    d.x_a, d.x_b, d.n_points = 0.0, 1.0, M
+    d.a, d.courant, d.courant_num, d.courant_den = 1.0, 0.9, 9, 10
+    d.n_sub, d.overlap = N, P
+    d.dtype = kw.get("dtype", 1)
+    d.span_mode = kw.get("span_mode", 0)
+    d.no_fuse = kw.get("no_fuse", 0)
+    nodes = np.ascontiguousarray(nodes, np.int64)
+    d.n_src = len(nodes)
+    d.src_node = nodes.ctypes.data
+    d.src_amp = amp_ptr
+    d.src_ld = ld
+    h = ctypes.c_void_p()
+    st = L.rswr_plan(ctypes.byref(d), ctypes.byref(h))
+    return st, h
+
+
+def test_source_plan_rules():
+    L = rs.lib()
+    st, h = raw_plan(4097, 8, 64, [1, 600, 4095])
+    assert st == 0
+    L.rswr_plan_destroy(h)
+    for bad in ([0], [4096], [-3], [5000]):
+        st, _ = raw_plan(4097, 8, 64, bad)
+        assert st == 1, bad  # RSWR_ERR_INVALID_ARG
+    st, _ = raw_plan(4097, 8, 64, [100], amp_ptr=0)
+    assert st == 1
+    st, _ = raw_plan(4097, 8, 64, [100], ld=0)
+    assert st == 1
+    # sources need the fused span
+    for kw in ({"no_fuse": 1}, {"span_mode": 1}):
+        st, _ = raw_plan(4097, 8, 64, [100], **kw)
+        assert rs.STATUS[st] == "RSWR_ERR_UNSUPPORTED", kw

@@ -1,0 +1,198 @@
+"""GPU parity of interior point sources (the pulse sources of the paper's
+experiments, Sec. 4) on the fused span: tiles inject the sources in their
+register region, prediction frames those of the neighbouring window, both
+after the leapfrog update of the level (the oracle's reading).  States,
+traces and flux rows are bit-identical to the CPU oracle."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2203_10477_amd as rs
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+NP = {torch.float64: np.float64, torch.float32: np.float32}
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+
+
+def dev(x, dtype):
+    return torch.as_tensor(np.ascontiguousarray(x), dtype=dtype, device=DEV)
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+def busy(M, n_steps, seed):
+    g = np.random.default_rng(seed)
+    st = workloads.smooth_state(M, g, shift=2e-3)
+    t = np.arange(n_steps + 1) * 0.9 / (M - 1)
+    return st, np.sin(2 * np.pi * 7 * t) + 0.3, np.cos(2 * np.pi * 5 * t)
+
+
+def lay_of(plan):
+    lo, hi, _, _ = plan.layout()
+    return oracle.explicit_layout(plan.M, lo, hi)
+
+
+def placed(lay, tiles, g, extra=()):
+    """Sources on output nodes and around them (inside prediction frames),
+    on input ends, mid-overlap, at tile region ends, on nodes 1 and M-2, a
+    repeated node, a cluster of seven within one tile and one frame (more
+    than the register slots), and a few at random."""
+    M = lay.M
+    nodes = [1, M - 2]
+    for i in range(lay.N - 1):
+        o_l, o_r = int(lay.lo[i + 1]), int(lay.hi[i])
+        nodes += [o_l, o_l + 1, o_l - 5, o_r, o_r - 2, o_r + 3, (o_l + o_r) // 2]
+    for a, b, *_ in tiles[:6]:
+        nodes += [int(a), int(b)]
+    c = int(lay.lo[1]) if lay.N > 1 else M // 2
+    nodes += [c - 9, c - 6, c - 4, c - 1, c + 2, c + 4, c + 7]
+    nodes += list(g.integers(1, M - 1, 5))
+    nodes.append(nodes[3])
+    nodes += list(extra)
+    nodes = np.array([n for n in nodes if 1 <= n <= M - 2], np.int64)
+    return nodes
+
+
+CASES = [
+    # M, N, P, windows, tile, n_steps, n0, span
+    (4097, 8, 64, None, None, 300, 0, 0),
+    (4097, 8, 64, None, (128, 8), 200, 7, 0),       # two waves per tile
+    (6000, 3, 40, None, (64, 8), 190, 0, 0),        # several tiles per window
+    (20001, 16, 64, None, (256, 16), 177, 2, 0),    # four waves per tile
+    (4097, 8, 64, None, (64, 33), 130, 0, 63),      # the largest fused span
+    (2001, 3, 0, ([0, 5, 1970], [30, 1995, 2000]), (64, 8), 160, 0, 0),  # Dirichlet frames
+    (2001, 3, 0, ([0, 400, 800], [700, 911, 2000]), (64, 8), 150, 0, 0),  # narrow window
+]
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+@pytest.mark.parametrize("case", range(len(CASES)))
+def test_solve_with_sources_bitwise(dtype, case):
+    M, N, P, win, tile, n_steps, n0, span = CASES[case]
+    if dtype == torch.float64 and tile is not None and tile[1] > 22:
+        pytest.skip("shape not built for FP64")
+    say("sources-solve", dtype, CASES[case])
+    npdt = NP[dtype]
+    g = np.random.default_rng(40 + case)
+    probe = rs.Plan(M, N, P, windows=win, tile=tile, span=span, dtype=dtype)
+    lay = lay_of(probe)
+    nodes = placed(lay, probe.tiles(), g)
+    amp = (g.standard_normal((len(nodes), n0 + n_steps + 3)) * 0.05).astype(npdt)
+    amp_d = dev(amp, dtype)
+    plan = rs.Plan(M, N, P, windows=win, tile=tile, span=span, dtype=dtype,
+                   sources=(nodes, amp_d))
+    assert plan.info["fused"] == 1
+    st0, fa, fb = busy(M, n0 + n_steps, seed=case)
+    st0, fa, fb = st0.astype(npdt), fa.astype(npdt), fb.astype(npdt)
+    rec = np.unique(np.concatenate([[0, 1, M - 2, M - 1], nodes[:6]]))
+    ref, tr_ref, _ = oracle.rswr(lay, plan.info["lambda"], plan.info["dx"], fa, fb,
+                                 n_steps, span=plan.span, state=st0, n0=n0, rec=rec,
+                                 src=(nodes, amp))
+    st = dev(st0, dtype)
+    tr = rs.rswr_solve(plan, st, dev(fa, dtype), dev(fb, dtype), n_steps, n0=n0,
+                       receivers=rec)
+    torch.cuda.synchronize()
+    assert np.array_equal(host(st), ref)
+    assert np.array_equal(host(tr), tr_ref)
+    # without receivers: the tiles with sources alone take the extended path
+    st = dev(st0, dtype)
+    rs.rswr_solve(plan, st, dev(fa, dtype), dev(fb, dtype), n_steps, n0=n0)
+    torch.cuda.synchronize()
+    assert np.array_equal(host(st), ref)
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_span_with_sources_matches_predict_update(dtype):
+    """rswr_span with sources against the oracle's predict + update with
+    sources; the flux rows of the input ends against the oracle's
+    prediction (sources inside the frames)."""
+    M, N, P = 4097, 8, 64
+    say("sources-span", dtype)
+    npdt = NP[dtype]
+    g = np.random.default_rng(5)
+    probe = rs.Plan(M, N, P, dtype=dtype)
+    lay = lay_of(probe)
+    nodes = placed(lay, probe.tiles(), g)
+    amp = (g.standard_normal((len(nodes), 400)) * 0.05).astype(npdt)
+    plan = rs.Plan(M, N, P, dtype=dtype, sources=(nodes, dev(amp, dtype)))
+    st0, fa, fb = busy(M, 500, seed=4)
+    st0, fa, fb = st0.astype(npdt), fa.astype(npdt), fb.astype(npdt)
+    n0 = 17
+    fa_d, fb_d, st_d = dev(fa, dtype), dev(fb, dtype), dev(st0, dtype)
+    lam, dx = plan.info["lambda"], plan.info["dx"]
+    for S in (plan.span, 5, 1):
+        ref_flux = oracle.predict(lay, lam, dx, fa, fb, n0, S, st0, ld=plan.flux_ld,
+                                  src=(nodes, amp))
+        ref, _ = oracle.update(lay, lam, dx, fa, fb, n0, S, st0, ref_flux,
+                               src=(nodes, amp))
+        fl = plan.flux_buffer()
+        out = rs.rswr_span(plan, st_d, fa_d, fb_d, n0, span=S, flux=fl)
+        torch.cuda.synchronize()
+        assert np.array_equal(host(out), ref), S
+        rows = sorted({2 * (w - 1) for _, _, _, _, w, lm, _, _ in plan.tiles() if lm == 1} |
+                      {2 * w + 1 for _, _, _, _, w, _, rm, _ in plan.tiles() if rm == 1})
+        got = host(fl).reshape(-1, plan.flux_ld)
+        want = ref_flux.reshape(-1, plan.flux_ld)
+        assert np.array_equal(got[rows, :S], want[rows, :S]), S
+    with pytest.raises(rs.RSWRError):
+        rs.rswr_span(plan, st_d, fa_d, fb_d, 395, span=plan.span)  # past the samples
+
+
+def test_sources_rejected_where_not_built():
+    M, N, P = 4097, 8, 64
+    amp = torch.zeros(2, 100, dtype=torch.float64, device=DEV)
+    plan = rs.Plan(M, N, P, sources=([100, 200], amp))
+    st = torch.zeros(2, M, dtype=torch.float64, device=DEV)
+    f = torch.zeros(200, dtype=torch.float64, device=DEV)
+    with pytest.raises(rs.RSWRError):
+        rs.rswr_solve(plan, st, f, f, 150)  # past the samples
+    with pytest.raises(rs.RSWRError):
+        rs.rswr_predict(plan, st, f, f, 0, 4, plan.flux_buffer())
+    ck = plan.checkpoint_buffer(50)
+    with pytest.raises(rs.RSWRError):
+        rs.rswr_solve_adjoint(plan, ck, f, f, 50, [300], torch.zeros(1, 50, dtype=torch.float64,
+                                                                    device=DEV))
+    with pytest.raises(rs.RSWRError):
+        rs.Batch([plan])
+    with pytest.raises(rs.RSWRError):
+        rs.Plan(M, N, P, fuse=False, sources=([100, 200], amp))
+
+
+def test_large_fp32_pulse_sources_sampled():
+    """2^24 nodes, 4096 windows, overlap 64, FP32, one pulse source per
+    window (the recipe standing in for the paper's N pulse sources): two
+    spans, sampled windows bitwise against the oracle's literal predict +
+    update with the same sources."""
+    prob = workloads.config5(np.float32)
+    say("large-2^24-fp32-sources")
+    g = workloads.rng(77)
+    nodes, amp = workloads.pulse_sources(prob.M, prob.N, 200, g)
+    amp = amp.astype(np.float32)
+    # make the first samples large so the pulses are already running
+    amp[:, :80] += np.float32(0.01)
+    plan = rs.Plan(prob.M, prob.N, prob.P, dtype=torch.float32,
+                   sources=(nodes, dev(amp, torch.float32)))
+    S = plan.span
+    lay = lay_of(plan)
+    st32 = workloads.smooth_state(prob.M, np.random.default_rng(78),
+                                  shift=prob.lam * prob.dx).astype(np.float32)
+    fa, fb = prob.sources()
+    st_d = dev(st32, torch.float32)
+    out = host(rs.rswr_span(plan, st_d, dev(fa, torch.float32), dev(fb, torch.float32), 0))
+    ref_flux = oracle.predict(lay, prob.lam, prob.dx, fa, fb, 0, S, st32, ld=plan.flux_ld,
+                              src=(nodes, amp))
+    wins = [0, 1, 2, 777, 2048, 4000, prob.N - 2, prob.N - 1]
+    ref, _ = oracle.update(lay, prob.lam, prob.dx, fa, fb, 0, S, st32, ref_flux,
+                           windows=wins, src=(nodes, amp))
+    for w in wins:
+        sl = slice(lay.own_lo[w], lay.own_hi[w] + 1)
+        assert np.array_equal(out[:, sl], ref[:, sl]), w
