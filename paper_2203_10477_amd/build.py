@@ -17,8 +17,10 @@ FLAGS = [
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-command-line-argument",
 ]
-SOURCES = ["rswr_fused.hip", "rswr_batch.hip", "rswr_kernels.hip", "rswr_adjoint.hip",
-           "rswr_host.cpp"]
+# the heaviest translation units first
+SOURCES = ["rswr_fused_ext_f32.hip", "rswr_fused_ext_f64.hip", "rswr_fused_gen.hip",
+           "rswr_adjoint.hip", "rswr_fused_plain.hip", "rswr_kernels.hip", "rswr_batch.hip",
+           "rswr_fused.hip", "rswr_host.cpp"]
 
 
 def _compile(src, verbose):

@@ -40,7 +40,7 @@ __global__ __launch_bounds__(NT) void k_fused_batch(const BatchArgs<T> b) {
     p.k = in.k;
     p.q = in.q;
     p.r = in.r;
-    fused_tile<T, NT, MPT, false, false>(p, tl, item, S, st, edge);
+    fused_tile<T, NT, MPT, false, false, false>(p, tl, item, S, st, edge);
   }
 }
 

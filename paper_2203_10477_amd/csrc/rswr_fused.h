@@ -139,7 +139,7 @@ __device__ __forceinline__ void frame_sources(const UpdateArgs<T>& p,
 // keeps the fluxes.  The lane shifts fill the wave's ends with zero: the
 // zero data of a cut region end; input ghosts, Dirichlet values and the
 // neighbouring wave's node replace it where they apply.
-template <typename T, int NT, int MPT, bool GEN, bool EXT, bool HL, bool HR>
+template <typename T, int NT, int MPT, bool GEN, bool REC, bool SRC, bool HL, bool HR>
 __device__ __forceinline__ void fused_step(const UpdateArgs<T>& p,
                                            const FusedCtx<T, NT, MPT>& c,
                                            const T (&cur)[MPT], T (&old)[MPT],
@@ -156,7 +156,7 @@ __device__ __forceinline__ void fused_step(const UpdateArgs<T>& p,
       const T d = rd_lane(c.vA, s + 1);
       frame_dirichlet(true, c.fmL, d, lo);
     }
-    if (EXT && (c.nfs[0] > 0 || c.ffe[0] > c.ffb[0]))
+    if (SRC && (c.nfs[0] > 0 || c.ffe[0] > c.ffb[0]))
       frame_sources(p, c, 0, c.a - kFrameHalf, s, lo);
     if (c.keep) fl = wr_lane(F, s, fl, c.lane);
     L = (c.lane == 0) ? fma_(c.nq, F, cur[1]) : L;
@@ -167,7 +167,7 @@ __device__ __forceinline__ void fused_step(const UpdateArgs<T>& p,
       const T d = rd_lane(c.vB, s + 1);
       frame_dirichlet(true, c.fmR, d, ro);
     }
-    if (EXT && (c.nfs[1] > 0 || c.ffe[1] > c.ffb[1]))
+    if (SRC && (c.nfs[1] > 0 || c.ffe[1] > c.ffb[1]))
       frame_sources(p, c, 1, c.a + NT * MPT - 1 - kFrameHalf, s, ro);
     if (c.keep) fr = wr_lane(F, s, fr, c.lane);
     R = (c.lane == 63) ? fma_(c.pq, F, cur[MPT - 2]) : R;
@@ -194,7 +194,7 @@ __device__ __forceinline__ void fused_step(const UpdateArgs<T>& p,
                              rd_lane(c.vA, s + 1));
   else
     step_chunk<T, MPT, false>(cur, old, L, R, p.c2, p.k, 0, 0, T(0), T(0));
-  if (EXT && (c.nsrc > 0 || c.sfe > c.sfb)) {
+  if (SRC && (c.nsrc > 0 || c.sfe > c.sfb)) {
     // interior sources of level n+1, in source order
 #pragma unroll
     for (int q = 0; q < kSrcSlots; ++q) {
@@ -209,7 +209,7 @@ __device__ __forceinline__ void fused_step(const UpdateArgs<T>& p,
       for (int e = 0; e < MPT; ++e) old[e] = (d == e) ? old[e] + g : old[e];
     }
   }
-  if (EXT && c.nrec > 0) {
+  if (REC && c.nrec > 0) {
     // receivers: the sample of level n+1 goes to lane s of tr[q] (all
     // branches wave-uniform)
     const T da = rd_lane(c.vA, s + 1), db = rd_lane(c.vB, s + 1);
@@ -227,7 +227,7 @@ __device__ __forceinline__ void fused_step(const UpdateArgs<T>& p,
   }
 }
 
-template <typename T, int NT, int MPT, bool GEN, bool EXT, bool HL, bool HR>
+template <typename T, int NT, int MPT, bool GEN, bool REC, bool SRC, bool HL, bool HR>
 __device__ __forceinline__ void fused_run(const UpdateArgs<T>& p, const Tile& tl,
                                           const FusedCtx<T, NT, MPT>& c, int S,
                                           T (&u)[MPT], T (&uo)[MPT]) {
@@ -241,17 +241,17 @@ __device__ __forceinline__ void fused_run(const UpdateArgs<T>& p, const Tile& tl
   if constexpr (HR) frame_load(p, tl.a + TM - 1, tl.window + 1, c.lane, rc, ro);
   int s = 0;
   for (; s + 1 < S; s += 2) {
-    fused_step<T, NT, MPT, GEN, EXT, HL, HR>(p, c, u, uo, lc, lo, rc, ro, fl, fr, tr, s);
-    fused_step<T, NT, MPT, GEN, EXT, HL, HR>(p, c, uo, u, lo, lc, ro, rc, fl, fr, tr, s + 1);
+    fused_step<T, NT, MPT, GEN, REC, SRC, HL, HR>(p, c, u, uo, lc, lo, rc, ro, fl, fr, tr, s);
+    fused_step<T, NT, MPT, GEN, REC, SRC, HL, HR>(p, c, uo, u, lo, lc, ro, rc, fl, fr, tr, s + 1);
   }
   if (s < S)
-    fused_step<T, NT, MPT, GEN, EXT, HL, HR>(p, c, u, uo, lc, lo, rc, ro, fl, fr, tr, s);
+    fused_step<T, NT, MPT, GEN, REC, SRC, HL, HR>(p, c, u, uo, lc, lo, rc, ro, fl, fr, tr, s);
   // per-span results, one value per lane and step: no stores in the loop
   if (p.flux_out != nullptr && c.lane < S) {
     if constexpr (HL) p.flux_out[static_cast<int64_t>(2 * tl.fl) * p.ld + c.lane] = fl;
     if constexpr (HR) p.flux_out[static_cast<int64_t>(2 * tl.fr + 1) * p.ld + c.lane] = fr;
   }
-  if (EXT && c.nrec > 0) {
+  if (REC && c.nrec > 0) {
 #pragma unroll
     for (int q = 0; q < kRecSlots; ++q)
       if (q < c.nrec && c.rwv[q] == c.wv && c.lane < S) c.rdst[q][c.lane] = tr[q];
@@ -260,7 +260,7 @@ __device__ __forceinline__ void fused_run(const UpdateArgs<T>& p, const Tile& tl
 
 // One tile over S levels: load, step (with the frames its waves carry),
 // store.  `st` is the LDS staging buffer, `edge` the cross-wave slots.
-template <typename T, int NT, int MPT, bool GEN, bool EXT>
+template <typename T, int NT, int MPT, bool GEN, bool REC, bool SRC>
 __device__ __forceinline__ void fused_tile(const UpdateArgs<T>& p, const Tile& tl, int slot,
                                            int S, T* st, T (*edge)[2][NT / 64]) {
   constexpr int NW = NT / 64;
@@ -321,7 +321,7 @@ __device__ __forceinline__ void fused_tile(const UpdateArgs<T>& p, const Tile& t
   }
   // receivers this tile records (REC instantiations; at most kRecSlots)
   c.nrec = 0;
-  if (EXT && p.rec_ptr) {
+  if (REC && p.rec_ptr) {
     const int rb = p.rec_ptr[slot], re = p.rec_ptr[slot + 1];
     c.nrec = re - rb < kRecSlots ? re - rb : kRecSlots;
 #pragma unroll
@@ -347,12 +347,12 @@ __device__ __forceinline__ void fused_tile(const UpdateArgs<T>& p, const Tile& t
     }
     c.nrec = __builtin_amdgcn_readfirstlane(c.nrec);
   }
-  // interior sources (EXT instantiations)
+  // interior sources (SRC instantiations)
   c.nsrc = 0;
   c.sfb = c.sfe = 0;
 #pragma unroll
   for (int sd = 0; sd < 2; ++sd) c.nfs[sd] = c.ffb[sd] = c.ffe[sd] = 0;
-  if (EXT && p.src_ptr) {
+  if (SRC && p.src_ptr) {
     const int t3 = 3 * p.tile_idx[slot];
     const int b0 = p.src_ptr[t3], b1 = p.src_ptr[t3 + 1];
     const int b2 = p.src_ptr[t3 + 2], b3 = p.src_ptr[t3 + 3];
@@ -396,14 +396,14 @@ __device__ __forceinline__ void fused_tile(const UpdateArgs<T>& p, const Tile& t
   const bool hr = c.wv == NW - 1 && tl.rmode == kEndGhost;
   if (hl) {
     if (hr)
-      fused_run<T, NT, MPT, GEN, EXT, true, true>(p, tl, c, S, u, uo);
+      fused_run<T, NT, MPT, GEN, REC, SRC, true, true>(p, tl, c, S, u, uo);
     else
-      fused_run<T, NT, MPT, GEN, EXT, true, false>(p, tl, c, S, u, uo);
+      fused_run<T, NT, MPT, GEN, REC, SRC, true, false>(p, tl, c, S, u, uo);
   } else {
     if (hr)
-      fused_run<T, NT, MPT, GEN, EXT, false, true>(p, tl, c, S, u, uo);
+      fused_run<T, NT, MPT, GEN, REC, SRC, false, true>(p, tl, c, S, u, uo);
     else
-      fused_run<T, NT, MPT, GEN, EXT, false, false>(p, tl, c, S, u, uo);
+      fused_run<T, NT, MPT, GEN, REC, SRC, false, false>(p, tl, c, S, u, uo);
   }
 
   const int64_t rlo = tl.out_lo > tl.a ? tl.out_lo : tl.a;

@@ -1,0 +1,61 @@
+// rswr_fused_kernel.h -- the fused span kernel of one problem (one launch
+// per span, one work-group per tile; device code in rswr_fused.h) and its
+// launcher over the built shapes.  Each launch kind is instantiated in a
+// translation unit of its own (rswr_fused_*.hip) so that they compile in
+// parallel.
+#pragma once
+
+#include "rswr_fused.h"
+
+namespace rswr {
+
+// kFusedGeneral: general tiles (node 0 inside the region), receivers
+// recorded and sources injected.  kFusedExt: a launch whose tiles may
+// record receivers or inject interior sources; each work-group takes the
+// code path its tile needs (a uniform branch), the others run the plain
+// step.  kFusedPlain: the plain step only.
+template <typename T, int NT, int MPT, int KIND>
+__global__ __launch_bounds__(NT) void k_fused(const UpdateArgs<T> p) {
+  constexpr int NW = NT / 64;
+  constexpr int TM = NT * MPT;
+  constexpr int TMP = TM + (TM >> 5) + 1;
+  __shared__ T st[TMP];
+  __shared__ T edge[2][2][NW];
+  const int slot = xcd_tile(blockIdx.x, gridDim.x);
+  const Tile tl = p.tiles[p.tile_idx[slot]];
+  const int S = p.span;
+  if (S <= 0 || S > kMaxFusedSpan) return;
+  if constexpr (KIND == kFusedGeneral) {
+    fused_tile<T, NT, MPT, true, true, true>(p, tl, slot, S, st, edge);
+  } else if constexpr (KIND == kFusedExt) {
+    const int t3 = 3 * p.tile_idx[slot];
+    if (p.src_ptr && p.src_ptr[t3 + 3] > p.src_ptr[t3])
+      fused_tile<T, NT, MPT, false, true, true>(p, tl, slot, S, st, edge);
+    else if (p.rec_ptr && p.rec_ptr[slot + 1] > p.rec_ptr[slot])
+      fused_tile<T, NT, MPT, false, true, false>(p, tl, slot, S, st, edge);
+    else
+      fused_tile<T, NT, MPT, false, false, false>(p, tl, slot, S, st, edge);
+  } else {
+    fused_tile<T, NT, MPT, false, false, false>(p, tl, slot, S, st, edge);
+  }
+}
+
+template <typename T, int KIND>
+hipError_t launch_fused_kind(const UpdateArgs<T>& a, int threads, int per_thread,
+                             hipStream_t s) {
+  if (a.n_tiles <= 0) return hipSuccess;
+#define RSWR_LAUNCH(NT_, MPT_)                                                      \
+  if (threads == NT_ && per_thread == MPT_) {                                     \
+    if constexpr (sizeof(T) == 8 && MPT_ > 22) return hipErrorInvalidValue;      \
+    else {                                                                        \
+      hipLaunchKernelGGL((k_fused<T, NT_, MPT_, KIND>), dim3(a.n_tiles), dim3(NT_), 0, \
+                         s, a);                                                   \
+      return hipGetLastError();                                                   \
+    }                                                                             \
+  }
+  RSWR_SHAPES(RSWR_LAUNCH)
+#undef RSWR_LAUNCH
+  return hipErrorInvalidValue;
+}
+
+}  // namespace rswr

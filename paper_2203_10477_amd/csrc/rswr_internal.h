@@ -193,6 +193,9 @@ enum { kFusedPlain = 0, kFusedExt = 1, kFusedGeneral = 2 };
 template <typename T>
 hipError_t launch_fused(const UpdateArgs<T>& a, int threads, int per_thread, int kind,
                         hipStream_t s);
+template <typename T, int KIND>
+hipError_t launch_fused_kind(const UpdateArgs<T>& a, int threads, int per_thread,
+                             hipStream_t s);
 // Batched fused span: one persistent launch over the items with `grid`
 // work-groups (at most the items); fused_batch_capacity gives the kernel's
 // resident work-groups on the current device (0: shape not built).
