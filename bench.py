@@ -182,6 +182,37 @@ def adjoint_section(reps):
             "checkpoint_bytes": ck.numel() * 8}
 
 
+def sources_section(reps, tile):
+    """The pulse-source form: the large case (2^24 nodes, 4096 windows,
+    overlap 64, 2*10^4 steps, FP32) with one Ricker pulse source in each of
+    its 4096 windows, the setting of the paper's experiments (N pulse
+    sources for N sub-domains); against the same solve without them."""
+    import numpy as np
+    import torch
+    import paper_2203_10477_amd as rs
+    import workloads
+    prob = workloads.config5(np.float32)
+    nodes, amp = workloads.pulse_sources(prob.M, prob.N, prob.n_steps, workloads.rng(6))
+    amp_d = torch.as_tensor(amp.astype(np.float32), device="cuda")
+    plan = rs.Plan(prob.M, prob.N, prob.P, dtype=torch.float32, tile=tile,
+                   sources=(nodes, amp_d))
+    fa_np, fb_np = prob.sources()
+    fa = torch.as_tensor(fa_np, device="cuda")
+    fb = torch.as_tensor(fb_np, device="cuda")
+    st = torch.zeros(2, prob.M, dtype=torch.float32, device="cuda")
+    ws = torch.empty(plan.workspace_bytes(0), dtype=torch.uint8, device="cuda")
+    n = prob.n_steps
+    ms = timed(lambda: (st.zero_(), rs.rswr_solve(plan, st, fa, fb, n, workspace=ws)), reps)
+    zero_ms = timed(lambda: st.zero_(), reps)
+    if not torch.isfinite(st).all():
+        raise RuntimeError("non-finite state after the pulse-source solve")
+    lo, hi = plan.info["tile_threads"], plan.info["tile_per_thread"]
+    return {"workload": f"{prob.M} nodes, {prob.N} windows, overlap {prob.P}, span "
+                        f"{plan.span}, {n} steps, FP32, {len(nodes)} pulse sources",
+            "glups": round(prob.M * n / ((ms - zero_ms) * 1e-3) / 1e9, 2),
+            "ms": round(ms - zero_ms, 3), "n_src": len(nodes), "tile": [lo, hi]}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -314,6 +345,8 @@ def main():
         line["batched"] = batched_section(max(1, args.steps))
         line["batched"]["vs_plain"] = round(line["batched"]["value"] / glups, 4)
         line["adjoint"] = adjoint_section(max(1, args.steps))
+        line["sources"] = sources_section(max(1, args.steps), tile)
+        line["sources"]["vs_plain"] = round(line["sources"]["glups"] / glups, 4)
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(prob, args.cpu_seconds)
     print(json.dumps(line), flush=True)

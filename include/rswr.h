@@ -215,9 +215,14 @@ rswr_status_t rswr_solve_workspace_size(rswr_plan_t plan, int32_t n_rec,
 rswr_status_t rswr_checkpoint_size(rswr_plan_t plan, int64_t n_steps,
                                    size_t* bytes);
 
-/* The redo loop of Sec. 2.6 (FIXED mode): n_steps levels from level n0,
- * predict -> select -> update per span, the last span shortened.  `state` is
- * read and overwritten with levels n0+n_steps-1 and n0+n_steps.
+/* The redo loop of Sec. 2.6: n_steps levels from level n0, predict ->
+ * select -> update per span, the last span shortened.  FIXED plans use the
+ * plan's span.  QUIET plans choose every span on the device (first
+ * predictive span S_cone, then ceil((1+beta) S_prev), capped by the plan's
+ * span cap and the levels left; the select rule of rswr_span_mode_t); the
+ * loop is recorded with enough rounds for spans of min(S_cone, cap) levels,
+ * and rounds after the last span exit at once.  Checkpoints need FIXED.
+ * `state` is read and overwritten with levels n0+n_steps-1 and n0+n_steps.
  * Receivers: `rec_idx` (host) holds n_rec node indices; `traces`
  * [n_rec][n_steps] receives U^{n0+s+1}[rec] at column s.  `checkpoints`
  * (optional, rswr_checkpoint_size bytes) receives the state at every span

@@ -51,6 +51,14 @@ __device__ __forceinline__ T in_vgpr(T v) {
   return v;
 }
 
+// A wave-uniform integer re-read in every loop iteration: tests on it stay
+// scalar compares and branches inside the loop instead of being hoisted out
+// as per-lane masks that occupy (and spill) scalar register pairs.
+__device__ __forceinline__ int uni(int x) {
+  asm volatile("" : "+s"(x));
+  return x;
+}
+
 template <int CTRL>
 __device__ __forceinline__ float lane_shift(float v) {
   return __builtin_bit_cast(float, dpp32<CTRL>(__builtin_bit_cast(uint32_t, v)));

@@ -42,6 +42,8 @@ struct FusedCtx {
   // receivers this tile records (all wave-uniform): trace row, the wave
   // and lane holding the node (wave -1: none), and its element (-1: node
   // 0's value, -2: node M-1's value)
+  // work bits of this wave (wave-uniform): kW* below
+  int work;
   int nrec;
   T* rdst[kRecSlots];
   int rwv[kRecSlots], rlane[kRecSlots], relem[kRecSlots];
@@ -105,6 +107,14 @@ __device__ __forceinline__ void frame_dirichlet(bool dir, const bool (&m)[2], T 
   }
 }
 
+// Work bits of a wave in a tile with receivers or sources.
+constexpr int kWSrc = 1 << 0;      // region source slot q: bit q (4 bits)
+constexpr int kWSrcMem = 1 << 4;   // region sources read from memory
+constexpr int kWFrame = 1 << 5;    // frame side sd has sources: bit 5 + sd
+constexpr int kWRec = 1 << 8;      // receiver slot q recorded by this wave: bit 8 + q
+constexpr int kWSrcAny = 0x1f;
+constexpr int kWRecAny = 0xf00;
+
 // Sources of the frame on side `sd` (0 left, 1 right) into its new level
 // (after the frame's step, as every window adds its sources after the
 // leapfrog): slots from registers, the rest from memory.  o0 is the frame's
@@ -113,10 +123,11 @@ template <typename T, int NT, int MPT>
 __device__ __forceinline__ void frame_sources(const UpdateArgs<T>& p,
                                              const FusedCtx<T, NT, MPT>& c, int sd,
                                              int64_t o0, int s, T (&lvl)[2]) {
+  const int nfs = uni(c.nfs[sd]);
 #pragma unroll
   for (int q = 0; q < kFrameSrc; ++q) {
-    if (q < c.nfs[sd]) {
-      const int x = c.fcode[sd][q];
+    if (q < nfs) {
+      const int x = uni(c.fcode[sd][q]);
       const T g = rd_lane(c.famp[sd][q], s);
       const bool mine = c.lane == (x >> 1);
       if (x & 1)
@@ -125,7 +136,7 @@ __device__ __forceinline__ void frame_sources(const UpdateArgs<T>& p,
         lvl[0] = mine ? lvl[0] + g : lvl[0];
     }
   }
-  for (int r = c.ffb[sd]; r < c.ffe[sd]; ++r) {
+  for (int r = uni(c.ffb[sd]); r < c.ffe[sd]; ++r) {
     const int64_t x = p.src_node[r] - o0 - 2 * c.lane;
     const T g = p.src_amp[static_cast<int64_t>(p.src_id[r]) * p.src_ld + p.n0 + s];
     lvl[0] = (x == 0) ? lvl[0] + g : lvl[0];
@@ -156,7 +167,7 @@ __device__ __forceinline__ void fused_step(const UpdateArgs<T>& p,
       const T d = rd_lane(c.vA, s + 1);
       frame_dirichlet(true, c.fmL, d, lo);
     }
-    if (SRC && (c.nfs[0] > 0 || c.ffe[0] > c.ffb[0]))
+    if (SRC && (uni(c.work) & (kWFrame << 0)))
       frame_sources(p, c, 0, c.a - kFrameHalf, s, lo);
     if (c.keep) fl = wr_lane(F, s, fl, c.lane);
     L = (c.lane == 0) ? fma_(c.nq, F, cur[1]) : L;
@@ -167,7 +178,7 @@ __device__ __forceinline__ void fused_step(const UpdateArgs<T>& p,
       const T d = rd_lane(c.vB, s + 1);
       frame_dirichlet(true, c.fmR, d, ro);
     }
-    if (SRC && (c.nfs[1] > 0 || c.ffe[1] > c.ffb[1]))
+    if (SRC && (uni(c.work) & (kWFrame << 1)))
       frame_sources(p, c, 1, c.a + NT * MPT - 1 - kFrameHalf, s, ro);
     if (c.keep) fr = wr_lane(F, s, fr, c.lane);
     R = (c.lane == 63) ? fma_(c.pq, F, cur[MPT - 2]) : R;
@@ -194,33 +205,38 @@ __device__ __forceinline__ void fused_step(const UpdateArgs<T>& p,
                              rd_lane(c.vA, s + 1));
   else
     step_chunk<T, MPT, false>(cur, old, L, R, p.c2, p.k, 0, 0, T(0), T(0));
-  if (SRC && (c.nsrc > 0 || c.sfe > c.sfb)) {
+  const int w = (REC || SRC) ? uni(c.work) : 0;
+  if (SRC && (w & kWSrcAny)) {
     // interior sources of level n+1, in source order
 #pragma unroll
     for (int q = 0; q < kSrcSlots; ++q) {
-      if (q < c.nsrc && (c.scode[q] >> 16) == c.wv)
-        add_at(old, c.scode[q] & 255, rd_lane(c.samp[q], s),
-               c.lane == ((c.scode[q] >> 8) & 255));
+      if (w & (kWSrc << q)) {
+        const int code = uni(c.scode[q]);
+        add_at(old, code & 255, rd_lane(c.samp[q], s), c.lane == ((code >> 8) & 255));
+      }
     }
-    for (int r = c.sfb; r < c.sfe; ++r) {
-      const int64_t d = p.src_node[r] - c.base;
-      const T g = p.src_amp[static_cast<int64_t>(p.src_id[r]) * p.src_ld + p.n0 + s];
+    if (w & kWSrcMem)
+      for (int r = uni(c.sfb); r < c.sfe; ++r) {
+        const int64_t d = p.src_node[r] - c.base;
+        const T g = p.src_amp[static_cast<int64_t>(p.src_id[r]) * p.src_ld + p.n0 + s];
 #pragma unroll
-      for (int e = 0; e < MPT; ++e) old[e] = (d == e) ? old[e] + g : old[e];
-    }
+        for (int e = 0; e < MPT; ++e) old[e] = (d == e) ? old[e] + g : old[e];
+      }
   }
-  if (REC && c.nrec > 0) {
+  if (REC && (w & kWRecAny)) {
     // receivers: the sample of level n+1 goes to lane s of tr[q] (all
     // branches wave-uniform)
-    const T da = rd_lane(c.vA, s + 1), db = rd_lane(c.vB, s + 1);
 #pragma unroll
     for (int q = 0; q < kRecSlots; ++q) {
-      if (q < c.nrec && c.rwv[q] == c.wv) {
+      if (w & (kWRec << q)) {
+        const int e = uni(c.relem[q]);
         T x;
-        if (c.relem[q] >= 0)
-          x = rd_lane(elem_at(old, c.relem[q]), c.rlane[q]);
+        if (e >= 0)
+          x = rd_lane(elem_at(old, e), uni(c.rlane[q]));
+        else if (e == -1)
+          x = rd_lane(c.vA, s + 1);
         else
-          x = (c.relem[q] == -1) ? da : db;
+          x = rd_lane(c.vB, s + 1);
         tr[q] = wr_lane(x, s, tr[q], c.lane);
       }
     }
@@ -390,6 +406,20 @@ __device__ __forceinline__ void fused_tile(const UpdateArgs<T>& p, const Tile& t
         c.famp[sd][q] = h ? sample(fb[sd] + q) : T(0);
       }
     }
+  }
+  {
+    int w = 0;
+#pragma unroll
+    for (int q = 0; q < kRecSlots; ++q)
+      if (REC && q < c.nrec && c.rwv[q] == c.wv) w |= kWRec << q;
+#pragma unroll
+    for (int q = 0; q < kSrcSlots; ++q)
+      if (SRC && q < c.nsrc && (c.scode[q] >> 16) == c.wv) w |= kWSrc << q;
+    if (SRC && c.sfe > c.sfb) w |= kWSrcMem;
+#pragma unroll
+    for (int sd = 0; sd < 2; ++sd)
+      if (SRC && (c.nfs[sd] > 0 || c.ffe[sd] > c.ffb[sd])) w |= kWFrame << sd;
+    c.work = __builtin_amdgcn_readfirstlane(w);
   }
 
   const bool hl = c.wv == 0 && tl.lmode == kEndGhost;

@@ -542,7 +542,7 @@ size_t elem_size(const rswr_plan_s& p) { return p.dtype == RSWR_F64 ? 8 : 4; }
 
 struct WsLayout {
   size_t state = 0, flux = 0, gen_idx = 0, fast_idx = 0, rec_ptr = 0, rec_node = 0,
-         rec_id = 0, total = 0;
+         rec_id = 0, ctl = 0, total = 0;
 };
 
 WsLayout ws_layout(const rswr_plan_s& p, int32_t n_rec) {
@@ -567,6 +567,8 @@ WsLayout ws_layout(const rswr_plan_s& p, int32_t n_rec) {
   off += round_up(size_t(std::max(n_rec, 1)) * sizeof(int64_t), 256);
   w.rec_id = off;
   off += round_up(size_t(std::max(n_rec, 1)) * sizeof(int32_t), 256);
+  w.ctl = off;  // control block of an adaptive solve
+  off += round_up(sizeof(rswr::QuietCtl), 256);
   w.total = off;
   return w;
 }
@@ -640,6 +642,65 @@ rswr_status_t enqueue_solve(rswr_plan_s* p, const DevTables& d, void* state,
     std::swap(x, y);
   }
   if (ck) RSWR_HIP(rswr::launch_copy<T>(user, ck + K * st_elems, 2 * M, s));
+  return RSWR_OK;
+}
+
+// The adaptive (QUIET) loop of Sec. 2.6 recorded as one graph: every span
+// is at least min(S_cone, cap) levels (or the levels left), which bounds
+// the rounds; each round predicts over the device's predictive span,
+// selects on the device, updates over the chosen span and advances the
+// control block, and rounds after the last span exit at once.  The result
+// ends in the caller's buffer or the workspace copy, as the device parity
+// says; a last conditional copy brings it to the caller's buffer.
+template <typename T>
+rswr_status_t enqueue_solve_quiet(rswr_plan_s* p, const DevTables& d, void* state,
+                                  const void* fa, const void* fb, int64_t n0,
+                                  int64_t n_steps, const Lists& lists, void* traces, char* ws,
+                                  const WsLayout& L, hipStream_t s) {
+  const int64_t M = p->M;
+  T* const user = static_cast<T*>(state);
+  T* const buf = reinterpret_cast<T*>(ws + L.state);
+  T* const flux = reinterpret_cast<T*>(ws + L.flux);
+  auto* const ctl = reinterpret_cast<rswr::QuietCtl*>(ws + L.ctl);
+  const int32_t cap = p->S_max;
+  const int32_t lo_span = std::max(1, std::min(p->S_cone, cap));
+  const int64_t rounds = (n_steps + lo_span - 1) / lo_span;
+  const int32_t shat0 =
+      static_cast<int32_t>(std::min<int64_t>({int64_t(p->S_cone), int64_t(cap), n_steps}));
+  RSWR_HIP(rswr::launch_quiet_init(ctl, n0, n0 + n_steps, shat0, cap, p->beta, s));
+  for (int64_t k = 0; k < rounds; ++k) {
+    T* in = (k & 1) ? buf : user;
+    T* out = (k & 1) ? user : buf;
+    rswr::PredictArgs<T> pa = predict_args<T>(*p, d, in, fa, fb, n0, cap, flux);
+    pa.n0_dev = &ctl->n0;
+    pa.shat_dev = &ctl->shat;
+    RSWR_HIP(rswr::launch_predict<T>(pa, 2 * cap + 1, s));
+    rswr::SelectArgs<T> sa{};
+    sa.flux = flux;
+    sa.span_dev = &ctl->span;
+    sa.shat_dev = &ctl->shat;
+    sa.n_rows = 2 * (p->N - 1);
+    sa.shat = cap;
+    sa.ld = p->flux_ld;
+    sa.cone = p->S_cone;
+    sa.mode = 1;
+    sa.fixed_span = p->S;
+    RSWR_HIP(rswr::launch_select<T>(sa, s));
+    rswr::UpdateArgs<T> ua = update_args<T>(*p, d, in, fa, fb, n0, flux, &ctl->span, 0, out);
+    ua.n0_dev = &ctl->n0;
+    if (lists.rec_ptr) {
+      ua.rec_ptr = lists.rec_ptr;
+      ua.rec_node = lists.rec_node;
+      ua.rec_id = lists.rec_id;
+      ua.traces = static_cast<T*>(traces);
+      ua.trace_ld = n_steps;
+      ua.trace_col0 = 0;  // plus the span's offset from n0, read on the device
+    }
+    RSWR_HIP(launch_update_pair<T>(*p, ua, lists.gen, lists.n_gen, lists.fast, lists.n_fast,
+                                   s));
+    RSWR_HIP(rswr::launch_quiet_next(ctl, s));
+  }
+  RSWR_HIP(rswr::launch_copy_if<T>(user, buf, 2 * M, &ctl->parity, s));
   return RSWR_OK;
 }
 
@@ -1080,12 +1141,14 @@ rswr_status_t rswr_select(rswr_plan_t p, const void* flux, int32_t span_hat,
   hipStream_t s = static_cast<hipStream_t>(stream);
   hipError_t e;
   if (p->dtype == RSWR_F64) {
-    rswr::SelectArgs<double> a{static_cast<const double*>(flux), span_dev, 2 * (p->N - 1),
-                               span_hat, p->flux_ld, p->S_cone, p->mode, p->S};
+    rswr::SelectArgs<double> a{static_cast<const double*>(flux), span_dev, nullptr,
+                               2 * (p->N - 1), span_hat, p->flux_ld, p->S_cone, p->mode,
+                               p->S};
     e = rswr::launch_select<double>(a, s);
   } else {
-    rswr::SelectArgs<float> a{static_cast<const float*>(flux), span_dev, 2 * (p->N - 1),
-                              span_hat, p->flux_ld, p->S_cone, p->mode, p->S};
+    rswr::SelectArgs<float> a{static_cast<const float*>(flux), span_dev, nullptr,
+                              2 * (p->N - 1), span_hat, p->flux_ld, p->S_cone, p->mode,
+                              p->S};
     e = rswr::launch_select<float>(a, s);
   }
   if (e != hipSuccess) return hip_fail(e, "select launch");
@@ -1188,8 +1251,8 @@ rswr_status_t rswr_solve(rswr_plan_t p, void* state, const void* f_a, const void
                          int32_t n_rec, void* traces, void* workspace, size_t ws_bytes,
                          void* checkpoints, void* stream) {
   if (!p || !state || !f_a || !f_b) return fail(RSWR_ERR_INVALID_ARG, "null pointer");
-  if (p->mode != RSWR_SPAN_FIXED)
-    return fail(RSWR_ERR_UNSUPPORTED, "rswr_solve runs FIXED plans");
+  if (p->mode != RSWR_SPAN_FIXED && checkpoints)
+    return fail(RSWR_ERR_UNSUPPORTED, "checkpoints need a FIXED plan");
   if (n0 < 0 || n_steps < 0 || n_rec < 0)
     return fail(RSWR_ERR_INVALID_ARG, "negative n0, n_steps or n_rec");
   if (n_rec > 0 && (!rec_idx || !traces))
@@ -1278,6 +1341,12 @@ rswr_status_t rswr_solve(rswr_plan_t p, void* state, const void* f_a, const void
   }
 
   auto enqueue = [&](hipStream_t q) {
+    if (p->mode == RSWR_SPAN_QUIET)
+      return p->dtype == RSWR_F64
+                 ? enqueue_solve_quiet<double>(p, *d, state, f_a, f_b, n0, n_steps, lists,
+                                               traces, ws, L, q)
+                 : enqueue_solve_quiet<float>(p, *d, state, f_a, f_b, n0, n_steps, lists,
+                                              traces, ws, L, q);
     return p->dtype == RSWR_F64
                ? enqueue_solve<double>(p, *d, state, f_a, f_b, n0, n_steps, lists,
                                        traces, ws, L, checkpoints, q)

@@ -18,8 +18,8 @@ constexpr int kRecSlots = 4;
 // Interior sources a fused tile injects from registers: kSrcSlots in its
 // region, kFrameSrc in each prediction frame; further ones are read from
 // memory every step.
-constexpr int kSrcSlots = 4;
-constexpr int kFrameSrc = 2;
+constexpr int kSrcSlots = 2;
+constexpr int kFrameSrc = 1;
 
 // Sentinel for "no left-input ghost in this tile".
 constexpr int64_t kNoNode = INT64_MIN;
@@ -60,6 +60,10 @@ struct PredictArgs {
   T* flux;              // [N-1][2][ld]
   const int64_t* lo;    // [N]
   const int64_t* hi;    // [N]
+  // nullable: read n0 / shat from the device (an adaptive solve recorded as
+  // one graph); shat 0 there means the solve is done
+  const int64_t* n0_dev;
+  const int32_t* shat_dev;
   int64_t M, n0;
   int32_t N, shat, ld, pad;
   T c2, k, r, q;
@@ -94,6 +98,9 @@ struct UpdateArgs {
   const int32_t* src_id;
   const T* src_amp;
   int64_t src_ld;
+  // nullable: the span starts at level *n0_dev instead of n0 (trace columns
+  // shift by the same amount)
+  const int64_t* n0_dev;
   int64_t M, n0, trace_ld, trace_col0;
   int32_t n_tiles, span, ld, pad;
   T c2, k, q, r;
@@ -103,7 +110,21 @@ template <typename T>
 struct SelectArgs {
   const T* flux;
   int32_t* span_dev;
+  const int32_t* shat_dev;  // nullable: shat from the device (0: done)
   int32_t n_rows, shat, ld, cone, mode, fixed_span;
+};
+
+// Device-side state of an adaptive (QUIET) solve recorded as one graph of a
+// bounded number of predict -> select -> update rounds; rounds after the
+// last span do nothing.
+struct QuietCtl {
+  int64_t n0;      // first level of the next span
+  int64_t n_end;   // level the solve ends at
+  int32_t shat;    // predictive span of the next span (0: done)
+  int32_t span;    // span the select chose (0: done)
+  int32_t parity;  // 1: the newest state is in the second buffer
+  int32_t s_max;   // cap of the predictive span
+  double beta;     // growth of Sec. 2.6
 };
 
 // Adjoint of the receiver misfit (see rswr_adjoint.hip).  The adjoint field
@@ -208,6 +229,14 @@ template <typename T>
 hipError_t launch_copy_many(const CopyJob<T>* jobs, int32_t n_jobs, hipStream_t s);
 template <typename T>
 hipError_t launch_select(const SelectArgs<T>& a, hipStream_t s);
+// Adaptive solve on the device: set up the control block, advance it after
+// each round, and copy the second buffer back when it holds the result.
+hipError_t launch_quiet_init(QuietCtl* c, int64_t n0, int64_t n_end, int32_t shat0,
+                             int32_t s_max, double beta, hipStream_t s);
+hipError_t launch_quiet_next(QuietCtl* c, hipStream_t s);
+template <typename T>
+hipError_t launch_copy_if(T* dst, const T* src, int64_t n, const int32_t* flag,
+                          hipStream_t s);
 template <typename T>
 hipError_t launch_copy(T* dst, const T* src, int64_t n, hipStream_t s);
 template <typename T>

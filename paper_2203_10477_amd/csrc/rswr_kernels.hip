@@ -20,7 +20,11 @@ namespace rswr {
 // whole-window prediction bit for bit.
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ __launch_bounds__(64) void k_predict(const PredictArgs<T> p) {
+__global__ __launch_bounds__(64) void k_predict(const PredictArgs<T> p0) {
+  PredictArgs<T> p = p0;
+  if (p0.n0_dev) p.n0 = *p0.n0_dev;
+  if (p0.shat_dev) p.shat = *p0.shat_dev;
+  if (p.shat <= 0) return;
   extern __shared__ unsigned char smem_raw[];
   T* const sm = reinterpret_cast<T*>(smem_raw);
   __shared__ T sda[kMaxSpan], sdb[kMaxSpan];
@@ -153,7 +157,13 @@ __device__ __forceinline__ void one_step(const UpdateArgs<T>& p,
 }
 
 template <typename T, int NT, int MPT, bool GEN>
-__global__ __launch_bounds__(NT) void k_update(const UpdateArgs<T> p) {
+__global__ __launch_bounds__(NT) void k_update(const UpdateArgs<T> p0) {
+  UpdateArgs<T> p = p0;
+  if (p0.n0_dev) {
+    const int64_t dn = *p0.n0_dev - p0.n0;
+    p.n0 += dn;
+    p.trace_col0 += dn;
+  }
   constexpr int NW = NT / 64;
   constexpr int TM = NT * MPT;
   constexpr int TMP = TM + (TM >> 5) + 1;
@@ -257,7 +267,13 @@ __global__ __launch_bounds__(NT) void k_update(const UpdateArgs<T> p) {
 // exact zeros of a predicted flux waveform (shat samples).
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ __launch_bounds__(256) void k_select(const SelectArgs<T> a) {
+__global__ __launch_bounds__(256) void k_select(const SelectArgs<T> a0) {
+  SelectArgs<T> a = a0;
+  if (a0.shat_dev) a.shat = *a0.shat_dev;
+  if (a.shat <= 0) {
+    if (threadIdx.x == 0) *a.span_dev = 0;
+    return;
+  }
   __shared__ int smin;
   if (threadIdx.x == 0) smin = 0x7fffffff;
   __syncthreads();
@@ -286,6 +302,50 @@ __global__ __launch_bounds__(256) void k_select(const SelectArgs<T> a) {
     }
     *a.span_dev = S;
   }
+}
+
+// Control block of the adaptive solve (Sec. 2.6): the first predictive span
+// is given; after each round the level advances by the chosen span and the
+// next predictive span is ceil((1 + beta) S), capped by s_max and the
+// levels left (0 once the solve is done).
+__global__ __launch_bounds__(64) void k_quiet_init(QuietCtl* c, int64_t n0, int64_t n_end,
+                                                   int32_t shat0, int32_t s_max,
+                                                   double beta) {
+  if (threadIdx.x == 0) {
+    c->n0 = n0;
+    c->n_end = n_end;
+    c->shat = n_end > n0 ? shat0 : 0;
+    c->span = 0;
+    c->parity = 0;
+    c->s_max = s_max;
+    c->beta = beta;
+  }
+}
+
+__global__ __launch_bounds__(64) void k_quiet_next(QuietCtl* c) {
+  if (threadIdx.x == 0) {
+    const int32_t S = c->span;
+    if (S > 0) {
+      c->n0 += S;
+      c->parity ^= 1;
+    }
+    const int64_t rem = c->n_end - c->n0;
+    int64_t sh = static_cast<int64_t>(ceil((1.0 + c->beta) * static_cast<double>(S)));
+    if (sh > c->s_max) sh = c->s_max;
+    if (sh > rem) sh = rem;
+    if (sh < 1) sh = 1;
+    c->shat = (S > 0 && rem > 0) ? static_cast<int32_t>(sh) : 0;
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_copy_if(T* __restrict__ dst, const T* __restrict__ src,
+                                                 int64_t n, const int32_t* flag) {
+  if (*flag == 0) return;
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+       i += stride)
+    dst[i] = src[i];
 }
 
 template <typename T>
@@ -347,6 +407,28 @@ hipError_t launch_select(const SelectArgs<T>& a, hipStream_t s) {
   return hipGetLastError();
 }
 
+hipError_t launch_quiet_init(QuietCtl* c, int64_t n0, int64_t n_end, int32_t shat0,
+                             int32_t s_max, double beta, hipStream_t s) {
+  hipLaunchKernelGGL(k_quiet_init, dim3(1), dim3(64), 0, s, c, n0, n_end, shat0, s_max, beta);
+  return hipGetLastError();
+}
+
+hipError_t launch_quiet_next(QuietCtl* c, hipStream_t s) {
+  hipLaunchKernelGGL(k_quiet_next, dim3(1), dim3(64), 0, s, c);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_copy_if(T* dst, const T* src, int64_t n, const int32_t* flag,
+                          hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  int64_t blocks = (n + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(k_copy_if<T>, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s,
+                     dst, src, n, flag);
+  return hipGetLastError();
+}
+
 template <typename T>
 hipError_t launch_copy(T* dst, const T* src, int64_t n, hipStream_t s) {
   if (n <= 0) return hipSuccess;
@@ -367,5 +449,9 @@ template hipError_t launch_select<float>(const SelectArgs<float>&, hipStream_t);
 template hipError_t launch_select<double>(const SelectArgs<double>&, hipStream_t);
 template hipError_t launch_copy<float>(float*, const float*, int64_t, hipStream_t);
 template hipError_t launch_copy<double>(double*, const double*, int64_t, hipStream_t);
+template hipError_t launch_copy_if<float>(float*, const float*, int64_t, const int32_t*,
+                                          hipStream_t);
+template hipError_t launch_copy_if<double>(double*, const double*, int64_t, const int32_t*,
+                                           hipStream_t);
 
 }  // namespace rswr
