@@ -223,9 +223,12 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-forms", action="store_true",
-                    help="skip the batched and adjoint sections")
+                    help="skip the batched, adjoint and pulse-source sections")
     ap.add_argument("--tile", default="", help="threads x nodes-per-lane, e.g. 320x13 "
                     "(default: autotuned)")
+    ap.add_argument("--section", choices=("batched", "adjoint", "sources"), default=None,
+                    help="run one of the other forms alone and print its figures "
+                         "(for profiling)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
@@ -239,6 +242,19 @@ def main():
     import workloads
 
     from paper_2203_10477_amd.autotune import autotune
+
+    if args.section:
+        torch.cuda.set_device(0)
+        reps = max(1, args.steps)
+        if args.section == "batched":
+            out = batched_section(reps)
+        elif args.section == "adjoint":
+            out = adjoint_section(reps)
+        else:
+            tile = tuple(int(v) for v in args.tile.split("x")) if args.tile else None
+            out = sources_section(reps, tile)
+        print(json.dumps({"section": args.section, **out}), flush=True)
+        return
 
     dev = "cuda:0"
     torch.cuda.set_device(0)
