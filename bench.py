@@ -147,23 +147,47 @@ def adjoint_section(reps):
     """The adjoint form: 2^18 nodes, 128 windows, overlap 64, FP64, 8192 steps,
     16 receivers; the forward solve keeping span checkpoints, then the
     backward sweep giving dJ/df_A and dJ/da; against the plain FP64 solve of
-    the same problem."""
+    the same problem.  The tile shape is tuned on the form itself (forward
+    with checkpoints + backward sweep, each shape timed once after a warm-up)."""
     import numpy as np
     import torch
     import paper_2203_10477_amd as rs
     import workloads
+    from paper_2203_10477_amd.autotune import kernel_shapes
     prob = workloads.config4()
-    plan = rs.Plan(prob.M, prob.N, prob.P, dtype=torch.float64)
     fa_np, fb_np = prob.sources()
     fa = torch.as_tensor(fa_np, device="cuda")
     fb = torch.as_tensor(fb_np, device="cuda")
     st = torch.zeros(2, prob.M, dtype=torch.float64, device="cuda")
     n = prob.n_steps
     rec = prob.rec
-    ws = torch.empty(plan.workspace_bytes(len(rec)), dtype=torch.uint8, device="cuda")
-    ck = plan.checkpoint_buffer(n)
     g = np.random.default_rng(7)
     gtr = torch.as_tensor(g.standard_normal((len(rec), n)), device="cuda")
+
+    def setup(tile):
+        plan = rs.Plan(prob.M, prob.N, prob.P, dtype=torch.float64, tile=tile)
+        ws = torch.empty(plan.workspace_bytes(len(rec)), dtype=torch.uint8, device="cuda")
+        return plan, ws
+
+    ck = None
+    tune = {}
+    for th, pt, fp64_ok in kernel_shapes():
+        if not fp64_ok or th * pt > 1024:
+            continue
+        try:
+            plan, ws = setup((th, pt))
+        except rs.RSWRError:
+            continue
+        ck = plan.checkpoint_buffer(n)
+
+        def both():
+            st.zero_()
+            rs.rswr_solve(plan, st, fa, fb, n, receivers=rec, checkpoints=ck, workspace=ws)
+            rs.rswr_solve_adjoint(plan, ck, fa, fb, n, rec, gtr)
+        tune[(th, pt)] = timed(both, 1)
+    tile = min(tune, key=tune.get)
+    plan, ws = setup(tile)
+    ck = plan.checkpoint_buffer(n)
 
     plain_ms = timed(lambda: (st.zero_(), rs.rswr_solve(plan, st, fa, fb, n, workspace=ws)),
                      reps)
@@ -180,6 +204,8 @@ def adjoint_section(reps):
             "forward_plus_adjoint_glups": round(upd / ((fwd_ms - zero_ms + adj_ms) * 1e-3), 2),
             "ms": {"plain": round(plain_ms - zero_ms, 3), "forward": round(fwd_ms - zero_ms, 3),
                    "adjoint": round(adj_ms, 3)},
+            "tile": list(tile),
+            "tune_ms": {f"{a}x{b}": round(v, 2) for (a, b), v in tune.items()},
             "checkpoint_bytes": ck.numel() * 8}
 
 

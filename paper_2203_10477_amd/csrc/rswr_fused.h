@@ -276,6 +276,9 @@ __device__ __forceinline__ void fused_run(const UpdateArgs<T>& p, const Tile& tl
 
 // One tile over S levels: load, step (with the frames its waves carry),
 // store.  `st` is the LDS staging buffer, `edge` the cross-wave slots.
+// GEN: node 0 may lie inside the region (per-element Dirichlet treatment).
+// REC: the tile may record receivers.  SRC: the tile and its frames may
+// inject interior sources.
 template <typename T, int NT, int MPT, bool GEN, bool REC, bool SRC>
 __device__ __forceinline__ void fused_tile(const UpdateArgs<T>& p, const Tile& tl, int slot,
                                            int S, T* st, T (*edge)[2][NT / 64]) {

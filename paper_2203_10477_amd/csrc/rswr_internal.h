@@ -205,7 +205,8 @@ hipError_t launch_predict(const PredictArgs<T>& a, int shmem_nodes,
 template <typename T>
 hipError_t launch_update(const UpdateArgs<T>& a, int threads, int per_thread,
                          bool general, hipStream_t s);
-// Fused span (rswr_fused.hip): predict folded into the update; needs
+// Fused span (rswr_fused.hip dispatching to rswr_fused_kernel.h, one
+// translation unit per launch kind): predict folded into the update; needs
 // 1 <= span <= kMaxFusedSpan and inputs only at region ends.
 // kFusedExt: a launch in which some tiles record receivers (CSR rec_ptr
 // over its slots) or inject interior sources (src_ptr); kFusedGeneral:
