@@ -259,6 +259,33 @@ rswr_status_t rswr_solve_adjoint(rswr_plan_t plan, const void* checkpoints,
                                  double* grad_lambda, void* workspace,
                                  size_t ws_bytes, void* stream);
 
+/* A batch of adjoint solves of one plan: n_prob problems of the same shape,
+ * receivers and span (a fused FIXED plan without sources), each the solve of
+ * rswr_solve from rest (zero levels -1 and 0) driven by its own boundary
+ * samples, with its own dJ/dtrace.  Per problem the result equals
+ * rswr_solve (with checkpoints) followed by rswr_solve_adjoint, bit for bit.
+ * Checkpoints are chunked, so a batch of large problems fits in memory: the
+ * forward pass keeps the state at every seg-th span boundary, and the
+ * backward sweep recomputes each segment's span states and fluxes (last
+ * segment first) before running its adjoint spans; that is one extra forward
+ * pass.  `group` problems share every launch (problem index in grid
+ * dimension y) and the workspace (rswr_adjoint_batch_workspace_size) holds
+ * one group; groups run one after another.  seg = 0 picks ceil(sqrt(spans)).
+ * Device arrays: f_a, f_b [n_prob][src_ld] (src_ld >= n_steps+1),
+ * grad_traces [n_prob][n_rec][n_steps], grad_f_a, grad_f_b
+ * [n_prob][n_steps+1], grad_lambda [n_prob] (double).  rec_idx is host.
+ * Errors: INVALID_ARG, NOMEM (workspace), UNSUPPORTED (plan), HIP. */
+rswr_status_t rswr_adjoint_batch_workspace_size(rswr_plan_t plan, int64_t n_steps,
+                                                int32_t n_rec, int32_t group, int32_t seg,
+                                                size_t* bytes);
+rswr_status_t rswr_solve_adjoint_batch(rswr_plan_t plan, int32_t n_prob, const void* f_a,
+                                       const void* f_b, int64_t src_ld, int64_t n_steps,
+                                       const int64_t* rec_idx, int32_t n_rec,
+                                       const void* grad_traces, void* grad_f_a,
+                                       void* grad_f_b, double* grad_lambda, int32_t group,
+                                       int32_t seg, void* workspace, size_t ws_bytes,
+                                       void* stream);
+
 /* ---- Batched solve -------------------------------------------------------
  * Many independent problems (each with its own grid, windows, wave speed,
  * span, sources and length) advanced by the redo loop of Sec. 2.6 in one

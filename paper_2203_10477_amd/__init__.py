@@ -80,6 +80,9 @@ def lib():
     L.rswr_solve_adjoint.argtypes = [vp, vp, vp, vp, i64, vp, i32, vp, vp, vp, vp, vp, sz,
                                      vp]
     L.rswr_solve.argtypes = [vp, vp, vp, vp, i64, i64, vp, i32, vp, vp, sz, vp, vp]
+    L.rswr_adjoint_batch_workspace_size.argtypes = [vp, i64, i32, i32, i32, ctypes.POINTER(sz)]
+    L.rswr_solve_adjoint_batch.argtypes = [vp, i32, vp, vp, i64, i64, vp, i32, vp, vp, vp,
+                                           vp, i32, i32, vp, sz, vp]
     L.rswr_span.argtypes = [vp, vp, vp, vp, i64, i32, vp, vp, vp]
     L.rswr_batch_plan.argtypes = [vp, i32, ctypes.POINTER(vp)]
     L.rswr_batch_destroy.argtypes = [vp]
@@ -89,7 +92,9 @@ def lib():
                  "rswr_plan_tiles",
                  "rswr_predict", "rswr_select", "rswr_update", "rswr_span",
                  "rswr_solve_workspace_size", "rswr_solve", "rswr_checkpoint_size",
-                 "rswr_adjoint_workspace_size", "rswr_solve_adjoint", "rswr_batch_plan",
+                 "rswr_adjoint_workspace_size", "rswr_solve_adjoint",
+                 "rswr_adjoint_batch_workspace_size", "rswr_solve_adjoint_batch",
+                 "rswr_batch_plan",
                  "rswr_batch_destroy", "rswr_batch_workspace_size", "rswr_batch_solve"):
         getattr(L, name).restype = ctypes.c_int
     L.rswr_status_string.argtypes = [ctypes.c_int]
@@ -364,6 +369,42 @@ def rswr_solve_adjoint(plan, checkpoints, f_a, f_b, n_steps, receivers, grad_tra
     return ga, gb, gl
 
 
+def rswr_solve_adjoint_batch(plan, f_a, f_b, n_steps, receivers, grad_traces, group=None,
+                             seg=0, workspace=None):
+    """Reverse mode of a batch of same-shape solves from rest (include/rswr.h):
+    f_a, f_b [n_prob, ld >= n_steps+1], grad_traces [n_prob, n_rec, n_steps].
+    `group` problems share each launch (default: all); seg = spans per
+    checkpoint segment (0: about the square root of the span count).
+    Returns (dJ/df_a [n_prob, n_steps+1], dJ/df_b, dJ/dlam [n_prob] float64)."""
+    rec = np.ascontiguousarray(np.asarray(receivers, np.int64).reshape(-1))
+    n_rec = len(rec)
+    n_prob, src_ld = int(f_a.shape[0]), int(f_a.shape[1])
+    if tuple(f_b.shape) != (n_prob, src_ld):
+        raise ValueError("f_b must have the shape of f_a")
+    group = n_prob if group is None else int(group)
+    dev_ = f_a.device
+    if workspace is None:
+        b = ctypes.c_size_t()
+        _check(lib().rswr_adjoint_batch_workspace_size(plan.handle, int(n_steps), n_rec, group,
+                                                       int(seg), ctypes.byref(b)),
+               "rswr_adjoint_batch_workspace_size")
+        workspace = torch.empty(b.value, dtype=torch.uint8, device=dev_)
+    ga = torch.empty(n_prob, n_steps + 1, dtype=plan.dtype, device=dev_)
+    gb = torch.empty_like(ga)
+    gl = torch.empty(n_prob, dtype=torch.float64, device=dev_)
+    gtr = grad_traces.contiguous()
+    _check(lib().rswr_solve_adjoint_batch(
+        plan.handle, n_prob, _dev(f_a, plan.dtype, n_prob * src_ld, "f_a"),
+        _dev(f_b, plan.dtype, n_prob * src_ld, "f_b"), src_ld, int(n_steps),
+        rec.ctypes.data if n_rec else None, n_rec,
+        _dev(gtr, plan.dtype, n_prob * n_rec * n_steps, "grad_traces") if n_rec else None,
+        _dev(ga, plan.dtype, ga.numel(), "grad_f_a"), _dev(gb, plan.dtype, gb.numel(), "grad_f_b"),
+        ctypes.c_void_p(gl.data_ptr()), group, int(seg),
+        _dev(workspace, torch.uint8, 1, "workspace"), workspace.numel(), _stream()),
+        "rswr_solve_adjoint_batch")
+    return ga, gb, gl
+
+
 class ProblemSpec:
     """Everything but f_A and a that fixes an RSWR forward run for autograd."""
 
@@ -465,3 +506,4 @@ predict, select, update, solve = rswr_predict, rswr_select, rswr_update, rswr_so
 span = rswr_span
 batch_solve = rswr_batch_solve
 solve_adjoint = rswr_solve_adjoint
+solve_adjoint_batch = rswr_solve_adjoint_batch

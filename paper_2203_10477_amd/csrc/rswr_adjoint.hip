@@ -31,8 +31,44 @@ namespace rswr {
 // ---------------------------------------------------------------------------
 constexpr int kAdjFrameSrc = 8;
 
+// Problem blockIdx.y of a same-shape batch (YStrides); the arguments as they
+// are for a single problem.
 template <typename T>
-__global__ __launch_bounds__(64) void k_adj_predict_frame(const AdjPredictArgs<T> p) {
+__device__ __forceinline__ AdjPredictArgs<T> batch_problem(const AdjPredictArgs<T>& a) {
+  AdjPredictArgs<T> p = a;
+  if (a.ys.ny > 1) {
+    p.w = at_y(a.w, a.ys.ws);
+    p.flux = at_y(a.flux, a.ys.ws);
+    p.gtr = at_y(a.gtr, a.ys.gtr);
+  }
+  return p;
+}
+
+template <typename T>
+__device__ __forceinline__ AdjUpdateArgs<T> batch_problem(const AdjUpdateArgs<T>& a) {
+  AdjUpdateArgs<T> p = a;
+  if (a.ys.ny > 1) {
+    p.w_in = at_y(a.w_in, a.ys.ws);
+    p.w_out = at_y(a.w_out, a.ys.ws);
+    p.u_end = at_y(a.u_end, a.ys.ws);
+    p.u_beg = at_y(a.u_beg, a.ys.ws);
+    p.ffl = at_y(a.ffl, a.ys.ws);
+    p.afl = at_y(a.afl, a.ys.ws);
+    p.lam_part = at_y(a.lam_part, a.ys.ws);
+    p.fa = at_y(a.fa, a.ys.src);
+    p.fb = at_y(a.fb, a.ys.src);
+    p.gtr = at_y(a.gtr, a.ys.gtr);
+    p.grad_fa = at_y(a.grad_fa, a.ys.grad);
+    p.grad_fb = at_y(a.grad_fb, a.ys.grad);
+  }
+  return p;
+}
+
+inline unsigned ny(const YStrides& y) { return y.ny > 1 ? static_cast<unsigned>(y.ny) : 1u; }
+
+template <typename T>
+__global__ __launch_bounds__(64) void k_adj_predict_frame(const AdjPredictArgs<T> p0) {
+  const AdjPredictArgs<T> p = batch_problem(p0);
   const int i = blockIdx.x >> 1, side = blockIdx.x & 1;
   const int w = i + side;
   const int64_t o = (side == 0) ? p.lo[i + 1] : p.hi[i];
@@ -146,7 +182,8 @@ __global__ __launch_bounds__(64) void k_adj_predict_frame(const AdjPredictArgs<T
 // The same prediction for spans beyond the frame: the light-cone trapezoid
 // around o in LDS (window ends inside it keep their exact treatment).
 template <typename T>
-__global__ __launch_bounds__(64) void k_adj_predict_lds(const AdjPredictArgs<T> p) {
+__global__ __launch_bounds__(64) void k_adj_predict_lds(const AdjPredictArgs<T> p0) {
+  const AdjPredictArgs<T> p = batch_problem(p0);
   extern __shared__ unsigned char smem_raw[];
   T* const sm = reinterpret_cast<T*>(smem_raw);
   const int i = blockIdx.x >> 1, side = blockIdx.x & 1;
@@ -405,7 +442,8 @@ __device__ __forceinline__ int adj_run(const AdjUpdateArgs<T>& p, const AdjCtx<T
 // nodes 1 / M-2 take the SRC step, the rest the plain one (a uniform branch
 // per work-group).
 template <typename T, int NT, int MPT, bool GEN, bool MIX>
-__global__ __launch_bounds__(NT) void k_adj_update(const AdjUpdateArgs<T> p) {
+__global__ __launch_bounds__(NT) void k_adj_update(const AdjUpdateArgs<T> p0) {
+  const AdjUpdateArgs<T> p = batch_problem(p0);
   constexpr int NW = NT / 64;
   constexpr int TM = NT * MPT;
   constexpr int TMP = TM + (TM >> 5) + 1;
@@ -604,10 +642,12 @@ template <typename T>
 hipError_t launch_adj_predict(const AdjPredictArgs<T>& a, int shmem_nodes, hipStream_t s) {
   if (a.N < 2) return hipSuccess;
   if (a.shat <= kMaxFusedSpan) {
-    hipLaunchKernelGGL(k_adj_predict_frame<T>, dim3(2 * (a.N - 1)), dim3(64), 0, s, a);
+    hipLaunchKernelGGL(k_adj_predict_frame<T>, dim3(2 * (a.N - 1), ny(a.ys)), dim3(64), 0, s,
+                       a);
   } else {
     const size_t shm = static_cast<size_t>(2 * shmem_nodes) * sizeof(T);
-    hipLaunchKernelGGL(k_adj_predict_lds<T>, dim3(2 * (a.N - 1)), dim3(64), shm, s, a);
+    hipLaunchKernelGGL(k_adj_predict_lds<T>, dim3(2 * (a.N - 1), ny(a.ys)), dim3(64), shm, s,
+                       a);
   }
   return hipGetLastError();
 }
@@ -619,11 +659,11 @@ hipError_t launch_adj_update(const AdjUpdateArgs<T>& a, int threads, int per_thr
 #define RSWR_ADJ_LAUNCH(NT_, MPT_)                                                  \
   if (threads == NT_ && per_thread == MPT_) {                                     \
     if (general)                                                                  \
-      hipLaunchKernelGGL((k_adj_update<T, NT_, MPT_, true, false>), dim3(a.n_tiles), \
-                         dim3(NT_), 0, s, a);                                     \
+      hipLaunchKernelGGL((k_adj_update<T, NT_, MPT_, true, false>),              \
+                         dim3(a.n_tiles, ny(a.ys)), dim3(NT_), 0, s, a);          \
     else                                                                          \
-      hipLaunchKernelGGL((k_adj_update<T, NT_, MPT_, false, true>), dim3(a.n_tiles), \
-                         dim3(NT_), 0, s, a);                                     \
+      hipLaunchKernelGGL((k_adj_update<T, NT_, MPT_, false, true>),              \
+                         dim3(a.n_tiles, ny(a.ys)), dim3(NT_), 0, s, a);          \
     return hipGetLastError();                                                     \
   }
   RSWR_SHAPES(RSWR_ADJ_LAUNCH)

@@ -51,6 +51,14 @@ __device__ __forceinline__ T in_vgpr(T v) {
   return v;
 }
 
+// Problem y's copy of a batched buffer: `stride` bytes per problem.
+template <typename P>
+__device__ __forceinline__ P* at_y(P* ptr, int64_t stride) {
+  return ptr ? reinterpret_cast<P*>(reinterpret_cast<uintptr_t>(ptr) +
+                                    static_cast<uintptr_t>(blockIdx.y * stride))
+             : ptr;
+}
+
 // A wave-uniform integer re-read in every loop iteration: tests on it stay
 // scalar compares and branches inside the loop instead of being hoisted out
 // as per-lane masks that occupy (and spill) scalar register pairs.

@@ -15,7 +15,15 @@ namespace rswr {
 // code path its tile needs (a uniform branch), the others run the plain
 // step.  kFusedPlain: the plain step only.
 template <typename T, int NT, int MPT, int KIND>
-__global__ __launch_bounds__(NT) void k_fused(const UpdateArgs<T> p) {
+__global__ __launch_bounds__(NT) void k_fused(const UpdateArgs<T> p0) {
+  UpdateArgs<T> p = p0;
+  if (p0.ys.ny > 1) {  // problem blockIdx.y of a same-shape batch
+    p.state_in = at_y(p0.state_in, p0.ys.ws);
+    p.state_out = at_y(p0.state_out, p0.ys.ws);
+    p.flux_out = at_y(p0.flux_out, p0.ys.ws);
+    p.fa = at_y(p0.fa, p0.ys.src);
+    p.fb = at_y(p0.fb, p0.ys.src);
+  }
   constexpr int NW = NT / 64;
   constexpr int TM = NT * MPT;
   constexpr int TMP = TM + (TM >> 5) + 1;
@@ -48,8 +56,8 @@ hipError_t launch_fused_kind(const UpdateArgs<T>& a, int threads, int per_thread
   if (threads == NT_ && per_thread == MPT_) {                                     \
     if constexpr (sizeof(T) == 8 && MPT_ > 22) return hipErrorInvalidValue;      \
     else {                                                                        \
-      hipLaunchKernelGGL((k_fused<T, NT_, MPT_, KIND>), dim3(a.n_tiles), dim3(NT_), 0, \
-                         s, a);                                                   \
+      hipLaunchKernelGGL((k_fused<T, NT_, MPT_, KIND>),                          \
+                         dim3(a.n_tiles, a.ys.ny > 1 ? a.ys.ny : 1), dim3(NT_), 0, s, a); \
       return hipGetLastError();                                                   \
     }                                                                             \
   }

@@ -783,6 +783,136 @@ struct AdjLists {
   int32_t n_gen = 0, n_fast = 0;
 };
 
+// Device tables of an adjoint run, shared by every problem of a batch: the
+// general and plain tile lists and the receiver sources as one CSR over both
+// (general first).  `W` is a layout with the offsets gen_idx, fast_idx,
+// src_ptr, src_node, src_id and rec_node.
+template <typename W>
+rswr_status_t upload_adj_lists(const rswr_plan_s& p, const int64_t* rec_idx, int32_t n_rec,
+                               char* ws, const W& L, hipStream_t s, AdjLists* al) {
+  const int64_t TM = int64_t(p.threads) * p.per_thread;
+  const int32_t n_all = static_cast<int32_t>(p.tiles.size());
+  std::vector<int32_t> gen, fast, ptr(1, 0), id;
+  std::vector<int64_t> node;
+  for (int32_t t = 0; t < n_all; ++t) (p.tiles[t].general ? gen : fast).push_back(t);
+  for (const std::vector<int32_t>* list : {&gen, &fast}) {
+    for (int32_t t : *list) {
+      const Tile& x = p.tiles[t];
+      for (int32_t r = 0; r < n_rec; ++r) {
+        const int64_t j = rec_idx[r];
+        if (j > 0 && j < p.M - 1 && j >= x.a && j <= x.a + TM - 1) {
+          id.push_back(r);
+          node.push_back(rec_idx[r]);
+        }
+      }
+      ptr.push_back(static_cast<int32_t>(id.size()));
+    }
+  }
+  std::vector<int64_t> recs(rec_idx, rec_idx + n_rec);
+  auto up = [&](size_t off, const void* src, size_t bytes) -> rswr_status_t {
+    if (bytes) RSWR_HIP(hipMemcpyAsync(ws + off, src, bytes, hipMemcpyHostToDevice, s));
+    return RSWR_OK;
+  };
+  rswr_status_t st;
+  if ((st = up(L.gen_idx, gen.data(), gen.size() * 4)) != RSWR_OK) return st;
+  if ((st = up(L.fast_idx, fast.data(), fast.size() * 4)) != RSWR_OK) return st;
+  if ((st = up(L.src_ptr, ptr.data(), ptr.size() * 4)) != RSWR_OK) return st;
+  if ((st = up(L.src_node, node.data(), node.size() * 8)) != RSWR_OK) return st;
+  if ((st = up(L.src_id, id.data(), id.size() * 4)) != RSWR_OK) return st;
+  if ((st = up(L.rec_node, recs.data(), recs.size() * 8)) != RSWR_OK) return st;
+  al->n_gen = static_cast<int32_t>(gen.size());
+  al->n_fast = static_cast<int32_t>(fast.size());
+  return RSWR_OK;
+}
+
+// Buffers of one backward span k (levels n_e = n_k + S down to n_k).
+template <typename T>
+struct AdjSpanIO {
+  T* w_cur;         // adjoint state at the span end (in)
+  T* w_nxt;         // at the span start (out)
+  T* afl;           // adjoint fluxes of the span
+  const T* u_beg;   // forward state at the span start
+  const T* u_end;   // and at its end
+  const T* ffl;     // forward fluxes of the span
+  double* lam;      // dJ/dlam partials, one per tile
+};
+
+// The adjoint predict and update of one span (last span first), all tiles;
+// `ys` batches same-shape problems along grid dimension y.
+template <typename T, typename W>
+rswr_status_t enqueue_adj_span(const rswr_plan_s* p, const DevTables& d, char* ws,
+                               const W& L, const AdjLists& al, int64_t k, int64_t n_steps,
+                               const AdjSpanIO<T>& io, const void* fa, const void* fb,
+                               const void* gtr, void* gfa, void* gfb, int32_t n_rec,
+                               const rswr::YStrides& ys, hipStream_t s) {
+  const int64_t M = p->M;
+  const int64_t n_k = k * p->S;
+  const int32_t S = static_cast<int32_t>(std::min<int64_t>(p->S, n_steps - n_k));
+  const int64_t n_e = n_k + S;
+  const double c2 = p->lam * p->lam;
+  rswr::AdjPredictArgs<T> pa{};
+  pa.w = io.w_cur;
+  pa.flux = io.afl;
+  pa.lo = d.lo;
+  pa.hi = d.hi;
+  pa.rec_node = reinterpret_cast<const int64_t*>(ws + L.rec_node);
+  pa.gtr = static_cast<const T*>(gtr);
+  pa.ys = ys;
+  pa.gtr_ld = n_steps;
+  pa.M = M;
+  pa.n_e = n_e;
+  pa.N = p->N;
+  pa.shat = S;
+  pa.ld = p->flux_ld;
+  pa.n_rec = n_rec;
+  pa.c2 = T(c2);
+  pa.k = T(2.0 - 2.0 * c2);
+  pa.r = T(1.0 / (2.0 * p->dx));
+  pa.q = T(2.0 * p->dx);
+  RSWR_HIP(rswr::launch_adj_predict<T>(pa, 2 * p->S_max + 1, s));
+  rswr::AdjUpdateArgs<T> ua{};
+  ua.w_in = io.w_cur;
+  ua.w_out = io.w_nxt;
+  ua.u_end = io.u_end;
+  ua.u_beg = io.u_beg;
+  ua.ffl = io.ffl;
+  ua.afl = io.afl;
+  ua.fa = static_cast<const T*>(fa);
+  ua.fb = static_cast<const T*>(fb);
+  ua.tiles = d.tiles;
+  ua.gtr = static_cast<const T*>(gtr);
+  ua.gtr_ld = n_steps;
+  ua.grad_fa = static_cast<T*>(gfa);
+  ua.grad_fb = static_cast<T*>(gfb);
+  ua.lam_part = io.lam;
+  ua.ys = ys;
+  ua.M = M;
+  ua.n_e = n_e;
+  ua.n_k = n_k;
+  ua.span = S;
+  ua.ld = p->flux_ld;
+  ua.c2 = T(c2);
+  ua.k = T(2.0 - 2.0 * c2);
+  ua.q = T(2.0 * p->dx);
+  ua.src_ptr = reinterpret_cast<const int32_t*>(ws + L.src_ptr);
+  ua.src_node = reinterpret_cast<const int64_t*>(ws + L.src_node);
+  ua.src_id = reinterpret_cast<const int32_t*>(ws + L.src_id);
+  if (al.n_gen > 0) {
+    rswr::AdjUpdateArgs<T> g = ua;
+    g.tile_idx = reinterpret_cast<const int32_t*>(ws + L.gen_idx);
+    g.n_tiles = al.n_gen;
+    RSWR_HIP(rswr::launch_adj_update<T>(g, p->threads, p->per_thread, true, s));
+  }
+  if (al.n_fast > 0) {
+    rswr::AdjUpdateArgs<T> f = ua;
+    f.tile_idx = reinterpret_cast<const int32_t*>(ws + L.fast_idx);
+    f.n_tiles = al.n_fast;
+    f.src_ptr = ua.src_ptr + al.n_gen;
+    RSWR_HIP(rswr::launch_adj_update<T>(f, p->threads, p->per_thread, false, s));
+  }
+  return RSWR_OK;
+}
+
 template <typename T>
 rswr_status_t enqueue_adjoint(rswr_plan_s* p, const DevTables& d, const void* ckpt,
                               const void* fa, const void* fb, int64_t n_steps,
@@ -804,77 +934,165 @@ rswr_status_t enqueue_adjoint(rswr_plan_s* p, const DevTables& d, const void* ck
   RSWR_HIP(rswr::launch_fill<double>(lam, 0.0, std::max(n_all, 1), s));
   RSWR_HIP(rswr::launch_fill<T>(static_cast<T*>(gfa), T(0), n_steps + 1, s));
   RSWR_HIP(rswr::launch_fill<T>(static_cast<T*>(gfb), T(0), n_steps + 1, s));
-  const double c2 = p->lam * p->lam;
+  const rswr::YStrides one{};
   for (int64_t k = K - 1; k >= 0; --k) {
-    const int64_t n_k = k * p->S;
-    const int32_t S = static_cast<int32_t>(std::min<int64_t>(p->S, n_steps - n_k));
-    const int64_t n_e = n_k + S;
-    rswr::AdjPredictArgs<T> pa{};
-    pa.w = w_cur;
-    pa.flux = afl;
-    pa.lo = d.lo;
-    pa.hi = d.hi;
-    pa.rec_node = reinterpret_cast<const int64_t*>(ws + L.rec_node);
-    pa.gtr = static_cast<const T*>(gtr);
-    pa.gtr_ld = n_steps;
-    pa.M = M;
-    pa.n_e = n_e;
-    pa.N = p->N;
-    pa.shat = S;
-    pa.ld = p->flux_ld;
-    pa.n_rec = n_rec;
-    pa.c2 = T(c2);
-    pa.k = T(2.0 - 2.0 * c2);
-    pa.r = T(1.0 / (2.0 * p->dx));
-    pa.q = T(2.0 * p->dx);
-    RSWR_HIP(rswr::launch_adj_predict<T>(pa, 2 * p->S_max + 1, s));
-    rswr::AdjUpdateArgs<T> ua{};
-    ua.w_in = w_cur;
-    ua.w_out = w_nxt;
-    ua.u_end = ck + (k + 1) * st_elems;
-    ua.u_beg = ck + k * st_elems;
-    ua.ffl = ck_flux + k * fl_elems;
-    ua.afl = afl;
-    ua.fa = static_cast<const T*>(fa);
-    ua.fb = static_cast<const T*>(fb);
-    ua.tiles = d.tiles;
-    ua.gtr = static_cast<const T*>(gtr);
-    ua.gtr_ld = n_steps;
-    ua.grad_fa = static_cast<T*>(gfa);
-    ua.grad_fb = static_cast<T*>(gfb);
-    ua.lam_part = lam;
-    ua.M = M;
-    ua.n_e = n_e;
-    ua.n_k = n_k;
-    ua.span = S;
-    ua.ld = p->flux_ld;
-    ua.c2 = T(c2);
-    ua.k = T(2.0 - 2.0 * c2);
-    ua.q = T(2.0 * p->dx);
-    if (al.n_gen > 0) {
-      rswr::AdjUpdateArgs<T> g = ua;
-      g.tile_idx = reinterpret_cast<const int32_t*>(ws + L.gen_idx);
-      g.n_tiles = al.n_gen;
-      g.src_ptr = reinterpret_cast<const int32_t*>(ws + L.src_ptr);
-      g.src_node = reinterpret_cast<const int64_t*>(ws + L.src_node);
-      g.src_id = reinterpret_cast<const int32_t*>(ws + L.src_id);
-      RSWR_HIP(rswr::launch_adj_update<T>(g, p->threads, p->per_thread, true, s));
-    }
-    if (al.n_fast > 0) {
-      rswr::AdjUpdateArgs<T> f = ua;
-      f.tile_idx = reinterpret_cast<const int32_t*>(ws + L.fast_idx);
-      f.n_tiles = al.n_fast;
-      f.src_ptr = reinterpret_cast<const int32_t*>(ws + L.src_ptr) + al.n_gen;
-      f.src_node = reinterpret_cast<const int64_t*>(ws + L.src_node);
-      f.src_id = reinterpret_cast<const int32_t*>(ws + L.src_id);
-      RSWR_HIP(rswr::launch_adj_update<T>(f, p->threads, p->per_thread, false, s));
-    }
+    const AdjSpanIO<T> io{w_cur, w_nxt, afl, ck + k * st_elems, ck + (k + 1) * st_elems,
+                          ck_flux + k * fl_elems, lam};
+    const rswr_status_t st = enqueue_adj_span<T>(p, d, ws, L, al, k, n_steps, io, fa, fb,
+                                                 gtr, gfa, gfb, n_rec, one, s);
+    if (st != RSWR_OK) return st;
     std::swap(w_cur, w_nxt);
   }
   RSWR_HIP(rswr::launch_adj_finish<T>(
       static_cast<T*>(gfa), static_cast<T*>(gfb), static_cast<const T*>(gtr), n_steps,
       reinterpret_cast<const int64_t*>(ws + L.rec_node), n_rec, M, n_steps, lam, n_all,
       p->lam, glam, s));
+  return RSWR_OK;
+}
+
+// A batch of adjoint solves of one plan (same shape, receivers and span),
+// each from rest, processed `group` problems at a time with chunked
+// checkpoints: the forward pass keeps the state at every C-th span boundary
+// (C spans per segment); the backward sweep recomputes each segment's span
+// states and fluxes, last segment first, and runs its adjoint spans.  All
+// problems of a group share every launch (grid dimension y).
+struct AdjBatchWs {
+  // shared tables (as AdjWs)
+  size_t gen_idx = 0, fast_idx = 0, src_ptr = 0, src_node = 0, src_id = 0, rec_node = 0;
+  // one block per problem of a group; offsets inside a block
+  size_t coarse = 0, seg_st = 0, seg_fl = 0, w0 = 0, w1 = 0, afl = 0, lam = 0;
+  size_t blocks = 0, block = 0, total = 0;
+  int64_t K = 0, C = 0, n_seg = 0;
+};
+
+AdjBatchWs adj_batch_layout(const rswr_plan_s& p, int64_t n_steps, int32_t n_rec,
+                            int32_t group, int32_t seg) {
+  AdjBatchWs w;
+  const size_t b = elem_size(p);
+  const size_t nt = std::max<size_t>(p.tiles.size(), 1);
+  const size_t nr = size_t(std::max(n_rec, 1));
+  w.K = (n_steps + p.S - 1) / p.S;
+  w.C = seg > 0 ? seg : static_cast<int64_t>(std::ceil(std::sqrt(double(w.K))));
+  w.C = std::max<int64_t>(1, std::min(w.C, w.K));
+  w.n_seg = (w.K + w.C - 1) / w.C;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = off;
+    off += round_up(bytes, 256);
+    return at;
+  };
+  w.gen_idx = take(nt * sizeof(int32_t));
+  w.fast_idx = take(nt * sizeof(int32_t));
+  w.src_ptr = take((nt + 1) * sizeof(int32_t));
+  w.src_node = take(nt * nr * sizeof(int64_t));
+  w.src_id = take(nt * nr * sizeof(int32_t));
+  w.rec_node = take(nr * sizeof(int64_t));
+  w.blocks = off;
+  const size_t st = 2 * size_t(p.M) * b;
+  const size_t fl = size_t(std::max(p.N - 1, 1)) * 2 * p.flux_ld * b;
+  off = 0;
+  w.coarse = take(size_t(w.n_seg) * st);
+  w.seg_st = take(size_t(w.C + 1) * st);
+  w.seg_fl = take(size_t(w.C) * fl);
+  w.w0 = take(st);
+  w.w1 = take(st);
+  w.afl = take(fl);
+  w.lam = take(nt * sizeof(double));
+  w.block = off;
+  w.total = w.blocks + size_t(std::max(group, 1)) * w.block;
+  return w;
+}
+
+template <typename T>
+rswr_status_t enqueue_adjoint_batch(rswr_plan_s* p, const DevTables& d, int32_t n_prob,
+                                    const void* fa, const void* fb, int64_t src_ld,
+                                    int64_t n_steps, const AdjLists& al, const void* gtr,
+                                    void* gfa, void* gfb, double* glam, char* ws,
+                                    const AdjBatchWs& L, int32_t n_rec, int32_t group,
+                                    hipStream_t s) {
+  const int64_t M = p->M;
+  const size_t stE = 2 * size_t(M);
+  const size_t flE = size_t(std::max(p->N - 1, 1)) * 2 * p->flux_ld;
+  const int32_t n_all = static_cast<int32_t>(p->tiles.size());
+  char* const blk = ws + L.blocks;
+  T* const coarse = reinterpret_cast<T*>(blk + L.coarse);
+  T* const seg_st = reinterpret_cast<T*>(blk + L.seg_st);
+  T* const seg_fl = reinterpret_cast<T*>(blk + L.seg_fl);
+  T* const w0 = reinterpret_cast<T*>(blk + L.w0);
+  T* const w1 = reinterpret_cast<T*>(blk + L.w1);
+  T* const afl = reinterpret_cast<T*>(blk + L.afl);
+  double* const lam = reinterpret_cast<double*>(blk + L.lam);
+  const int64_t B = static_cast<int64_t>(L.block);
+  const int64_t gstride = int64_t(n_rec) * n_steps;
+  for (int32_t g0 = 0; g0 < n_prob; g0 += group) {
+    const int32_t G = std::min(group, n_prob - g0);
+    rswr::YStrides ys{};
+    ys.ws = B;
+    ys.src = src_ld * int64_t(sizeof(T));
+    ys.gtr = gstride * int64_t(sizeof(T));
+    ys.grad = (n_steps + 1) * int64_t(sizeof(T));
+    ys.ny = G;
+    const T* fa0 = static_cast<const T*>(fa) + int64_t(g0) * src_ld;
+    const T* fb0 = static_cast<const T*>(fb) + int64_t(g0) * src_ld;
+    const T* gtr0 = static_cast<const T*>(gtr) + int64_t(g0) * gstride;
+    T* gfa0 = static_cast<T*>(gfa) + int64_t(g0) * (n_steps + 1);
+    T* gfb0 = static_cast<T*>(gfb) + int64_t(g0) * (n_steps + 1);
+    // one forward span of every problem of the group: in -> out (+ fluxes)
+    auto fwd = [&](int64_t k, const T* in, T* out, T* flux_out) -> rswr_status_t {
+      const int64_t n0 = k * p->S;
+      const int32_t S = static_cast<int32_t>(std::min<int64_t>(p->S, n_steps - n0));
+      rswr::UpdateArgs<T> ua = update_args<T>(*p, d, in, fa0, fb0, n0, nullptr, nullptr, S, out);
+      ua.flux = nullptr;
+      ua.flux_out = flux_out;
+      ua.ys = ys;
+      RSWR_HIP(launch_fused_span<T>(*p, ua, d.idx, p->n_gen, d.idx + p->n_gen,
+                                    n_all - p->n_gen, s));
+      return RSWR_OK;
+    };
+    rswr_status_t st;
+    // forward from rest, keeping the state at every C-th span boundary
+    RSWR_HIP(rswr::launch_fill_y<T>(coarse, T(0), int64_t(stE), G, B, s));
+    const T* cur = coarse;
+    for (int64_t k = 0; k < L.K; ++k) {
+      T* out;
+      if ((k + 1) % L.C == 0 && (k + 1) / L.C < L.n_seg)
+        out = coarse + ((k + 1) / L.C) * stE;
+      else
+        out = (cur == seg_st) ? seg_st + stE : seg_st;
+      if ((st = fwd(k, cur, out, nullptr)) != RSWR_OK) return st;
+      cur = out;
+    }
+    // backward: segments last first; each recomputed, then swept in reverse
+    RSWR_HIP(rswr::launch_fill_y<T>(w0, T(0), int64_t(stE), G, B, s));
+    RSWR_HIP(rswr::launch_fill_y<double>(lam, 0.0, std::max(n_all, 1), G, B, s));
+    RSWR_HIP(rswr::launch_fill<T>(gfa0, T(0), int64_t(G) * (n_steps + 1), s));
+    RSWR_HIP(rswr::launch_fill<T>(gfb0, T(0), int64_t(G) * (n_steps + 1), s));
+    T* w_cur = w0;
+    T* w_nxt = w1;
+    for (int64_t j = L.n_seg - 1; j >= 0; --j) {
+      const int64_t k0 = j * L.C, k1 = std::min(L.K, k0 + L.C);
+      RSWR_HIP(rswr::launch_copy_y<T>(seg_st, coarse + j * stE, int64_t(stE), G, B, s));
+      for (int64_t k = k0; k < k1; ++k)
+        if ((st = fwd(k, seg_st + (k - k0) * stE, seg_st + (k - k0 + 1) * stE,
+                      seg_fl + (k - k0) * flE)) != RSWR_OK)
+          return st;
+      for (int64_t k = k1 - 1; k >= k0; --k) {
+        const AdjSpanIO<T> io{w_cur, w_nxt, afl, seg_st + (k - k0) * stE,
+                              seg_st + (k - k0 + 1) * stE, seg_fl + (k - k0) * flE, lam};
+        if ((st = enqueue_adj_span<T>(p, d, ws, L, al, k, n_steps, io, fa0, fb0, gtr0, gfa0,
+                                      gfb0, n_rec, ys, s)) != RSWR_OK)
+          return st;
+        std::swap(w_cur, w_nxt);
+      }
+    }
+    for (int32_t y = 0; y < G; ++y)
+      RSWR_HIP(rswr::launch_adj_finish<T>(
+          gfa0 + int64_t(y) * (n_steps + 1), gfb0 + int64_t(y) * (n_steps + 1),
+          gtr0 + int64_t(y) * gstride, n_steps,
+          reinterpret_cast<const int64_t*>(ws + L.rec_node), n_rec, M, n_steps,
+          reinterpret_cast<const double*>(reinterpret_cast<const char*>(lam) + y * B), n_all,
+          p->lam, glam + g0 + y, s));
+  }
   return RSWR_OK;
 }
 
@@ -1400,42 +1618,8 @@ rswr_status_t rswr_solve_adjoint(rswr_plan_t p, const void* checkpoints, const v
   if (st != RSWR_OK) return st;
   hipStream_t s = static_cast<hipStream_t>(stream);
   char* ws = static_cast<char*>(workspace);
-  const int64_t TM = int64_t(p->threads) * p->per_thread;
-
-  // general kernel: the general tiles; every other tile in the second
-  // launch.  Sources (interior receivers in a tile's register region) as one
-  // CSR over the general list, then the other.
-  const int32_t n_all = static_cast<int32_t>(p->tiles.size());
-  std::vector<int32_t> gen, fast, ptr(1, 0), id;
-  std::vector<int64_t> node;
-  for (int32_t t = 0; t < n_all; ++t) (p->tiles[t].general ? gen : fast).push_back(t);
-  for (const std::vector<int32_t>* list : {&gen, &fast}) {
-    for (int32_t t : *list) {
-      const Tile& x = p->tiles[t];
-      for (int32_t r = 0; r < n_rec; ++r) {
-        const int64_t j = rec_idx[r];
-        if (j > 0 && j < p->M - 1 && j >= x.a && j <= x.a + TM - 1) {
-          id.push_back(r);
-          node.push_back(rec_idx[r]);
-        }
-      }
-      ptr.push_back(static_cast<int32_t>(id.size()));
-    }
-  }
-  std::vector<int64_t> recs(rec_idx, rec_idx + n_rec);
-  auto up = [&](size_t off, const void* src, size_t bytes) -> rswr_status_t {
-    if (bytes) RSWR_HIP(hipMemcpyAsync(ws + off, src, bytes, hipMemcpyHostToDevice, s));
-    return RSWR_OK;
-  };
-  if ((st = up(L.gen_idx, gen.data(), gen.size() * 4)) != RSWR_OK) return st;
-  if ((st = up(L.fast_idx, fast.data(), fast.size() * 4)) != RSWR_OK) return st;
-  if ((st = up(L.src_ptr, ptr.data(), ptr.size() * 4)) != RSWR_OK) return st;
-  if ((st = up(L.src_node, node.data(), node.size() * 8)) != RSWR_OK) return st;
-  if ((st = up(L.src_id, id.data(), id.size() * 4)) != RSWR_OK) return st;
-  if ((st = up(L.rec_node, recs.data(), recs.size() * 8)) != RSWR_OK) return st;
   AdjLists al;
-  al.n_gen = static_cast<int32_t>(gen.size());
-  al.n_fast = static_cast<int32_t>(fast.size());
+  if ((st = upload_adj_lists(*p, rec_idx, n_rec, ws, L, s, &al)) != RSWR_OK) return st;
 
   auto enqueue = [&](hipStream_t q) {
     return p->dtype == RSWR_F64
@@ -1457,6 +1641,72 @@ rswr_status_t rswr_solve_adjoint(rswr_plan_t p, const void* checkpoints, const v
                      reinterpret_cast<int64_t>(grad_f_a),
                      reinterpret_cast<int64_t>(grad_f_b),
                      reinterpret_cast<int64_t>(grad_lambda),
+                     reinterpret_cast<int64_t>(workspace),
+                     al.n_gen,
+                     al.n_fast};
+  return run_graph(p, d, key, enqueue, s);
+}
+
+rswr_status_t rswr_adjoint_batch_workspace_size(rswr_plan_t p, int64_t n_steps, int32_t n_rec,
+                                                int32_t group, int32_t seg, size_t* bytes) {
+  if (!p || !bytes || n_steps < 1 || n_rec < 0 || group < 1 || seg < 0)
+    return fail(RSWR_ERR_INVALID_ARG, "bad argument");
+  *bytes = adj_batch_layout(*p, n_steps, n_rec, group, seg).total;
+  return RSWR_OK;
+}
+
+rswr_status_t rswr_solve_adjoint_batch(rswr_plan_t p, int32_t n_prob, const void* f_a,
+                                       const void* f_b, int64_t src_ld, int64_t n_steps,
+                                       const int64_t* rec_idx, int32_t n_rec,
+                                       const void* grad_traces, void* grad_f_a,
+                                       void* grad_f_b, double* grad_lambda, int32_t group,
+                                       int32_t seg, void* workspace, size_t ws_bytes,
+                                       void* stream) {
+  if (!p || !f_a || !f_b || !grad_f_a || !grad_f_b || !grad_lambda || n_prob < 1)
+    return fail(RSWR_ERR_INVALID_ARG, "null pointer or no problems");
+  if (p->mode != RSWR_SPAN_FIXED || !p->fused || !p->src_node.empty())
+    return fail(RSWR_ERR_UNSUPPORTED,
+                "rswr_solve_adjoint_batch runs fused FIXED plans without sources");
+  if (n_steps < 1 || n_rec < 0 || (n_rec > 0 && (!rec_idx || !grad_traces)) || group < 1 ||
+      seg < 0 || src_ld < n_steps + 1)
+    return fail(RSWR_ERR_INVALID_ARG, "bad n_steps, receivers, group, seg or src_ld");
+  for (int32_t r = 0; r < n_rec; ++r)
+    if (rec_idx[r] < 0 || rec_idx[r] >= p->M)
+      return fail(RSWR_ERR_INVALID_ARG, "receiver index out of range");
+  const AdjBatchWs L = adj_batch_layout(*p, n_steps, n_rec, group, seg);
+  if (!workspace || ws_bytes < L.total)
+    return fail(RSWR_ERR_NOMEM, "workspace needs " + std::to_string(L.total) + " bytes");
+  DevTables* d = nullptr;
+  int device = 0;
+  rswr_status_t st = ensure_device(p, &d, &device);
+  if (st != RSWR_OK) return st;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  char* ws = static_cast<char*>(workspace);
+  AdjLists al;
+  if ((st = upload_adj_lists(*p, rec_idx, n_rec, ws, L, s, &al)) != RSWR_OK) return st;
+  auto enqueue = [&](hipStream_t q) {
+    return p->dtype == RSWR_F64
+               ? enqueue_adjoint_batch<double>(p, *d, n_prob, f_a, f_b, src_ld, n_steps, al,
+                                               grad_traces, grad_f_a, grad_f_b, grad_lambda,
+                                               ws, L, n_rec, group, q)
+               : enqueue_adjoint_batch<float>(p, *d, n_prob, f_a, f_b, src_ld, n_steps, al,
+                                              grad_traces, grad_f_a, grad_f_b, grad_lambda,
+                                              ws, L, n_rec, group, q);
+  };
+  const GraphKey key{7,
+                     device,
+                     n_prob,
+                     reinterpret_cast<int64_t>(f_a),
+                     reinterpret_cast<int64_t>(f_b),
+                     src_ld,
+                     n_steps,
+                     n_rec,
+                     reinterpret_cast<int64_t>(grad_traces),
+                     reinterpret_cast<int64_t>(grad_f_a),
+                     reinterpret_cast<int64_t>(grad_f_b),
+                     reinterpret_cast<int64_t>(grad_lambda),
+                     group,
+                     seg,
                      reinterpret_cast<int64_t>(workspace),
                      al.n_gen,
                      al.n_fast};

@@ -52,6 +52,17 @@ struct Tile {
 };
 static_assert(sizeof(Tile) == 64, "Tile layout");
 
+// Problems of a same-shape batch along grid dimension y: problem y's
+// buffers lie a fixed number of bytes after problem 0's.  ny <= 1: a
+// single problem (every stride unused).
+struct YStrides {
+  int64_t ws;    // buffers in the batch workspace (states, fluxes, adjoint state, partials)
+  int64_t src;   // boundary samples f_A, f_B
+  int64_t gtr;   // dJ/dtrace
+  int64_t grad;  // dJ/df outputs
+  int32_t ny, pad;
+};
+
 template <typename T>
 struct PredictArgs {
   const T* state;       // [2][M]
@@ -101,6 +112,7 @@ struct UpdateArgs {
   // nullable: the span starts at level *n0_dev instead of n0 (trace columns
   // shift by the same amount)
   const int64_t* n0_dev;
+  YStrides ys;  // batch of same-shape problems (fused span: states, fa/fb, flux_out)
   int64_t M, n0, trace_ld, trace_col0;
   int32_t n_tiles, span, ld, pad;
   T c2, k, q, r;
@@ -138,6 +150,7 @@ struct AdjPredictArgs {
   const int64_t* hi;
   const int64_t* rec_node;  // all receivers, in receiver order
   const T* gtr;         // dJ/dtrace [n_rec][gtr_ld], column L-1 for level L
+  YStrides ys;          // batch of same-shape problems (w, flux, gtr)
   int64_t gtr_ld, M, n_e;
   int32_t N, shat, ld, n_rec;
   T c2, k, r, q;
@@ -163,6 +176,7 @@ struct AdjUpdateArgs {
   T* grad_fa;           // [n_steps+1]
   T* grad_fb;
   double* lam_part;     // one accumulator per tile (indexed by tile number)
+  YStrides ys;          // batch of same-shape problems (every pointer above but the tables)
   int64_t M, n_e, n_k;
   int32_t n_tiles, span, ld, pad;
   T c2, k, q;
@@ -238,6 +252,12 @@ hipError_t launch_quiet_next(QuietCtl* c, hipStream_t s);
 template <typename T>
 hipError_t launch_copy_if(T* dst, const T* src, int64_t n, const int32_t* flag,
                           hipStream_t s);
+// n elements for each of ny problems, problem y at y * stride bytes
+template <typename T>
+hipError_t launch_copy_y(T* dst, const T* src, int64_t n, int32_t ny, int64_t stride,
+                         hipStream_t s);
+template <typename T>
+hipError_t launch_fill_y(T* dst, T v, int64_t n, int32_t ny, int64_t stride, hipStream_t s);
 template <typename T>
 hipError_t launch_copy(T* dst, const T* src, int64_t n, hipStream_t s);
 template <typename T>

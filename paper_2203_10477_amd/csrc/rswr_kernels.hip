@@ -430,6 +430,47 @@ hipError_t launch_copy_if(T* dst, const T* src, int64_t n, const int32_t* flag,
 }
 
 template <typename T>
+__global__ __launch_bounds__(256) void k_copy_y(T* dst, const T* src, int64_t n,
+                                                int64_t stride) {
+  T* const d = at_y(dst, stride);
+  const T* const x = at_y(src, stride);
+  const int64_t step = static_cast<int64_t>(gridDim.x) * blockDim.x;
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+       i += step)
+    d[i] = x[i];
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_fill_y(T* dst, T v, int64_t n, int64_t stride) {
+  T* const d = at_y(dst, stride);
+  const int64_t step = static_cast<int64_t>(gridDim.x) * blockDim.x;
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+       i += step)
+    d[i] = v;
+}
+
+template <typename T>
+hipError_t launch_copy_y(T* dst, const T* src, int64_t n, int32_t ny, int64_t stride,
+                         hipStream_t s) {
+  if (n <= 0 || ny <= 0) return hipSuccess;
+  int64_t blocks = (n + 255) / 256;
+  if (blocks > 1024) blocks = 1024;
+  hipLaunchKernelGGL(k_copy_y<T>, dim3(static_cast<unsigned>(blocks), ny), dim3(256), 0, s,
+                     dst, src, n, stride);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_fill_y(T* dst, T v, int64_t n, int32_t ny, int64_t stride, hipStream_t s) {
+  if (n <= 0 || ny <= 0) return hipSuccess;
+  int64_t blocks = (n + 255) / 256;
+  if (blocks > 1024) blocks = 1024;
+  hipLaunchKernelGGL(k_fill_y<T>, dim3(static_cast<unsigned>(blocks), ny), dim3(256), 0, s,
+                     dst, v, n, stride);
+  return hipGetLastError();
+}
+
+template <typename T>
 hipError_t launch_copy(T* dst, const T* src, int64_t n, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   int64_t blocks = (n + 255) / 256;
@@ -450,6 +491,14 @@ template hipError_t launch_select<double>(const SelectArgs<double>&, hipStream_t
 template hipError_t launch_copy<float>(float*, const float*, int64_t, hipStream_t);
 template hipError_t launch_copy<double>(double*, const double*, int64_t, hipStream_t);
 template hipError_t launch_copy_if<float>(float*, const float*, int64_t, const int32_t*,
+                                          hipStream_t);
+template hipError_t launch_copy_y<float>(float*, const float*, int64_t, int32_t, int64_t,
+                                         hipStream_t);
+template hipError_t launch_copy_y<double>(double*, const double*, int64_t, int32_t, int64_t,
+                                          hipStream_t);
+template hipError_t launch_fill_y<float>(float*, float, int64_t, int32_t, int64_t,
+                                         hipStream_t);
+template hipError_t launch_fill_y<double>(double*, double, int64_t, int32_t, int64_t,
                                           hipStream_t);
 template hipError_t launch_copy_if<double>(double*, const double*, int64_t, const int32_t*,
                                            hipStream_t);
