@@ -19,6 +19,7 @@ sample of the same workload.  Beside it, in the same line: the batched form
 the plain single-problem solve.
 """
 import argparse
+import ctypes
 import hashlib
 import json
 import os
@@ -240,6 +241,53 @@ def sources_section(reps, tile):
             "ms": round(ms - zero_ms, 3), "n_src": len(nodes), "tile": [lo, hi]}
 
 
+def adjoint_batch_section(tile, group=16):
+    """The large case's adjoint batch: 64 adjoint solves of the 2^24-node,
+    4096-window, overlap-64, 2*10^4-step FP32 problem, each driven by its own
+    random Ricker source at X_A, 16 receivers on nodes the wave reaches, a
+    random dJ/dtrace; checkpoints chunked (one state per segment of about
+    sqrt(572) spans, each segment recomputed in the backward sweep), `group`
+    problems per launch.  Timed once after one untimed call (which records
+    the graph).  Rate: forward updates of the batch (64 M n_steps) per
+    second of the whole call (forward pass, recomputation and backward
+    sweep)."""
+    import numpy as np
+    import torch
+    import paper_2203_10477_amd as rs
+    import workloads
+    prob = workloads.config5(np.float32)
+    n, n_prob = prob.n_steps, 64
+    plan = rs.Plan(prob.M, prob.N, prob.P, dtype=torch.float32, tile=tile)
+    fa = torch.as_tensor(workloads.adjoint_batch_sources(prob.M, n, n_prob),
+                         dtype=torch.float32, device="cuda")
+    fb = torch.zeros_like(fa)
+    g = workloads.rng(56)
+    rec = workloads.receivers(g, 16, min(prob.M - 2, int(0.8 * 0.9 * n)))
+    gtr = torch.as_tensor(g.standard_normal((n_prob, len(rec), n)), dtype=torch.float32,
+                          device="cuda")
+    ws_b = ctypes.c_size_t()
+    rs._check(rs.lib().rswr_adjoint_batch_workspace_size(plan.handle, n, len(rec), group, 0,
+                                                         ctypes.byref(ws_b)),
+              "rswr_adjoint_batch_workspace_size")
+    ws = torch.empty(ws_b.value, dtype=torch.uint8, device="cuda")
+    run = lambda: rs.rswr_solve_adjoint_batch(plan, fa, fb, n, rec, gtr, group=group,
+                                              workspace=ws)
+    ms = timed(run, 1)
+    ga, gb, gl = run()
+    torch.cuda.synchronize()
+    if not (torch.isfinite(ga).all() and torch.isfinite(gl).all()):
+        raise RuntimeError("non-finite gradients in the adjoint batch")
+    upd = n_prob * prob.M * n / 1e9
+    K = -(-n // plan.span)
+    return {"workload": f"{n_prob} adjoint solves of {prob.M} nodes, {prob.N} windows, "
+                        f"overlap {prob.P}, span {plan.span}, {n} steps, FP32, "
+                        f"{len(rec)} receivers, Ricker sources",
+            "glups": round(upd / (ms * 1e-3), 2), "s": round(ms / 1e3, 3),
+            "group": group, "seg_spans": int(np.ceil(np.sqrt(K))),
+            "workspace_gb": round(ws_b.value / 1e9, 1),
+            "tile": [plan.info["tile_threads"], plan.info["tile_per_thread"]]}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -252,7 +300,8 @@ def main():
                     help="skip the batched, adjoint and pulse-source sections")
     ap.add_argument("--tile", default="", help="threads x nodes-per-lane, e.g. 320x13 "
                     "(default: autotuned)")
-    ap.add_argument("--section", choices=("batched", "adjoint", "sources"), default=None,
+    ap.add_argument("--section", choices=("batched", "adjoint", "sources", "adjoint_batch"),
+                    default=None,
                     help="run one of the other forms alone and print its figures "
                          "(for profiling)")
     args = ap.parse_args()
@@ -276,6 +325,9 @@ def main():
             out = batched_section(reps)
         elif args.section == "adjoint":
             out = adjoint_section(reps)
+        elif args.section == "adjoint_batch":
+            tile = tuple(int(v) for v in args.tile.split("x")) if args.tile else None
+            out = adjoint_batch_section(tile)
         else:
             tile = tuple(int(v) for v in args.tile.split("x")) if args.tile else None
             out = sources_section(reps, tile)
@@ -390,6 +442,8 @@ def main():
         line["adjoint"] = adjoint_section(max(1, args.steps))
         line["sources"] = sources_section(max(1, args.steps), tile)
         line["sources"]["vs_plain"] = round(line["sources"]["glups"] / glups, 4)
+        line["adjoint_batch"] = adjoint_batch_section(tile)
+        line["adjoint_batch"]["vs_plain"] = round(line["adjoint_batch"]["glups"] / glups, 4)
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(prob, args.cpu_seconds)
     print(json.dumps(line), flush=True)

@@ -1071,14 +1071,15 @@ rswr_status_t enqueue_adjoint_batch(rswr_plan_s* p, const DevTables& d, int32_t 
     T* w_nxt = w1;
     for (int64_t j = L.n_seg - 1; j >= 0; --j) {
       const int64_t k0 = j * L.C, k1 = std::min(L.K, k0 + L.C);
-      RSWR_HIP(rswr::launch_copy_y<T>(seg_st, coarse + j * stE, int64_t(stE), G, B, s));
+      // state at boundary k0 + i of the segment: the coarse checkpoint, then
+      // the recomputed ones
+      auto bnd = [&](int64_t i) { return i == 0 ? coarse + j * stE : seg_st + i * stE; };
       for (int64_t k = k0; k < k1; ++k)
-        if ((st = fwd(k, seg_st + (k - k0) * stE, seg_st + (k - k0 + 1) * stE,
-                      seg_fl + (k - k0) * flE)) != RSWR_OK)
+        if ((st = fwd(k, bnd(k - k0), bnd(k - k0 + 1), seg_fl + (k - k0) * flE)) != RSWR_OK)
           return st;
       for (int64_t k = k1 - 1; k >= k0; --k) {
-        const AdjSpanIO<T> io{w_cur, w_nxt, afl, seg_st + (k - k0) * stE,
-                              seg_st + (k - k0 + 1) * stE, seg_fl + (k - k0) * flE, lam};
+        const AdjSpanIO<T> io{w_cur, w_nxt, afl, bnd(k - k0), bnd(k - k0 + 1),
+                              seg_fl + (k - k0) * flE, lam};
         if ((st = enqueue_adj_span<T>(p, d, ws, L, al, k, n_steps, io, fa0, fb0, gtr0, gfa0,
                                       gfb0, n_rec, ys, s)) != RSWR_OK)
           return st;
