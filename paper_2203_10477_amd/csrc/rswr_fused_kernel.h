@@ -9,21 +9,13 @@
 
 namespace rswr {
 
-// kFusedGeneral: general tiles (node 0 inside the region), receivers
-// recorded and sources injected.  kFusedExt: a launch whose tiles may
+// The kernel body.  kFusedGeneral: general tiles (node 0 inside the region),
+// receivers recorded and sources injected.  kFusedExt: a launch whose tiles may
 // record receivers or inject interior sources; each work-group takes the
 // code path its tile needs (a uniform branch), the others run the plain
 // step.  kFusedPlain: the plain step only.
 template <typename T, int NT, int MPT, int KIND>
-__global__ __launch_bounds__(NT) void k_fused(const UpdateArgs<T> p0) {
-  UpdateArgs<T> p = p0;
-  if (p0.ys.ny > 1) {  // problem blockIdx.y of a same-shape batch
-    p.state_in = at_y(p0.state_in, p0.ys.ws);
-    p.state_out = at_y(p0.state_out, p0.ys.ws);
-    p.flux_out = at_y(p0.flux_out, p0.ys.ws);
-    p.fa = at_y(p0.fa, p0.ys.src);
-    p.fb = at_y(p0.fb, p0.ys.src);
-  }
+__device__ __forceinline__ void fused_kernel_body(const UpdateArgs<T>& p) {
   constexpr int NW = NT / 64;
   constexpr int TM = NT * MPT;
   constexpr int TMP = TM + (TM >> 5) + 1;
@@ -48,6 +40,23 @@ __global__ __launch_bounds__(NT) void k_fused(const UpdateArgs<T> p0) {
   }
 }
 
+// BY: problem blockIdx.y of a same-shape batch (YStrides); its states,
+// boundary samples and flux rows lie at fixed strides from problem 0's.
+template <typename T, int NT, int MPT, int KIND, bool BY>
+__global__ __launch_bounds__(NT) void k_fused(const UpdateArgs<T> p) {
+  if constexpr (BY) {
+    UpdateArgs<T> q = p;
+    q.state_in = at_y(p.state_in, p.ys.ws);
+    q.state_out = at_y(p.state_out, p.ys.ws);
+    q.flux_out = at_y(p.flux_out, p.ys.ws);
+    q.fa = at_y(p.fa, p.ys.src);
+    q.fb = at_y(p.fb, p.ys.src);
+    fused_kernel_body<T, NT, MPT, KIND>(q);
+  } else {
+    fused_kernel_body<T, NT, MPT, KIND>(p);
+  }
+}
+
 template <typename T, int KIND>
 hipError_t launch_fused_kind(const UpdateArgs<T>& a, int threads, int per_thread,
                              hipStream_t s) {
@@ -56,8 +65,15 @@ hipError_t launch_fused_kind(const UpdateArgs<T>& a, int threads, int per_thread
   if (threads == NT_ && per_thread == MPT_) {                                     \
     if constexpr (sizeof(T) == 8 && MPT_ > 22) return hipErrorInvalidValue;      \
     else {                                                                        \
-      hipLaunchKernelGGL((k_fused<T, NT_, MPT_, KIND>),                          \
-                         dim3(a.n_tiles, a.ys.ny > 1 ? a.ys.ny : 1), dim3(NT_), 0, s, a); \
+      if (a.ys.ny <= 1) {                                                         \
+        hipLaunchKernelGGL((k_fused<T, NT_, MPT_, KIND, false>), dim3(a.n_tiles), \
+                           dim3(NT_), 0, s, a);                                   \
+      } else if constexpr (KIND != kFusedExt) {                                   \
+        hipLaunchKernelGGL((k_fused<T, NT_, MPT_, KIND, true>),                   \
+                           dim3(a.n_tiles, a.ys.ny), dim3(NT_), 0, s, a);         \
+      } else {                                                                    \
+        return hipErrorInvalidValue;                                              \
+      }                                                                           \
       return hipGetLastError();                                                   \
     }                                                                             \
   }
