@@ -43,6 +43,29 @@ __device__ __forceinline__ double lane_shift_z(double v) {
   return __builtin_bit_cast(double, lo | (hi << 32));
 }
 
+// Lane shift whose lane without a source (lane 0 for a right shift, lane 63
+// for a left shift) takes `old` instead: one DPP move sets a wave's end value
+// together with the shift.
+template <int CTRL>
+__device__ __forceinline__ float lane_shift_old(float old, float v) {
+  return __builtin_bit_cast(
+      float, static_cast<uint32_t>(__builtin_amdgcn_update_dpp(
+                 __builtin_bit_cast(int, old), __builtin_bit_cast(int, v), CTRL, 0xf, 0xf,
+                 false)));
+}
+template <int CTRL>
+__device__ __forceinline__ double lane_shift_old(double old, double v) {
+  const uint64_t b = __builtin_bit_cast(uint64_t, v);
+  const uint64_t o = __builtin_bit_cast(uint64_t, old);
+  const uint64_t lo = static_cast<uint32_t>(__builtin_amdgcn_update_dpp(
+      static_cast<int>(static_cast<uint32_t>(o)), static_cast<int>(static_cast<uint32_t>(b)),
+      CTRL, 0xf, 0xf, false));
+  const uint64_t hi = static_cast<uint32_t>(__builtin_amdgcn_update_dpp(
+      static_cast<int>(static_cast<uint32_t>(o >> 32)),
+      static_cast<int>(static_cast<uint32_t>(b >> 32)), CTRL, 0xf, 0xf, false));
+  return __builtin_bit_cast(double, lo | (hi << 32));
+}
+
 // A wave-uniform value kept in a vector register, so an instruction may
 // combine it with a scalar operand (one scalar source per VALU instruction).
 template <typename T>

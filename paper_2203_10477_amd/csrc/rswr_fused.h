@@ -159,8 +159,10 @@ __device__ __forceinline__ void fused_step(const UpdateArgs<T>& p,
                                            int s) {
   constexpr int NW = NT / 64;
   const int par = s & 1;
-  T L = lane_shift_z<kWaveShr1>(cur[MPT - 1]);
-  T R = lane_shift_z<kWaveShl1>(cur[0]);
+  // the left neighbour of lane 0 and the right neighbour of lane 63: zero
+  // data at a cut end, else the input ghost, the Dirichlet value or the
+  // neighbouring wave's node; the lane shifts below put them in place
+  T L0 = T(0), R0 = T(0);
   if constexpr (HL) {
     const T F = frame_step(lc, lo, p.c2, p.k, p.r);
     if (c.fdirL) {
@@ -170,7 +172,7 @@ __device__ __forceinline__ void fused_step(const UpdateArgs<T>& p,
     if (SRC && (uni(c.work) & (kWFrame << 0)))
       frame_sources(p, c, 0, c.a - kFrameHalf, s, lo);
     if (c.keep) fl = wr_lane(F, s, fl, c.lane);
-    L = (c.lane == 0) ? fma_(c.nq, F, cur[1]) : L;
+    L0 = fma_(c.nq, F, cur[1]);
   }
   if constexpr (HR) {
     const T F = frame_step(rc, ro, p.c2, p.k, p.r);
@@ -181,25 +183,21 @@ __device__ __forceinline__ void fused_step(const UpdateArgs<T>& p,
     if (SRC && (uni(c.work) & (kWFrame << 1)))
       frame_sources(p, c, 1, c.a + NT * MPT - 1 - kFrameHalf, s, ro);
     if (c.keep) fr = wr_lane(F, s, fr, c.lane);
-    R = (c.lane == 63) ? fma_(c.pq, F, cur[MPT - 2]) : R;
+    R0 = fma_(c.pq, F, cur[MPT - 2]);
   }
   if constexpr (NW > 1) {
     if (c.lane == 63) c.edge[par][1][c.wv] = cur[MPT - 1];
     if (c.lane == 0) c.edge[par][0][c.wv] = cur[0];
     __syncthreads();
-    if (!HL && c.wv > 0) L = (c.lane == 0) ? c.edge[par][1][c.wv - 1] : L;
-    if (!HR && c.wv < NW - 1) R = (c.lane == 63) ? c.edge[par][0][c.wv + 1] : R;
+    if (!HL && c.wv > 0) L0 = c.edge[par][1][c.wv - 1];
+    if (!HR && c.wv < NW - 1) R0 = c.edge[par][0][c.wv + 1];
   }
   // readlane reads another lane, so it runs with the whole wave active (a
-  // wave-uniform branch), never under the lane-0 / lane-63 condition
-  if (!HL && c.dirL) {
-    const T d = rd_lane(c.vA, s);
-    L = (c.lane == 0) ? d : L;
-  }
-  if (!HR && c.dirR) {
-    const T d = rd_lane(c.vB, s);
-    R = (c.lane == 63) ? d : R;
-  }
+  // wave-uniform branch)
+  if (!HL && c.dirL) L0 = rd_lane(c.vA, s);
+  if (!HR && c.dirR) R0 = rd_lane(c.vB, s);
+  const T L = lane_shift_old<kWaveShr1>(L0, cur[MPT - 1]);
+  const T R = lane_shift_old<kWaveShl1>(R0, cur[0]);
   if (GEN && c.gen)
     step_chunk<T, MPT, true>(cur, old, L, R, p.c2, p.k, -1000, c.d0, T(0),
                              rd_lane(c.vA, s + 1));
