@@ -1,70 +1,16 @@
-// rswr_adjoint.hip -- gfx950 kernels of the adjoint of the RSWR solve.
-//
-// Misfit J = sum_r sum_n (U^n[j_r] - d_r^n)^2; its reverse mode (the
-// transposed leapfrog) is W^n_j = g^n_j + k W^{n+1}_j - W^{n+2}_j +
-// c2 (W^{n+1}_{j-1} + W^{n+1}_{j+1}) on interior nodes, W = 0 on the two
-// Dirichlet nodes, g = dJ/dtrace on receiver nodes.  It is the same
-// self-adjoint wave equation run backward in time with point sources, so
-// each span of it is advanced with the method's own predict / update
-// exchange (Sec. 2.3-2.5 of Wei & Zhao, arXiv 2203.10477) on the forward
-// plan's windows.  dJ/df_A[n] = c2 W^{n+1}_1 (+ g^n_0), and
-// dJ/dlam = 2 lam sum_n sum_j W^n_j (U^{n-1}_{j-1} - 2 U^{n-1}_j + U^{n-1}_{j+1});
-// the forward field is rebuilt span by span by running the leapfrog
-// backward from the span-end checkpoint (it is time-reversible), with the
-// stored forward flux waveforms as ghost data.
-#include "rswr_device.h"
+// rswr_adjoint.hip -- gfx950 kernels of the adjoint of the RSWR solve:
+// the predict kernels, k_adj_finish and the launchers; the update of the
+// two-launch path (the fused update: rswr_adjoint_fused_*.hip).  The
+// method and the device code shared by both: rswr_adjoint.h.
+#include "rswr_adjoint.h"
 
 namespace rswr {
 
-// ---------------------------------------------------------------------------
-// Adjoint predict: W's flux at each output node over shat levels, zero input
-// flux at the window's own inputs, receiver sources injected in receiver
-// order after each level (the order the single-domain reverse sweep uses).
-// One wave per (interface, side) carries a 128-node frame around the output
-// node o, two nodes per lane, in registers: the sample at o over shat <=
-// light-cone-limit levels reads only [o-shat, o+shat] (the window's input
-// ends lie farther away), so the frame runs the plain stencil with the data
-// mirrored into the window, W = 0 on nodes 0 and M-1, and the sources of
-// [o-shat, o+shat] inside the window: the same samples as the whole-window
-// prediction, bit for bit.  Each source's samples for the span sit one per
-// lane (kAdjFrameSrc of them in registers, further ones read each step).
-// ---------------------------------------------------------------------------
-constexpr int kAdjFrameSrc = 8;
-
-// Problem blockIdx.y of a same-shape batch (YStrides); the arguments as they
-// are for a single problem.
-template <typename T>
-__device__ __forceinline__ AdjPredictArgs<T> batch_problem(const AdjPredictArgs<T>& a) {
-  AdjPredictArgs<T> p = a;
-  if (a.ys.ny > 1) {
-    p.w = at_y(a.w, a.ys.ws);
-    p.flux = at_y(a.flux, a.ys.ws);
-    p.gtr = at_y(a.gtr, a.ys.gtr);
-  }
-  return p;
-}
-
-template <typename T>
-__device__ __forceinline__ AdjUpdateArgs<T> batch_problem(const AdjUpdateArgs<T>& a) {
-  AdjUpdateArgs<T> p = a;
-  if (a.ys.ny > 1) {
-    p.w_in = at_y(a.w_in, a.ys.ws);
-    p.w_out = at_y(a.w_out, a.ys.ws);
-    p.u_end = at_y(a.u_end, a.ys.ws);
-    p.u_beg = at_y(a.u_beg, a.ys.ws);
-    p.ffl = at_y(a.ffl, a.ys.ws);
-    p.afl = at_y(a.afl, a.ys.ws);
-    p.lam_part = at_y(a.lam_part, a.ys.ws);
-    p.fa = at_y(a.fa, a.ys.src);
-    p.fb = at_y(a.fb, a.ys.src);
-    p.gtr = at_y(a.gtr, a.ys.gtr);
-    p.grad_fa = at_y(a.grad_fa, a.ys.grad);
-    p.grad_fb = at_y(a.grad_fb, a.ys.grad);
-  }
-  return p;
-}
-
-inline unsigned ny(const YStrides& y) { return y.ny > 1 ? static_cast<unsigned>(y.ny) : 1u; }
+// the fused update is instantiated in its own translation units
+extern template hipError_t launch_adj_update_kind<float, true>(const AdjUpdateArgs<float>&, int,
+                                                               int, bool, hipStream_t);
+extern template hipError_t launch_adj_update_kind<double, true>(const AdjUpdateArgs<double>&,
+                                                                int, int, bool, hipStream_t);
 
 template <typename T>
 __global__ __launch_bounds__(64) void k_adj_predict_frame(const AdjPredictArgs<T> p0) {
@@ -72,109 +18,16 @@ __global__ __launch_bounds__(64) void k_adj_predict_frame(const AdjPredictArgs<T
   const int i = blockIdx.x >> 1, side = blockIdx.x & 1;
   const int w = i + side;
   const int64_t o = (side == 0) ? p.lo[i + 1] : p.hi[i];
-  const int64_t wlo = p.lo[w], whi = p.hi[w];
   const int shat = p.shat;
   const int lane = threadIdx.x;
-  const int64_t A = (o - shat > wlo) ? o - shat : wlo;
-  const int64_t B = (o + shat < whi) ? o + shat : whi;
-  const int64_t base = o - kFrameHalf;
-  // frame: cur = W^{L+1}, old = W^{L+2}, lane holds base + 2 lane + e
-  T cur[2], old[2];
-  bool dir[2];
-#pragma unroll
-  for (int e = 0; e < 2; ++e) {
-    const int64_t x = base + 2 * lane + e;
-    int64_t j = (x < wlo) ? 2 * wlo - x : ((x > whi) ? 2 * whi - x : x);
-    j = j < wlo ? wlo : (j > whi ? whi : j);
-    cur[e] = p.w[p.M + j];
-    old[e] = p.w[j];
-    dir[e] = (x == 0) || (x == p.M - 1);
-  }
-  // sources in [A, B] (interior nodes), in receiver order: frame offset and
-  // the span's samples (lane s: level n_e - s, column n_e - s - 1)
-  // (64 receivers checked at once, one per lane; the hits taken in order)
-  int nsrc = 0;
-  int sx[kAdjFrameSrc];
-  T sg[kAdjFrameSrc];
-#pragma unroll
-  for (int q = 0; q < kAdjFrameSrc; ++q) {
-    sx[q] = 0;
-    sg[q] = T(0);
-  }
-  int first_extra = p.n_rec;
-  for (int r0 = 0; r0 < p.n_rec && first_extra == p.n_rec; r0 += 64) {
-    const int r = r0 + lane;
-    const int64_t j = (r < p.n_rec) ? p.rec_node[r] : int64_t(-1);
-    const bool hit = j > 0 && j < p.M - 1 && j >= A && j <= B;
-    uint64_t m = __ballot(hit);
-    while (m != 0) {
-      const int b = __builtin_ctzll(m);
-      m &= m - 1;
-      if (nsrc == kAdjFrameSrc) {
-        first_extra = r0 + b;
-        break;
-      }
-      const int x = __builtin_amdgcn_readlane(static_cast<int>(j - base), b);
-      const T* g = p.gtr + static_cast<int64_t>(r0 + b) * p.gtr_ld + (p.n_e - 1);
-      const T gs = (lane < shat) ? g[-lane] : T(0);
-#pragma unroll
-      for (int q = 0; q < kAdjFrameSrc; ++q) {
-        if (q == nsrc) {
-          sx[q] = x;
-          sg[q] = gs;
-        }
-      }
-      ++nsrc;
-    }
-  }
-#pragma unroll
-  for (int e = 0; e < 2; ++e) {
-    cur[e] = in_vgpr(cur[e]);
-    old[e] = in_vgpr(old[e]);
-  }
-#pragma unroll
-  for (int q = 0; q < kAdjFrameSrc; ++q) sg[q] = in_vgpr(sg[q]);
-
+  AdjFrame<T, kAdjFrameSrc> f;
+  adj_frame_load(p.w, p.lo, p.hi, p.rec_node, p.n_rec, p.gtr, p.gtr_ld, p.M, p.n_e, o, w,
+                 shat, lane, f);
   T fl = T(0);
   for (int s = 0; s < shat; ++s) {
-    const T l1 = lane_shift_z<kWaveShr1>(cur[1]);
-    const T r0 = lane_shift_z<kWaveShl1>(cur[0]);
-    const T f = rd_lane((cur[1] - l1) * p.r, kFrameHalf / 2);
-    fl = (lane == s) ? f : fl;
-    if (s == shat - 1) break;
-    T n0 = leap(p.c2, p.k, l1, cur[0], cur[1], old[0]);
-    T n1 = leap(p.c2, p.k, cur[0], cur[1], r0, old[1]);
-    n0 = dir[0] ? T(0) : n0;
-    n1 = dir[1] ? T(0) : n1;
-#pragma unroll
-    for (int q = 0; q < kAdjFrameSrc; ++q) {
-      if (q < nsrc) {
-        const T g = rd_lane(sg[q], s);
-        const int sl = sx[q] >> 1;
-        if (sx[q] & 1)
-          n1 = (lane == sl) ? n1 + g : n1;
-        else
-          n0 = (lane == sl) ? n0 + g : n0;
-      }
-    }
-    if (first_extra < p.n_rec) {
-      const int64_t L = p.n_e - s;  // level just computed
-      for (int r = first_extra; r < p.n_rec; ++r) {
-        const int64_t j = p.rec_node[r];
-        if (j > 0 && j < p.M - 1 && j >= A && j <= B) {
-          const T g = p.gtr[static_cast<int64_t>(r) * p.gtr_ld + (L - 1)];
-          const int x = static_cast<int>(j - base);
-          if (x & 1)
-            n1 = (lane == (x >> 1)) ? n1 + g : n1;
-          else
-            n0 = (lane == (x >> 1)) ? n0 + g : n0;
-        }
-      }
-    }
-    old[0] = cur[0];
-    old[1] = cur[1];
-    cur[0] = n0;
-    cur[1] = n1;
+    const T F = adj_frame_step(f, p.rec_node, p.n_rec, p.gtr, p.gtr_ld, p.M, p.n_e, p.c2,
+                               p.k, p.r, s, lane, s < shat - 1);
+    fl = (lane == s) ? F : fl;
   }
   if (lane < shat) p.flux[static_cast<int64_t>(2 * i + side) * p.ld + lane] = fl;
 }
@@ -238,369 +91,6 @@ __global__ __launch_bounds__(64) void k_adj_predict_lds(const AdjPredictArgs<T> 
   }
 }
 
-// ---------------------------------------------------------------------------
-// Adjoint update.  Per lane MPT consecutive nodes of four register arrays:
-// W^{L+1}, W^{L+2} (adjoint) and U^{L-1}, U^L (forward, rebuilt backward).
-// One step: exchange lane-end values (DPP inside a wave, LDS across waves),
-// W^L by the leapfrog (+ sources, general tiles), the dJ/dlam terms of the
-// stored interior nodes, then U^{L-2} by the reversed leapfrog.
-// ---------------------------------------------------------------------------
-template <typename T, int NT, int MPT>
-struct AdjCtx {
-  T (*edge)[4][NT / 64];
-  const T* sRw;
-  const T* sLw;
-  const T* sRu;
-  const T* sLu;
-  const T* sAu;
-  const T* sBu;
-  int64_t base;
-  int dl, d0, dM, d1, dM2;
-  int sb, se, lane, wv, lmode, rmode;
-  uint32_t cnt;  // bit e: element e is stored and interior (enters dJ/dlam)
-  bool gen, wr_fa, wr_fb;
-  RecSlots rs;          // the tile's first sources (GEN, SRC)
-  const T (*sg)[kMaxSpan];  // their dJ/dtrace samples of this span, by step
-  // SRC, all wave-uniform: the slot sources' wave, lane and element, and
-  // those of nodes 1 and M-2 (index 0 / 1; wave -1: not in this tile)
-  int swv[kRecSlots], slane[kRecSlots], selem[kRecSlots];
-  int gwv[2], glane[2], gelem[2];
-};
-
-// W (or a reversed U) one level: old <- leap(cur) with the general tile's
-// treatments (ghost at element dl, Dirichlet value at d0 / dM).
-template <typename T, int MPT, bool GEN>
-__device__ __forceinline__ void adj_chunk(const T (&cur)[MPT], T (&old)[MPT], T L,
-                                          T R, T c2, T k, int dl, int d0, int dM,
-                                          T ghost, T pin0, T pinM) {
-#pragma unroll
-  for (int e = 0; e < MPT; ++e) {
-    T ul = (e == 0) ? L : cur[e - 1];
-    const T ur = (e == MPT - 1) ? R : cur[e + 1];
-    if (GEN) ul = (e == dl) ? ghost : ul;
-    T v = leap(c2, k, ul, cur[e], ur, old[e]);
-    if (GEN) {
-      v = (e == d0) ? pin0 : v;
-      v = (e == dM) ? pinM : v;
-    }
-    old[e] = v;
-  }
-}
-
-// dJ/dlam terms W^L_j (U_{j-1} + U_{j+1} - 2 U_j) of the counted elements,
-// accumulated in double; then (if rev) U^{L-2} into uold.
-template <typename T, int MPT, bool GEN>
-__device__ __forceinline__ void lap_and_reverse(const T (&wn)[MPT], const T (&ucur)[MPT],
-                                                T (&uold)[MPT], T L, T R, T c2, T k,
-                                                int dl, int d0, int dM, T ghost, T pin0,
-                                                T pinM, uint32_t cnt, bool rev,
-                                                double& acc) {
-#pragma unroll
-  for (int e = 0; e < MPT; ++e) {
-    T ul = (e == 0) ? L : ucur[e - 1];
-    const T ur = (e == MPT - 1) ? R : ucur[e + 1];
-    if (GEN) ul = (e == dl) ? ghost : ul;
-    const T s = ul + ur;
-    const T lap = s - T(2) * ucur[e];
-    const T lapm = ((cnt >> e) & 1u) ? lap : T(0);
-    acc = __builtin_fma(static_cast<double>(wn[e]), static_cast<double>(lapm), acc);
-    if (rev) {
-      T v = fma_(c2, s, fma_(k, ucur[e], -uold[e]));
-      if (GEN) {
-        v = (e == d0) ? pin0 : v;
-        v = (e == dM) ? pinM : v;
-      }
-      uold[e] = v;
-    }
-  }
-}
-
-// GEN: general tiles (per-element treatments at the window's own ends).
-// SRC: plain tiles holding sources or storing nodes 1 / M-2.  Both inject
-// the sources and write dJ/df; neither: the plain step.
-template <typename T, int NT, int MPT, bool GEN, bool SRC>
-__device__ __forceinline__ void adj_step(const AdjUpdateArgs<T>& p,
-                                         const AdjCtx<T, NT, MPT>& c,
-                                         const T (&wc)[MPT], T (&wp)[MPT],
-                                         const T (&uc)[MPT], T (&up)[MPT], T (&gf)[2],
-                                         int tau, int S, double& acc) {
-  constexpr int NW = NT / 64;
-  const int par = tau & 1;
-  const int64_t L = p.n_e - tau;  // adjoint level computed now
-  const int mi = S - 1 - tau;     // sample of the forward level m = L-1
-  T Lw = lane_shift<kWaveShr1>(wc[MPT - 1]);
-  T Rw = lane_shift<kWaveShl1>(wc[0]);
-  T Lu = lane_shift<kWaveShr1>(uc[MPT - 1]);
-  T Ru = lane_shift<kWaveShl1>(uc[0]);
-  if constexpr (NW > 1) {
-    if (c.lane == 63) {
-      c.edge[par][1][c.wv] = wc[MPT - 1];
-      c.edge[par][3][c.wv] = uc[MPT - 1];
-    }
-    if (c.lane == 0) {
-      c.edge[par][0][c.wv] = wc[0];
-      c.edge[par][2][c.wv] = uc[0];
-    }
-    __syncthreads();
-  }
-  if (c.lane == 0) {
-    if (c.wv > 0) {
-      Lw = c.edge[par][1][c.wv - 1];
-      Lu = c.edge[par][3][c.wv - 1];
-    } else {
-      Lw = end_value(c.lmode, fma_(-p.q, c.sLw[tau], wc[1]), T(0));
-      Lu = end_value(c.lmode, fma_(-p.q, c.sLu[mi], uc[1]), c.sAu[mi]);
-    }
-  }
-  if (c.lane == 63) {
-    if (c.wv < NW - 1) {
-      Rw = c.edge[par][0][c.wv + 1];
-      Ru = c.edge[par][2][c.wv + 1];
-    } else {
-      Rw = end_value(c.rmode, fma_(p.q, c.sRw[tau], wc[MPT - 2]), T(0));
-      Ru = end_value(c.rmode, fma_(p.q, c.sRu[mi], uc[MPT - 2]), c.sBu[mi]);
-    }
-  }
-  // dJ/df at level L from W^{L+1} next to the Dirichlet nodes
-  if (GEN) {
-    if (c.wr_fa && c.d1 >= 0 && c.d1 < MPT) p.grad_fa[L] = p.c2 * pick<T, MPT>(wc, c.d1);
-    if (c.wr_fb && c.dM2 >= 0 && c.dM2 < MPT) p.grad_fb[L] = p.c2 * pick<T, MPT>(wc, c.dM2);
-  } else if (SRC) {  // into lane tau of gf, stored after the loop
-#pragma unroll
-    for (int g = 0; g < 2; ++g) {
-      if (c.gwv[g] == c.wv) {
-        const T x = rd_lane(elem_at(wc, c.gelem[g]), c.glane[g]);
-        gf[g] = wr_lane(p.c2 * x, tau, gf[g], c.lane);
-      }
-    }
-  }
-  const bool rev = tau < S - 1;
-  if (GEN && c.gen) {
-    const int rn = c.dl + 1;
-    const T rw = (rn == MPT) ? Rw : pick<T, MPT>(wc, rn);
-    const T gw = fma_(-p.q, c.sLw[tau], rw);
-    adj_chunk<T, MPT, true>(wc, wp, Lw, Rw, p.c2, p.k, c.dl, c.d0, c.dM, gw, T(0), T(0));
-  } else {
-    adj_chunk<T, MPT, false>(wc, wp, Lw, Rw, p.c2, p.k, 0, 0, 0, T(0), T(0), T(0));
-  }
-  if (GEN || SRC) {
-    // receiver sources in list order: the slots (samples staged in LDS),
-    // then any further ones from memory
-    auto inject = [&](int64_t node, T g) {
-      const int64_t d = node - c.base;
-      if (d >= 0 && d < MPT) {
-#pragma unroll
-        for (int e = 0; e < MPT; ++e) wp[e] = (d == e) ? wp[e] + g : wp[e];
-      }
-    };
-#pragma unroll
-    for (int q = 0; q < kRecSlots; ++q) {
-      if (GEN) {
-        if (q < c.rs.n) inject(c.rs.node[q], c.sg[q][tau]);
-      } else if (q < c.rs.n && c.swv[q] == c.wv) {
-        add_at(wp, c.selem[q], c.sg[q][tau], c.lane == c.slane[q]);
-      }
-    }
-    for (int r = c.sb + kRecSlots; r < c.se; ++r)
-      inject(p.src_node[r], p.gtr[static_cast<int64_t>(p.src_id[r]) * p.gtr_ld + (L - 1)]);
-  }
-  if (GEN && c.gen) {
-    const int rn = c.dl + 1;
-    const T ru = (rn == MPT) ? Ru : pick<T, MPT>(uc, rn);
-    const T gu = fma_(-p.q, c.sLu[mi], ru);
-    const T p0 = rev ? c.sAu[mi - 1] : T(0);
-    const T pM = rev ? c.sBu[mi - 1] : T(0);
-    lap_and_reverse<T, MPT, true>(wp, uc, up, Lu, Ru, p.c2, p.k, c.dl, c.d0, c.dM, gu, p0,
-                                  pM, c.cnt, rev, acc);
-  } else {
-    lap_and_reverse<T, MPT, false>(wp, uc, up, Lu, Ru, p.c2, p.k, 0, 0, 0, T(0), T(0),
-                                   T(0), c.cnt, rev, acc);
-  }
-}
-
-// The span's S steps; returns tau (tau < S: the last step left W^{n_k+1}
-// in wp, else in wc).
-template <typename T, int NT, int MPT, bool GEN, bool SRC>
-__device__ __forceinline__ int adj_run(const AdjUpdateArgs<T>& p, const AdjCtx<T, NT, MPT>& c,
-                                       T (&wc)[MPT], T (&wp)[MPT], T (&uc)[MPT],
-                                       T (&up)[MPT], int S, double& acc) {
-  T gf[2] = {T(0), T(0)};
-  int tau = 0;
-  for (; tau + 1 < S; tau += 2) {
-    adj_step<T, NT, MPT, GEN, SRC>(p, c, wc, wp, uc, up, gf, tau, S, acc);
-    adj_step<T, NT, MPT, GEN, SRC>(p, c, wp, wc, up, uc, gf, tau + 1, S, acc);
-  }
-  if (tau < S) adj_step<T, NT, MPT, GEN, SRC>(p, c, wc, wp, uc, up, gf, tau, S, acc);
-  if (SRC && c.lane < S) {  // dJ/df of levels n_e - lane
-    if (c.gwv[0] == c.wv) p.grad_fa[p.n_e - c.lane] = gf[0];
-    if (c.gwv[1] == c.wv) p.grad_fb[p.n_e - c.lane] = gf[1];
-  }
-  return tau;
-}
-
-// GEN: general tiles.  MIX: every other tile; those holding sources or
-// nodes 1 / M-2 take the SRC step, the rest the plain one (a uniform branch
-// per work-group).
-template <typename T, int NT, int MPT, bool GEN, bool MIX>
-__global__ __launch_bounds__(NT) void k_adj_update(const AdjUpdateArgs<T> p0) {
-  const AdjUpdateArgs<T> p = batch_problem(p0);
-  constexpr int NW = NT / 64;
-  constexpr int TM = NT * MPT;
-  constexpr int TMP = TM + (TM >> 5) + 1;
-  __shared__ T st[TMP];
-  __shared__ T sRw[kMaxSpan], sLw[kMaxSpan], sRu[kMaxSpan], sLu[kMaxSpan];
-  __shared__ T sAu[kMaxSpan], sBu[kMaxSpan];
-  __shared__ T edge[2][4][NW];
-  __shared__ double red[NW];
-  __shared__ T sg[(GEN || MIX) ? kRecSlots : 1][kMaxSpan];
-
-  const int tid = threadIdx.x;
-  const int slot = xcd_tile(blockIdx.x, gridDim.x);
-  const int tix = p.tile_idx[slot];
-  const Tile tl = p.tiles[tix];
-  int S = p.span < kMaxSpan ? p.span : kMaxSpan;
-  if (S <= 0) return;
-  const int64_t M = p.M;
-
-  for (int s = tid; s < S; s += NT) {
-    const int64_t rr = static_cast<int64_t>(2 * tl.fr + 1) * p.ld + s;
-    const int64_t rl = static_cast<int64_t>(2 * tl.fl + 0) * p.ld + s;
-    sRw[s] = (tl.fr >= 0) ? p.afl[rr] : T(0);
-    sLw[s] = (tl.fl >= 0) ? p.afl[rl] : T(0);
-    sRu[s] = (tl.fr >= 0) ? p.ffl[rr] : T(0);
-    sLu[s] = (tl.fl >= 0) ? p.ffl[rl] : T(0);
-    sAu[s] = (s == 0) ? p.u_beg[M] : p.fa[p.n_k + s];
-    sBu[s] = (s == 0) ? p.u_beg[2 * M - 1] : p.fb[p.n_k + s];
-  }
-
-  const bool inside = tl.a >= 0 && tl.a + TM <= M;
-  T wc[MPT], wp[MPT], uc[MPT], up[MPT];
-  {
-    T t[MPT];
-    load_level<T, NT, MPT>(p.w_in + M, tl.a, M, inside, t);
-    transpose_in<T, NT, MPT>(t, st, wc);  // W^{n_e+1}
-    load_level<T, NT, MPT>(p.w_in, tl.a, M, inside, t);
-    transpose_in<T, NT, MPT>(t, st, wp);  // W^{n_e+2}
-    load_level<T, NT, MPT>(p.u_end, tl.a, M, inside, t);
-    transpose_in<T, NT, MPT>(t, st, uc);  // U^{n_e-1}
-    load_level<T, NT, MPT>(p.u_end + M, tl.a, M, inside, t);
-    transpose_in<T, NT, MPT>(t, st, up);  // U^{n_e}
-  }
-
-  AdjCtx<T, NT, MPT> c;
-  c.edge = edge;
-  c.sRw = sRw;
-  c.sLw = sLw;
-  c.sRu = sRu;
-  c.sLu = sLu;
-  c.sAu = sAu;
-  c.sBu = sBu;
-  c.base = tl.a + static_cast<int64_t>(tid) * MPT;
-  c.lane = tid & 63;
-  c.wv = tid >> 6;
-  c.lmode = tl.lmode;
-  c.rmode = tl.rmode;
-  auto rel = [](int64_t node, int64_t base) -> int {
-    const int64_t d = node - base;
-    return (d < -2 || d > MPT + 1) ? -1000 : static_cast<int>(d);
-  };
-  c.dl = (tl.lin == kNoNode) ? -1000 : rel(tl.lin, c.base);
-  c.d0 = rel(0, c.base);
-  c.dM = rel(M - 1, c.base);
-  c.d1 = rel(1, c.base);
-  c.dM2 = rel(M - 2, c.base);
-  c.wr_fa = tl.out_lo <= 1 && 1 <= tl.out_hi;
-  c.wr_fb = tl.out_lo <= M - 2 && M - 2 <= tl.out_hi;
-  {
-    const bool mine = (c.dl >= 0 && c.dl < MPT) || (c.d0 >= 0 && c.d0 < MPT) ||
-                      (c.dM >= 0 && c.dM < MPT);
-    c.gen = GEN && (__any(mine) != 0);
-  }
-  c.sb = ((GEN || MIX) && p.src_ptr) ? p.src_ptr[slot] : 0;
-  c.se = ((GEN || MIX) && p.src_ptr) ? p.src_ptr[slot + 1] : 0;
-  c.rs = (GEN || MIX) ? load_slots(p.src_node, p.src_id, c.sb, c.se) : RecSlots{0, {}, {}};
-  c.sg = sg;
-  {
-    // wave-uniform positions: tile offset x lies in thread x / MPT,
-    // element x % MPT
-    auto place = [&](bool use, int64_t node, int& w, int& l, int& e) {
-      const int64_t x = node - tl.a;
-      const bool in = use && x >= 0 && x < TM;
-      const int th = in ? static_cast<int>(x) / MPT : 0;
-      w = __builtin_amdgcn_readfirstlane(in ? th >> 6 : -1);
-      l = __builtin_amdgcn_readfirstlane(th & 63);
-      e = __builtin_amdgcn_readfirstlane(in ? static_cast<int>(x) % MPT : 0);
-    };
-#pragma unroll
-    for (int q = 0; q < kRecSlots; ++q)
-      place(q < c.rs.n, c.rs.node[q], c.swv[q], c.slane[q], c.selem[q]);
-    place(c.wr_fa, 1, c.gwv[0], c.glane[0], c.gelem[0]);
-    place(c.wr_fb, M - 2, c.gwv[1], c.glane[1], c.gelem[1]);
-  }
-  if (GEN || MIX) {
-    // dJ/dtrace of the slot sources at levels n_e-1-tau, tau = 0..S-1
-#pragma unroll
-    for (int q = 0; q < kRecSlots; ++q) {
-      if (q < c.rs.n) {
-        const T* g = p.gtr + static_cast<int64_t>(c.rs.id[q]) * p.gtr_ld + (p.n_e - 1);
-        for (int tau = tid; tau < S; tau += NT) sg[q][tau] = g[-tau];
-      }
-    }
-    __syncthreads();
-  }
-  uint32_t cnt = 0;
-#pragma unroll
-  for (int e = 0; e < MPT; ++e) {
-    const int64_t j = c.base + e;
-    const bool counts = j >= tl.out_lo && j <= tl.out_hi && j > 0 && j < M - 1;
-    cnt |= counts ? (1u << e) : 0u;
-  }
-  c.cnt = cnt;
-
-  double acc = 0.0;
-  int tau;
-  if constexpr (GEN) {
-    tau = adj_run<T, NT, MPT, true, false>(p, c, wc, wp, uc, up, S, acc);
-  } else if constexpr (MIX) {
-    if (c.se > c.sb || c.wr_fa || c.wr_fb)
-      tau = adj_run<T, NT, MPT, false, true>(p, c, wc, wp, uc, up, S, acc);
-    else
-      tau = adj_run<T, NT, MPT, false, false>(p, c, wc, wp, uc, up, S, acc);
-  } else {
-    tau = adj_run<T, NT, MPT, false, false>(p, c, wc, wp, uc, up, S, acc);
-  }
-  const int64_t rlo = tl.out_lo > tl.a ? tl.out_lo : tl.a;
-  const int64_t rhi = tl.out_hi < tl.a + TM - 1 ? tl.out_hi : tl.a + TM - 1;
-  const int xlo = static_cast<int>(rlo - tl.a);
-  const int xhi = static_cast<int>(rhi - tl.a);
-  if (tau < S) {
-    stage_out<T, NT, MPT>(p.w_out, tl.a, xlo, xhi, st, wc);      // W^{n_k+2}
-    stage_out<T, NT, MPT>(p.w_out + M, tl.a, xlo, xhi, st, wp);  // W^{n_k+1}
-  } else {
-    stage_out<T, NT, MPT>(p.w_out, tl.a, xlo, xhi, st, wp);
-    stage_out<T, NT, MPT>(p.w_out + M, tl.a, xlo, xhi, st, wc);
-  }
-  // Dirichlet nodes next to the region: W = 0
-  if (tid == 0 && tl.lmode == kEndDirichlet) {
-    p.w_out[0] = T(0);
-    p.w_out[M] = T(0);
-  }
-  if (tid == NT - 1 && tl.rmode == kEndDirichlet) {
-    p.w_out[M - 1] = T(0);
-    p.w_out[2 * M - 1] = T(0);
-  }
-  // fixed-order reduction of the dJ/dlam partial of this tile
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
-  if (c.lane == 0) red[c.wv] = acc;
-  __syncthreads();
-  if (tid == 0) {
-    double t = 0.0;
-    for (int w = 0; w < NW; ++w) t += red[w];
-    p.lam_part[tix] += t;
-  }
-}
-
 template <typename T>
 __global__ __launch_bounds__(256) void k_adj_finish(T* grad_fa, T* grad_fb, const T* gtr,
                                                    int64_t gtr_ld, const int64_t* rec_node,
@@ -654,21 +144,9 @@ hipError_t launch_adj_predict(const AdjPredictArgs<T>& a, int shmem_nodes, hipSt
 
 template <typename T>
 hipError_t launch_adj_update(const AdjUpdateArgs<T>& a, int threads, int per_thread,
-                             bool general, hipStream_t s) {
-  if (a.n_tiles <= 0) return hipSuccess;
-#define RSWR_ADJ_LAUNCH(NT_, MPT_)                                                  \
-  if (threads == NT_ && per_thread == MPT_) {                                     \
-    if (general)                                                                  \
-      hipLaunchKernelGGL((k_adj_update<T, NT_, MPT_, true, false>),              \
-                         dim3(a.n_tiles, ny(a.ys)), dim3(NT_), 0, s, a);          \
-    else                                                                          \
-      hipLaunchKernelGGL((k_adj_update<T, NT_, MPT_, false, true>),              \
-                         dim3(a.n_tiles, ny(a.ys)), dim3(NT_), 0, s, a);          \
-    return hipGetLastError();                                                     \
-  }
-  RSWR_SHAPES(RSWR_ADJ_LAUNCH)
-#undef RSWR_ADJ_LAUNCH
-  return hipErrorInvalidValue;
+                             bool general, bool fused, hipStream_t s) {
+  return fused ? launch_adj_update_kind<T, true>(a, threads, per_thread, general, s)
+               : launch_adj_update_kind<T, false>(a, threads, per_thread, general, s);
 }
 
 template <typename T>
@@ -695,9 +173,13 @@ template hipError_t launch_adj_predict<float>(const AdjPredictArgs<float>&, int,
 template hipError_t launch_adj_predict<double>(const AdjPredictArgs<double>&, int,
                                                hipStream_t);
 template hipError_t launch_adj_update<float>(const AdjUpdateArgs<float>&, int, int, bool,
-                                             hipStream_t);
+                                             bool, hipStream_t);
 template hipError_t launch_adj_update<double>(const AdjUpdateArgs<double>&, int, int, bool,
-                                              hipStream_t);
+                                              bool, hipStream_t);
+template hipError_t launch_adj_update_kind<float, false>(const AdjUpdateArgs<float>&, int,
+                                                         int, bool, hipStream_t);
+template hipError_t launch_adj_update_kind<double, false>(const AdjUpdateArgs<double>&, int,
+                                                          int, bool, hipStream_t);
 template hipError_t launch_adj_finish<float>(float*, float*, const float*, int64_t,
                                              const int64_t*, int32_t, int64_t, int64_t,
                                              const double*, int32_t, double, double*,
@@ -710,3 +192,4 @@ template hipError_t launch_fill<float>(float*, float, int64_t, hipStream_t);
 template hipError_t launch_fill<double>(double*, double, int64_t, hipStream_t);
 
 }  // namespace rswr
+

@@ -869,7 +869,9 @@ rswr_status_t enqueue_adj_span(const rswr_plan_s* p, const DevTables& d, char* w
   pa.k = T(2.0 - 2.0 * c2);
   pa.r = T(1.0 / (2.0 * p->dx));
   pa.q = T(2.0 * p->dx);
-  RSWR_HIP(rswr::launch_adj_predict<T>(pa, 2 * p->S_max + 1, s));
+  // fused plans: the update tiles carry the W frames of their input ends
+  const bool fused = p->fused;
+  if (!fused) RSWR_HIP(rswr::launch_adj_predict<T>(pa, 2 * p->S_max + 1, s));
   rswr::AdjUpdateArgs<T> ua{};
   ua.w_in = io.w_cur;
   ua.w_out = io.w_nxt;
@@ -897,18 +899,23 @@ rswr_status_t enqueue_adj_span(const rswr_plan_s* p, const DevTables& d, char* w
   ua.src_ptr = reinterpret_cast<const int32_t*>(ws + L.src_ptr);
   ua.src_node = reinterpret_cast<const int64_t*>(ws + L.src_node);
   ua.src_id = reinterpret_cast<const int32_t*>(ws + L.src_id);
+  ua.lo = d.lo;
+  ua.hi = d.hi;
+  ua.rec_all = pa.rec_node;
+  ua.n_rec_all = n_rec;
+  ua.r = pa.r;
   if (al.n_gen > 0) {
     rswr::AdjUpdateArgs<T> g = ua;
     g.tile_idx = reinterpret_cast<const int32_t*>(ws + L.gen_idx);
     g.n_tiles = al.n_gen;
-    RSWR_HIP(rswr::launch_adj_update<T>(g, p->threads, p->per_thread, true, s));
+    RSWR_HIP(rswr::launch_adj_update<T>(g, p->threads, p->per_thread, true, fused, s));
   }
   if (al.n_fast > 0) {
     rswr::AdjUpdateArgs<T> f = ua;
     f.tile_idx = reinterpret_cast<const int32_t*>(ws + L.fast_idx);
     f.n_tiles = al.n_fast;
     f.src_ptr = ua.src_ptr + al.n_gen;
-    RSWR_HIP(rswr::launch_adj_update<T>(f, p->threads, p->per_thread, false, s));
+    RSWR_HIP(rswr::launch_adj_update<T>(f, p->threads, p->per_thread, false, fused, s));
   }
   return RSWR_OK;
 }

@@ -176,10 +176,15 @@ struct AdjUpdateArgs {
   T* grad_fa;           // [n_steps+1]
   T* grad_fb;
   double* lam_part;     // one accumulator per tile (indexed by tile number)
+  // fused update only: window bounds and every receiver's node (receiver
+  // order), for the W frames the tiles carry at their input ends
+  const int64_t* lo;
+  const int64_t* hi;
+  const int64_t* rec_all;
   YStrides ys;          // batch of same-shape problems (every pointer above but the tables)
   int64_t M, n_e, n_k;
-  int32_t n_tiles, span, ld, pad;
-  T c2, k, q;
+  int32_t n_tiles, span, ld, n_rec_all;
+  T c2, k, q, r;
 };
 
 // One problem of a batched launch.  Round r reads st_a (r even) or st_b
@@ -265,9 +270,15 @@ hipError_t launch_fill(T* dst, T v, int64_t n, hipStream_t s);
 template <typename T>
 hipError_t launch_adj_predict(const AdjPredictArgs<T>& a, int shmem_nodes,
                               hipStream_t s);
+// fused: the tiles predict their input ends' W fluxes themselves (plans
+// that run the fused span; afl unused), else afl holds the predict
+// kernel's rows.
 template <typename T>
 hipError_t launch_adj_update(const AdjUpdateArgs<T>& a, int threads,
-                             int per_thread, bool general, hipStream_t s);
+                             int per_thread, bool general, bool fused, hipStream_t s);
+template <typename T, bool FR>
+hipError_t launch_adj_update_kind(const AdjUpdateArgs<T>& a, int threads, int per_thread,
+                                  bool general, hipStream_t s);
 // grad_fa[L] += dJ/dtrace of receivers on node 0 (grad_fb: node M-1), in
 // receiver order, for L = 1..n_steps; grad_lam = 2 lam * sum(lam_part).
 template <typename T>

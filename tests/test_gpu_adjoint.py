@@ -166,3 +166,34 @@ def test_adjoint_full_size_fp64():
     assert np.abs(ra).max() > 0
     assert np.abs(gah - ra).max() <= 1e-11 * np.abs(ra).max()
     assert abs(gl.item() - rl) <= 1e-8 * abs(rl), (gl.item(), rl)
+
+
+@pytest.mark.parametrize("case", range(len(CASES)))
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_fused_adjoint_equals_two_launch(case, dtype):
+    """On plans that run the fused span the adjoint update tiles carry the W
+    frames of their input ends; the plan built with fuse=False runs the
+    separate predict kernel.  Both give the same gradients bit for bit."""
+    M, N, P, tile, n_steps, rec = CASES[case]
+    say("fused-adjoint", CASES[case], dtype)
+    plans = [rs.Plan(M, N, P, tile=tile, dtype=dtype, fuse=f) for f in (True, False)]
+    assert not plans[1].info["fused"]
+    if not plans[0].info["fused"]:
+        pytest.skip("plan does not run the fused span")
+    g = np.random.default_rng(100 + case)
+    fa = g.standard_normal(n_steps + 1)
+    fa[0] = 0.0
+    fb = g.standard_normal(n_steps + 1)
+    fb[0] = 0.0
+    rec = np.asarray(rec, np.int64)
+    w = g.standard_normal((len(rec), n_steps))
+    out = []
+    for plan in plans:
+        _, ck = forward_gpu(plan, fa, fb, n_steps, rec, dtype)
+        ga, gb, gl = rs.rswr_solve_adjoint(plan, ck, dev(fa, dtype), dev(fb, dtype), n_steps,
+                                           rec, dev(w, dtype))
+        torch.cuda.synchronize()
+        out.append((ga.cpu().numpy(), gb.cpu().numpy(), float(gl.item())))
+    assert np.array_equal(out[0][0], out[1][0])
+    assert np.array_equal(out[0][1], out[1][1])
+    assert out[0][2] == out[1][2]
