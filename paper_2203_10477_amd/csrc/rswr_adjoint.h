@@ -82,8 +82,7 @@ inline unsigned ny(const YStrides& y) { return y.ny > 1 ? static_cast<unsigned>(
 // (lane s: level n_e - s), the rest read each step.
 template <typename T, int NS>
 struct AdjFrame {
-  T cur[2], old[2];  // W^{L+1}, W^{L+2}
-  bool dir[2];
+  bool dir[2];  // element e is node 0 or M-1 (W = 0)
   int nsrc, first_extra;
   int64_t A, B, base;
   int sx[NS];
@@ -95,7 +94,8 @@ __device__ __forceinline__ void adj_frame_load(const T* w, const int64_t* lo,
                                                const int64_t* hi, const int64_t* rec_node,
                                                int n_rec, const T* gtr, int64_t gtr_ld,
                                                int64_t M, int64_t n_e, int64_t o, int win,
-                                               int shat, int lane, AdjFrame<T, NS>& f) {
+                                               int shat, int lane, T (&cur)[2], T (&old)[2],
+                                               AdjFrame<T, NS>& f) {
   const int64_t wlo = lo[win], whi = hi[win];
   f.A = (o - shat > wlo) ? o - shat : wlo;
   f.B = (o + shat < whi) ? o + shat : whi;
@@ -105,8 +105,8 @@ __device__ __forceinline__ void adj_frame_load(const T* w, const int64_t* lo,
     const int64_t x = f.base + 2 * lane + e;
     int64_t j = (x < wlo) ? 2 * wlo - x : ((x > whi) ? 2 * whi - x : x);
     j = j < wlo ? wlo : (j > whi ? whi : j);
-    f.cur[e] = w[M + j];
-    f.old[e] = w[j];
+    cur[e] = w[M + j];
+    old[e] = w[j];
     f.dir[e] = (x == 0) || (x == M - 1);
   }
   // sources in [A, B] (interior nodes), in receiver order: frame offset and
@@ -146,40 +146,42 @@ __device__ __forceinline__ void adj_frame_load(const T* w, const int64_t* lo,
   }
 #pragma unroll
   for (int e = 0; e < 2; ++e) {
-    f.cur[e] = in_vgpr(f.cur[e]);
-    f.old[e] = in_vgpr(f.old[e]);
+    cur[e] = in_vgpr(cur[e]);
+    old[e] = in_vgpr(old[e]);
   }
 #pragma unroll
   for (int q = 0; q < NS; ++q) f.sg[q] = in_vgpr(f.sg[q]);
 }
 
-// Step s of the frame: returns the centred flux at o from W^{L+1} (L =
-// n_e - s; wave-uniform); if `adv`, advances the frame to W^L.
+// Step s of the frame (cur = W^{L+1}, old = W^{L+2}, L = n_e - s): returns
+// the centred flux at o (wave-uniform); if `adv`, writes W^L over old.
 template <typename T, int NS>
-__device__ __forceinline__ T adj_frame_step(AdjFrame<T, NS>& f, const int64_t* rec_node,
+__device__ __forceinline__ T adj_frame_step(const T (&cur)[2], T (&old)[2],
+                                            const AdjFrame<T, NS>& f, const int64_t* rec_node,
                                             int n_rec, const T* gtr, int64_t gtr_ld, int64_t M,
                                             int64_t n_e, T c2, T k, T r, int s, int lane,
                                             bool adv) {
-  const T l1 = lane_shift_z<kWaveShr1>(f.cur[1]);
-  const T r0 = lane_shift_z<kWaveShl1>(f.cur[0]);
-  const T F = rd_lane((f.cur[1] - l1) * r, kFrameHalf / 2);
+  const T l1 = lane_shift_z<kWaveShr1>(cur[1]);
+  const T r0 = lane_shift_z<kWaveShl1>(cur[0]);
+  const T F = rd_lane((cur[1] - l1) * r, kFrameHalf / 2);
   if (adv) {
-    T n0 = leap(c2, k, l1, f.cur[0], f.cur[1], f.old[0]);
-    T n1 = leap(c2, k, f.cur[0], f.cur[1], r0, f.old[1]);
+    T n0 = leap(c2, k, l1, cur[0], cur[1], old[0]);
+    T n1 = leap(c2, k, cur[0], cur[1], r0, old[1]);
     n0 = f.dir[0] ? T(0) : n0;
     n1 = f.dir[1] ? T(0) : n1;
+    const int ns = uni(f.nsrc);
 #pragma unroll
     for (int q = 0; q < NS; ++q) {
-      if (q < f.nsrc) {
+      if (q < ns) {
         const T g = rd_lane(f.sg[q], s);
-        const int sl = f.sx[q] >> 1;
-        if (f.sx[q] & 1)
-          n1 = (lane == sl) ? n1 + g : n1;
+        const int x = uni(f.sx[q]);
+        if (x & 1)
+          n1 = (lane == (x >> 1)) ? n1 + g : n1;
         else
-          n0 = (lane == sl) ? n0 + g : n0;
+          n0 = (lane == (x >> 1)) ? n0 + g : n0;
       }
     }
-    if (f.first_extra < n_rec) {
+    if (uni(f.first_extra) < n_rec) {
       const int64_t L = n_e - s;  // level just computed
       for (int r = f.first_extra; r < n_rec; ++r) {
         const int64_t j = rec_node[r];
@@ -193,10 +195,8 @@ __device__ __forceinline__ T adj_frame_step(AdjFrame<T, NS>& f, const int64_t* r
         }
       }
     }
-    f.old[0] = f.cur[0];
-    f.old[1] = f.cur[1];
-    f.cur[0] = n0;
-    f.cur[1] = n1;
+    old[0] = n0;
+    old[1] = n1;
   }
   return F;
 }
@@ -228,6 +228,11 @@ struct AdjCtx {
   // those of nodes 1 and M-2 (index 0 / 1; wave -1: not in this tile)
   int swv[kRecSlots], slane[kRecSlots], selem[kRecSlots];
   int gwv[2], glane[2], gelem[2];
+  // fused update (span <= 64): lane s holds sample s of the forward flux at
+  // the left / right input and of nodes 0 / M-1 (the staged rows, read with
+  // readlane); wvu: the wave index as a scalar
+  T vLu, vRu, vAu, vBu;
+  int wvu;
 };
 
 // W (or a reversed U) one level: old <- leap(cur) with the general tile's
@@ -293,37 +298,73 @@ __device__ __forceinline__ void adj_step(const AdjUpdateArgs<T>& p,
   const int par = tau & 1;
   const int64_t L = p.n_e - tau;  // adjoint level computed now
   const int mi = S - 1 - tau;     // sample of the forward level m = L-1
-  T Lw = lane_shift<kWaveShr1>(wc[MPT - 1]);
-  T Rw = lane_shift<kWaveShl1>(wc[0]);
-  T Lu = lane_shift<kWaveShr1>(uc[MPT - 1]);
-  T Ru = lane_shift<kWaveShl1>(uc[0]);
-  if constexpr (NW > 1) {
-    if (c.lane == 63) {
-      c.edge[par][1][c.wv] = wc[MPT - 1];
-      c.edge[par][3][c.wv] = uc[MPT - 1];
+  T Lw, Rw, Lu, Ru;
+  if constexpr (FR) {
+    // the neighbours of lane 0 and lane 63, computed on every lane (the
+    // branches are wave-uniform) and put in place by the lane shifts
+    if constexpr (NW > 1) {
+      if (c.lane == 63) {
+        c.edge[par][1][c.wvu] = wc[MPT - 1];
+        c.edge[par][3][c.wvu] = uc[MPT - 1];
+      }
+      if (c.lane == 0) {
+        c.edge[par][0][c.wvu] = wc[0];
+        c.edge[par][2][c.wvu] = uc[0];
+      }
+      __syncthreads();
+    }
+    T Lw0, Lu0, Rw0, Ru0;
+    if (NW > 1 && c.wvu > 0) {
+      Lw0 = c.edge[par][1][c.wvu - 1];
+      Lu0 = c.edge[par][3][c.wvu - 1];
+    } else {
+      Lw0 = end_value(c.lmode, fma_(-p.q, fwL, wc[1]), T(0));
+      Lu0 = end_value(c.lmode, fma_(-p.q, rd_lane(c.vLu, mi), uc[1]), rd_lane(c.vAu, mi));
+    }
+    if (NW > 1 && c.wvu < NW - 1) {
+      Rw0 = c.edge[par][0][c.wvu + 1];
+      Ru0 = c.edge[par][2][c.wvu + 1];
+    } else {
+      Rw0 = end_value(c.rmode, fma_(p.q, fwR, wc[MPT - 2]), T(0));
+      Ru0 = end_value(c.rmode, fma_(p.q, rd_lane(c.vRu, mi), uc[MPT - 2]), rd_lane(c.vBu, mi));
+    }
+    Lw = lane_shift_old<kWaveShr1>(Lw0, wc[MPT - 1]);
+    Rw = lane_shift_old<kWaveShl1>(Rw0, wc[0]);
+    Lu = lane_shift_old<kWaveShr1>(Lu0, uc[MPT - 1]);
+    Ru = lane_shift_old<kWaveShl1>(Ru0, uc[0]);
+  } else {
+    Lw = lane_shift<kWaveShr1>(wc[MPT - 1]);
+    Rw = lane_shift<kWaveShl1>(wc[0]);
+    Lu = lane_shift<kWaveShr1>(uc[MPT - 1]);
+    Ru = lane_shift<kWaveShl1>(uc[0]);
+    if constexpr (NW > 1) {
+      if (c.lane == 63) {
+        c.edge[par][1][c.wv] = wc[MPT - 1];
+        c.edge[par][3][c.wv] = uc[MPT - 1];
+      }
+      if (c.lane == 0) {
+        c.edge[par][0][c.wv] = wc[0];
+        c.edge[par][2][c.wv] = uc[0];
+      }
+      __syncthreads();
     }
     if (c.lane == 0) {
-      c.edge[par][0][c.wv] = wc[0];
-      c.edge[par][2][c.wv] = uc[0];
+      if (c.wv > 0) {
+        Lw = c.edge[par][1][c.wv - 1];
+        Lu = c.edge[par][3][c.wv - 1];
+      } else {
+        Lw = end_value(c.lmode, fma_(-p.q, c.sLw[tau], wc[1]), T(0));
+        Lu = end_value(c.lmode, fma_(-p.q, c.sLu[mi], uc[1]), c.sAu[mi]);
+      }
     }
-    __syncthreads();
-  }
-  if (c.lane == 0) {
-    if (c.wv > 0) {
-      Lw = c.edge[par][1][c.wv - 1];
-      Lu = c.edge[par][3][c.wv - 1];
-    } else {
-      Lw = end_value(c.lmode, fma_(-p.q, FR ? fwL : c.sLw[tau], wc[1]), T(0));
-      Lu = end_value(c.lmode, fma_(-p.q, c.sLu[mi], uc[1]), c.sAu[mi]);
-    }
-  }
-  if (c.lane == 63) {
-    if (c.wv < NW - 1) {
-      Rw = c.edge[par][0][c.wv + 1];
-      Ru = c.edge[par][2][c.wv + 1];
-    } else {
-      Rw = end_value(c.rmode, fma_(p.q, FR ? fwR : c.sRw[tau], wc[MPT - 2]), T(0));
-      Ru = end_value(c.rmode, fma_(p.q, c.sRu[mi], uc[MPT - 2]), c.sBu[mi]);
+    if (c.lane == 63) {
+      if (c.wv < NW - 1) {
+        Rw = c.edge[par][0][c.wv + 1];
+        Ru = c.edge[par][2][c.wv + 1];
+      } else {
+        Rw = end_value(c.rmode, fma_(p.q, c.sRw[tau], wc[MPT - 2]), T(0));
+        Ru = end_value(c.rmode, fma_(p.q, c.sRu[mi], uc[MPT - 2]), c.sBu[mi]);
+      }
     }
   }
   // dJ/df at level L from W^{L+1} next to the Dirichlet nodes
@@ -399,29 +440,31 @@ __device__ __forceinline__ int adj_run(const AdjUpdateArgs<T>& p, const AdjCtx<T
       ((c.wv == NW - 1 && tl.rmode == kEndGhost) ? 2 : 0));
   const bool hl = FR && (uni(ends) & 1) != 0;
   const bool hr = FR && (uni(ends) & 2) != 0;
+  T flc[2], flo[2], frc[2], fro[2];  // the frames' two levels, swapped each step
   AdjFrame<T, kAdjFuseSrc> fa, fb;
   if (hl)
     adj_frame_load(p.w_in, p.lo, p.hi, p.rec_all, p.n_rec_all, p.gtr, p.gtr_ld, p.M, p.n_e,
-                   p.lo[tl.fl + 1], tl.fl, S, c.lane, fa);
+                   p.lo[tl.fl + 1], tl.fl, S, c.lane, flc, flo, fa);
   if (hr)
     adj_frame_load(p.w_in, p.lo, p.hi, p.rec_all, p.n_rec_all, p.gtr, p.gtr_ld, p.M, p.n_e,
-                   p.hi[tl.fr], tl.fr + 1, S, c.lane, fb);
-  auto step = [&](T (&w0)[MPT], T (&w1)[MPT], T (&u0)[MPT], T (&u1)[MPT], int t) {
+                   p.hi[tl.fr], tl.fr + 1, S, c.lane, frc, fro, fb);
+  auto step = [&](T (&w0)[MPT], T (&w1)[MPT], T (&u0)[MPT], T (&u1)[MPT], T (&lc)[2],
+                  T (&lo)[2], T (&rc)[2], T (&ro)[2], int t) {
     T fwL = T(0), fwR = T(0);
     if (hl)
-      fwL = adj_frame_step(fa, p.rec_all, p.n_rec_all, p.gtr, p.gtr_ld, p.M, p.n_e, p.c2,
-                           p.k, p.r, t, c.lane, true);
+      fwL = adj_frame_step(lc, lo, fa, p.rec_all, p.n_rec_all, p.gtr, p.gtr_ld, p.M, p.n_e,
+                           p.c2, p.k, p.r, t, c.lane, true);
     if (hr)
-      fwR = adj_frame_step(fb, p.rec_all, p.n_rec_all, p.gtr, p.gtr_ld, p.M, p.n_e, p.c2,
-                           p.k, p.r, t, c.lane, true);
+      fwR = adj_frame_step(rc, ro, fb, p.rec_all, p.n_rec_all, p.gtr, p.gtr_ld, p.M, p.n_e,
+                           p.c2, p.k, p.r, t, c.lane, true);
     adj_step<T, NT, MPT, GEN, SRC, FR>(p, c, w0, w1, u0, u1, gf, t, S, acc, fwL, fwR);
   };
   int tau = 0;
   for (; tau + 1 < S; tau += 2) {
-    step(wc, wp, uc, up, tau);
-    step(wp, wc, up, uc, tau + 1);
+    step(wc, wp, uc, up, flc, flo, frc, fro, tau);
+    step(wp, wc, up, uc, flo, flc, fro, frc, tau + 1);
   }
-  if (tau < S) step(wc, wp, uc, up, tau);
+  if (tau < S) step(wc, wp, uc, up, flc, flo, frc, fro, tau);
   if (SRC && c.lane < S) {  // dJ/df of levels n_e - lane
     if (c.gwv[0] == c.wv) p.grad_fa[p.n_e - c.lane] = gf[0];
     if (c.gwv[1] == c.wv) p.grad_fb[p.n_e - c.lane] = gf[1];
@@ -490,8 +533,17 @@ __global__ __launch_bounds__(NT) void k_adj_update(const AdjUpdateArgs<T> p0) {
   c.base = tl.a + static_cast<int64_t>(tid) * MPT;
   c.lane = tid & 63;
   c.wv = tid >> 6;
-  c.lmode = tl.lmode;
-  c.rmode = tl.rmode;
+  c.wvu = __builtin_amdgcn_readfirstlane(tid >> 6);
+  c.lmode = __builtin_amdgcn_readfirstlane(tl.lmode);
+  c.rmode = __builtin_amdgcn_readfirstlane(tl.rmode);
+  c.vLu = c.vRu = c.vAu = c.vBu = T(0);
+  if (FR && c.lane < S) {
+    const int s = c.lane;
+    if (tl.fl >= 0) c.vLu = p.ffl[static_cast<int64_t>(2 * tl.fl + 0) * p.ld + s];
+    if (tl.fr >= 0) c.vRu = p.ffl[static_cast<int64_t>(2 * tl.fr + 1) * p.ld + s];
+    c.vAu = (s == 0) ? p.u_beg[M] : p.fa[p.n_k + s];
+    c.vBu = (s == 0) ? p.u_beg[2 * M - 1] : p.fb[p.n_k + s];
+  }
   auto rel = [](int64_t node, int64_t base) -> int {
     const int64_t d = node - base;
     return (d < -2 || d > MPT + 1) ? -1000 : static_cast<int>(d);

@@ -20,14 +20,20 @@ __global__ __launch_bounds__(64) void k_adj_predict_frame(const AdjPredictArgs<T
   const int64_t o = (side == 0) ? p.lo[i + 1] : p.hi[i];
   const int shat = p.shat;
   const int lane = threadIdx.x;
+  T a[2], b[2];
   AdjFrame<T, kAdjFrameSrc> f;
   adj_frame_load(p.w, p.lo, p.hi, p.rec_node, p.n_rec, p.gtr, p.gtr_ld, p.M, p.n_e, o, w,
-                 shat, lane, f);
+                 shat, lane, a, b, f);
   T fl = T(0);
-  for (int s = 0; s < shat; ++s) {
-    const T F = adj_frame_step(f, p.rec_node, p.n_rec, p.gtr, p.gtr_ld, p.M, p.n_e, p.c2,
-                               p.k, p.r, s, lane, s < shat - 1);
+  for (int s = 0; s < shat; s += 2) {
+    T F = adj_frame_step(a, b, f, p.rec_node, p.n_rec, p.gtr, p.gtr_ld, p.M, p.n_e, p.c2,
+                         p.k, p.r, s, lane, s < shat - 1);
     fl = (lane == s) ? F : fl;
+    if (s + 1 < shat) {
+      F = adj_frame_step(b, a, f, p.rec_node, p.n_rec, p.gtr, p.gtr_ld, p.M, p.n_e, p.c2, p.k,
+                         p.r, s + 1, lane, s + 1 < shat - 1);
+      fl = (lane == s + 1) ? F : fl;
+    }
   }
   if (lane < shat) p.flux[static_cast<int64_t>(2 * i + side) * p.ld + lane] = fl;
 }
