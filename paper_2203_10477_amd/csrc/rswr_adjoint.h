@@ -318,15 +318,29 @@ __device__ __forceinline__ void adj_step(const AdjUpdateArgs<T>& p,
       Lw0 = c.edge[par][1][c.wvu - 1];
       Lu0 = c.edge[par][3][c.wvu - 1];
     } else {
-      Lw0 = end_value(c.lmode, fma_(-p.q, fwL, wc[1]), T(0));
-      Lu0 = end_value(c.lmode, fma_(-p.q, rd_lane(c.vLu, mi), uc[1]), rd_lane(c.vAu, mi));
+      const int m = uni(c.lmode);
+      Lw0 = T(0);
+      Lu0 = T(0);
+      if (m == kEndGhost) {
+        Lw0 = fma_(-p.q, fwL, wc[1]);
+        Lu0 = fma_(-p.q, rd_lane(c.vLu, mi), uc[1]);
+      } else if (m == kEndDirichlet) {
+        Lu0 = rd_lane(c.vAu, mi);
+      }
     }
     if (NW > 1 && c.wvu < NW - 1) {
       Rw0 = c.edge[par][0][c.wvu + 1];
       Ru0 = c.edge[par][2][c.wvu + 1];
     } else {
-      Rw0 = end_value(c.rmode, fma_(p.q, fwR, wc[MPT - 2]), T(0));
-      Ru0 = end_value(c.rmode, fma_(p.q, rd_lane(c.vRu, mi), uc[MPT - 2]), rd_lane(c.vBu, mi));
+      const int m = uni(c.rmode);
+      Rw0 = T(0);
+      Ru0 = T(0);
+      if (m == kEndGhost) {
+        Rw0 = fma_(p.q, fwR, wc[MPT - 2]);
+        Ru0 = fma_(p.q, rd_lane(c.vRu, mi), uc[MPT - 2]);
+      } else if (m == kEndDirichlet) {
+        Ru0 = rd_lane(c.vBu, mi);
+      }
     }
     Lw = lane_shift_old<kWaveShr1>(Lw0, wc[MPT - 1]);
     Rw = lane_shift_old<kWaveShl1>(Rw0, wc[0]);
@@ -665,6 +679,27 @@ hipError_t launch_adj_update_kind(const AdjUpdateArgs<T>& a, int threads, int pe
   RSWR_SHAPES(RSWR_ADJ_LAUNCH)
 #undef RSWR_ADJ_LAUNCH
   return hipErrorInvalidValue;
+}
+
+// Whether both fused update kernels of a shape keep their state in
+// registers (no scratch): the fused adjoint runs only there.
+template <typename T>
+bool adj_update_fused_fits(int threads, int per_thread) {
+#define RSWR_ADJ_FIT(NT_, MPT_)                                                          \
+  if (threads == NT_ && per_thread == MPT_) {                                          \
+    hipFuncAttributes g{}, f{};                                                        \
+    if (hipFuncGetAttributes(&g, reinterpret_cast<const void*>(                        \
+                                     k_adj_update<T, NT_, MPT_, true, false, true>)) !=  \
+            hipSuccess ||                                                              \
+        hipFuncGetAttributes(&f, reinterpret_cast<const void*>(                        \
+                                     k_adj_update<T, NT_, MPT_, false, true, true>)) !=  \
+            hipSuccess)                                                                \
+      return false;                                                                    \
+    return g.localSizeBytes == 0 && f.localSizeBytes == 0;                             \
+  }
+  RSWR_SHAPES(RSWR_ADJ_FIT)
+#undef RSWR_ADJ_FIT
+  return false;
 }
 
 }  // namespace rswr

@@ -6,5 +6,6 @@ namespace rswr {
 
 template hipError_t launch_adj_update_kind<float, true>(const AdjUpdateArgs<float>&, int, int,
                                                         bool, hipStream_t);
+template bool adj_update_fused_fits<float>(int, int);
 
 }  // namespace rswr

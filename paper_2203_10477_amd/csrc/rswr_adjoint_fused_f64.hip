@@ -6,5 +6,6 @@ namespace rswr {
 
 template hipError_t launch_adj_update_kind<double, true>(const AdjUpdateArgs<double>&, int, int,
                                                          bool, hipStream_t);
+template bool adj_update_fused_fits<double>(int, int);
 
 }  // namespace rswr

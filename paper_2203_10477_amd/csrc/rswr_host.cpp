@@ -781,7 +781,15 @@ AdjWs adj_ws_layout(const rswr_plan_s& p, int32_t n_rec) {
 
 struct AdjLists {
   int32_t n_gen = 0, n_fast = 0;
+  // the update tiles carry the W frames of their input ends (fused plans
+  // whose fused update kernels fit in registers); else a predict launch
+  bool fused = false;
 };
+
+bool adj_fused_fits(const rswr_plan_s& p) {
+  return p.dtype == RSWR_F64 ? rswr::adj_update_fused_fits<double>(p.threads, p.per_thread)
+                             : rswr::adj_update_fused_fits<float>(p.threads, p.per_thread);
+}
 
 // Device tables of an adjoint run, shared by every problem of a batch: the
 // general and plain tile lists and the receiver sources as one CSR over both
@@ -869,8 +877,7 @@ rswr_status_t enqueue_adj_span(const rswr_plan_s* p, const DevTables& d, char* w
   pa.k = T(2.0 - 2.0 * c2);
   pa.r = T(1.0 / (2.0 * p->dx));
   pa.q = T(2.0 * p->dx);
-  // fused plans: the update tiles carry the W frames of their input ends
-  const bool fused = p->fused;
+  const bool fused = al.fused;
   if (!fused) RSWR_HIP(rswr::launch_adj_predict<T>(pa, 2 * p->S_max + 1, s));
   rswr::AdjUpdateArgs<T> ua{};
   ua.w_in = io.w_cur;
@@ -1628,6 +1635,7 @@ rswr_status_t rswr_solve_adjoint(rswr_plan_t p, const void* checkpoints, const v
   char* ws = static_cast<char*>(workspace);
   AdjLists al;
   if ((st = upload_adj_lists(*p, rec_idx, n_rec, ws, L, s, &al)) != RSWR_OK) return st;
+  al.fused = p->fused && adj_fused_fits(*p);
 
   auto enqueue = [&](hipStream_t q) {
     return p->dtype == RSWR_F64
@@ -1692,6 +1700,7 @@ rswr_status_t rswr_solve_adjoint_batch(rswr_plan_t p, int32_t n_prob, const void
   char* ws = static_cast<char*>(workspace);
   AdjLists al;
   if ((st = upload_adj_lists(*p, rec_idx, n_rec, ws, L, s, &al)) != RSWR_OK) return st;
+  al.fused = p->fused && adj_fused_fits(*p);
   auto enqueue = [&](hipStream_t q) {
     return p->dtype == RSWR_F64
                ? enqueue_adjoint_batch<double>(p, *d, n_prob, f_a, f_b, src_ld, n_steps, al,

@@ -276,6 +276,10 @@ hipError_t launch_adj_predict(const AdjPredictArgs<T>& a, int shmem_nodes,
 template <typename T>
 hipError_t launch_adj_update(const AdjUpdateArgs<T>& a, int threads,
                              int per_thread, bool general, bool fused, hipStream_t s);
+// the fused update kernels of this shape run without scratch (the current
+// device's code objects)
+template <typename T>
+bool adj_update_fused_fits(int threads, int per_thread);
 template <typename T, bool FR>
 hipError_t launch_adj_update_kind(const AdjUpdateArgs<T>& a, int threads, int per_thread,
                                   bool general, hipStream_t s);
