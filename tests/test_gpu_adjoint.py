@@ -41,6 +41,9 @@ CASES = [
     (301, 20, 20, (64, 8), 250, [2, 100, 200, 298]),   # general tiles
     (6000, 3, 40, (64, 8), 400, [10, 1990, 2000, 2010, 5000]),
     (20001, 16, 64, (256, 16), 300, [5, 9000, 9001, 9001, 19990]),  # repeated receiver
+    # four receivers (one repeated) in the frame around node 510, two beyond
+    # the registers the fused update gives a frame's sources
+    (1001, 2, 20, None, 600, [3, 489, 500, 505, 505, 510, 990]),
     # FP64 at this shape: the fused update would need scratch, so the fused
     # plan's adjoint keeps the predict launch
     (40001, 8, 64, (512, 12), 200, [7, 5000, 5001, 20000, 39999]),
