@@ -1530,10 +1530,23 @@ rswr_status_t rswr_solve(rswr_plan_t p, void* state, const void* f_a, const void
     // covers both lists.
     // a fused-path tile records at most kRecSlots receivers per launched
     // copy: a tile holding more is listed once per group (the copies store
-    // the same state bits)
+    // the same state bits).  On a grid that leaves SIMDs idle (at most two
+    // waves per SIMD even with one copy per receiver; 4 SIMDs per CU) each
+    // copy records one receiver: there the recording tiles set the span's
+    // time, and their copies run side by side.
+    size_t rg = rswr::kRecSlots;
+    if (p->fused) {
+      int dev = 0, cus = 0;
+      if (hipGetDevice(&dev) == hipSuccess &&
+          hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) ==
+              hipSuccess) {
+        const int64_t waves = (int64_t(n_all) + n_rec) * (p->threads / 64);
+        if (cus > 0 && waves <= 2 * 4 * int64_t(cus)) rg = 1;
+      }
+    }
     auto add = [&](std::vector<int32_t>& list, int32_t t) {
       const size_t n = per[t].size();
-      const size_t g = p->fused ? size_t(rswr::kRecSlots) : std::max<size_t>(n, 1);
+      const size_t g = p->fused ? rg : std::max<size_t>(n, 1);
       for (size_t b = 0; b == 0 || b < n; b += g) {
         list.push_back(t);
         for (size_t r = b; r < std::min(n, b + g); ++r) {
