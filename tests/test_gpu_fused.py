@@ -228,3 +228,28 @@ def test_fused_many_receivers_in_one_tile(dtype):
     torch.cuda.synchronize()
     assert np.array_equal(host(st), ref)
     assert np.array_equal(host(tr), tr_ref)
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_fused_receivers_large_grid(dtype):
+    """A grid of more tiles than two waves per SIMD (4542 tiles of 64x2), where
+    a tile recording several receivers is launched once per group of four
+    (small grids launch one copy per receiver): six receivers in one tile,
+    one repeated, and others spread out; traces and state bitwise against
+    the oracle."""
+    M, N, P, n_steps = 2 ** 18 + 1, 64, 64, 120
+    say("receivers-large-grid", dtype)
+    plan = rs.Plan(M, N, P, tile=(64, 2), dtype=dtype)
+    assert plan.info["fused"] == 1 and plan.info["n_tiles"] > 2 * 1024
+    lay = lay_of(plan)
+    npdt = NP[dtype]
+    st0, fa, fb = busy(M, n_steps, seed=23)
+    st0, fa, fb = st0.astype(npdt), fa.astype(npdt), fb.astype(npdt)
+    rec = np.array([7, 50000, 50001, 50002, 50003, 50001, 50004, 131072, M - 2], np.int64)
+    ref, tr_ref, _ = oracle.rswr(lay, plan.info["lambda"], plan.info["dx"], fa, fb, n_steps,
+                                 span=plan.span, state=st0, rec=rec)
+    st = dev(st0, dtype)
+    tr = rs.rswr_solve(plan, st, dev(fa, dtype), dev(fb, dtype), n_steps, receivers=rec)
+    torch.cuda.synchronize()
+    assert np.array_equal(host(st), ref)
+    assert np.array_equal(host(tr), tr_ref)
