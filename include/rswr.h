@@ -244,9 +244,11 @@ rswr_status_t rswr_adjoint_workspace_size(rswr_plan_t plan, int32_t n_rec,
  * gradient works).  Reverse mode of the discrete solve: the adjoint field
  * obeys the same leapfrog backward in time with the trace gradients as point
  * sources, and is advanced span by span, last span first, with the method's
- * own predict / update exchange (Sec. 2.3-2.5) on the plan's windows; the
- * forward field is rebuilt inside each span from the span-end checkpoint by
- * running the leapfrog backward.  `checkpoints` is the buffer filled by
+ * own predict / update exchange (Sec. 2.3-2.5) on the plan's windows (on
+ * plans that run the fused span, one launch per span: the tiles holding an
+ * input end advance its prediction themselves); the forward field is rebuilt
+ * inside each span from the span-end checkpoint by running the leapfrog
+ * backward.  `checkpoints` is the buffer filled by
  * rswr_solve over the same n_steps.  Writes dJ/df_A[n], dJ/df_B[n]
  * (n = 0..n_steps, entry 0 is 0) to grad_f_a / grad_f_b and dJ/dlam
  * (lam = a dt/dx at fixed dt) to the device double *grad_lambda; dJ/da is
