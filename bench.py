@@ -241,6 +241,49 @@ def sources_section(reps, tile):
             "ms": round(ms - zero_ms, 3), "n_src": len(nodes), "tile": [lo, hi]}
 
 
+def quiet_section(reps, tile=None):
+    """The adaptive (QUIET) select of Sec. 2.6 on the large case (2^24 nodes,
+    4096 windows, overlap 64, 2*10^4 steps, FP32, Ricker source at X_A):
+    every span chosen on the device inside one recorded graph (predict ->
+    select -> update per span, the two-launch kernels; spans from the light-
+    cone limit up to its double while the overlaps are quiet).  Against the
+    FIXED plan on the same two-launch kernels (span 35) and the FIXED fused
+    solve (tile `tile`, else the plan's default)."""
+    import math
+    import numpy as np
+    import torch
+    import paper_2203_10477_amd as rs
+    import workloads
+    prob = workloads.config5(np.float32)
+    fa_np, fb_np = prob.sources()
+    fa = torch.as_tensor(fa_np, device="cuda")
+    fb = torch.as_tensor(fb_np, device="cuda")
+    n = prob.n_steps
+    st = torch.zeros(2, prob.M, dtype=torch.float32, device="cuda")
+    zero_ms = timed(lambda: st.zero_(), reps)
+    out = {}
+    plans = {"quiet": rs.Plan(prob.M, prob.N, prob.P, dtype=torch.float32,
+                              span_mode=rs.QUIET),
+             "fixed_two_launch": rs.Plan(prob.M, prob.N, prob.P, dtype=torch.float32,
+                                         fuse=False),
+             "fixed_fused": rs.Plan(prob.M, prob.N, prob.P, dtype=torch.float32,
+                                    tile=tile)}
+    for name, plan in plans.items():
+        ws = torch.empty(plan.workspace_bytes(0), dtype=torch.uint8, device="cuda")
+        ms = timed(lambda: (st.zero_(), rs.rswr_solve(plan, st, fa, fb, n, workspace=ws)),
+                   reps) - zero_ms
+        if not torch.isfinite(st).all():
+            raise RuntimeError(f"non-finite state after the {name} solve")
+        out[name] = {"glups": round(prob.M * n / (ms * 1e-3) / 1e9, 2), "ms": round(ms, 3),
+                     "span": plan.span, "tile": [plan.info["tile_threads"],
+                                                 plan.info["tile_per_thread"]]}
+        del ws
+    q = plans["quiet"]
+    out["quiet"]["rounds_recorded"] = math.ceil(n / min(q.info["span_cone"], q.span))
+    return {"workload": f"{prob.M} nodes, {prob.N} windows, overlap {prob.P}, "
+                        f"{n} steps, FP32, Ricker at X_A", **out}
+
+
 def adjoint_batch_section(tile, group=16):
     """The large case's adjoint batch: 64 adjoint solves of the 2^24-node,
     4096-window, overlap-64, 2*10^4-step FP32 problem, each driven by its own
@@ -297,10 +340,12 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-forms", action="store_true",
-                    help="skip the batched, adjoint and pulse-source sections")
+                    help="skip the batched, adjoint, pulse-source, adjoint-batch and "
+                         "QUIET sections")
     ap.add_argument("--tile", default="", help="threads x nodes-per-lane, e.g. 320x13 "
                     "(default: autotuned)")
-    ap.add_argument("--section", choices=("batched", "adjoint", "sources", "adjoint_batch"),
+    ap.add_argument("--section", choices=("batched", "adjoint", "sources", "adjoint_batch",
+                                          "quiet"),
                     default=None,
                     help="run one of the other forms alone and print its figures "
                          "(for profiling)")
@@ -328,6 +373,9 @@ def main():
         elif args.section == "adjoint_batch":
             tile = tuple(int(v) for v in args.tile.split("x")) if args.tile else None
             out = adjoint_batch_section(tile)
+        elif args.section == "quiet":
+            tile = tuple(int(v) for v in args.tile.split("x")) if args.tile else None
+            out = quiet_section(reps, tile)
         else:
             tile = tuple(int(v) for v in args.tile.split("x")) if args.tile else None
             out = sources_section(reps, tile)
@@ -444,6 +492,7 @@ def main():
         line["sources"]["vs_plain"] = round(line["sources"]["glups"] / glups, 4)
         line["adjoint_batch"] = adjoint_batch_section(tile)
         line["adjoint_batch"]["vs_plain"] = round(line["adjoint_batch"]["glups"] / glups, 4)
+        line["quiet"] = quiet_section(max(1, args.steps), tile)
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(prob, args.cpu_seconds)
     print(json.dumps(line), flush=True)

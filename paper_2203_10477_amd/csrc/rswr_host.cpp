@@ -679,6 +679,7 @@ rswr_status_t enqueue_solve_quiet(rswr_plan_s* p, const DevTables& d, void* stat
     sa.flux = flux;
     sa.span_dev = &ctl->span;
     sa.shat_dev = &ctl->shat;
+    sa.qmin = &ctl->qmin;
     sa.n_rows = 2 * (p->N - 1);
     sa.shat = cap;
     sa.ld = p->flux_ld;

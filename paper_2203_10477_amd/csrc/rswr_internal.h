@@ -124,6 +124,10 @@ struct SelectArgs {
   int32_t* span_dev;
   const int32_t* shat_dev;  // nullable: shat from the device (0: done)
   int32_t n_rows, shat, ld, cone, mode, fixed_span;
+  // nullable (mode 1): the rows are scanned by many work-groups, one wave
+  // per row, which take the minimum into *qmin (INT32_MAX on entry); the
+  // last launch forms the span and restores *qmin to INT32_MAX
+  int32_t* qmin;
 };
 
 // Device-side state of an adaptive (QUIET) solve recorded as one graph of a
@@ -137,6 +141,8 @@ struct QuietCtl {
   int32_t parity;  // 1: the newest state is in the second buffer
   int32_t s_max;   // cap of the predictive span
   double beta;     // growth of Sec. 2.6
+  int32_t qmin;    // the select's running minimum (INT32_MAX between rounds)
+  int32_t pad;
 };
 
 // Adjoint of the receiver misfit (see rswr_adjoint.hip).  The adjoint field

@@ -304,6 +304,50 @@ __global__ __launch_bounds__(256) void k_select(const SelectArgs<T> a0) {
   }
 }
 
+// The same select for many rows: one wave per row finds the row's first
+// nonzero sample with a ballot over 64 samples at a time (the leading exact
+// zeros, capped by shat and the cone, as above) and the waves' minimum goes
+// to *qmin; k_select_final then forms the span and restores *qmin.
+template <typename T>
+__global__ __launch_bounds__(256) void k_select_rows(const SelectArgs<T> a) {
+  const int shat = a.shat_dev ? *a.shat_dev : a.shat;
+  if (shat <= 0) return;
+  const int lane = threadIdx.x & 63;
+  const int wave = static_cast<int>((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
+  const int n_waves = static_cast<int>((gridDim.x * blockDim.x) >> 6);
+  int wmin = 0x7fffffff;
+  for (int r = wave; r < a.n_rows; r += n_waves) {
+    const T* f = a.flux + static_cast<int64_t>(r) * a.ld;
+    int q = shat;
+    for (int s0 = 0; s0 < shat; s0 += 64) {
+      const int s = s0 + lane;
+      const bool nz = s < shat && !(f[s] == T(0));
+      const uint64_t m = __ballot(nz);
+      if (m != 0) {
+        q = s0 + __builtin_ctzll(m);
+        break;
+      }
+    }
+    q = q < a.cone ? q : a.cone;
+    wmin = q < wmin ? q : wmin;
+  }
+  if (lane == 0 && wmin != 0x7fffffff) atomicMin(a.qmin, wmin);
+}
+
+template <typename T>
+__global__ __launch_bounds__(64) void k_select_final(const SelectArgs<T> a) {
+  if (threadIdx.x == 0) {
+    const int shat = a.shat_dev ? *a.shat_dev : a.shat;
+    int S = shat > 0 ? shat : 0;
+    if (S > 0 && a.n_rows > 0) {
+      const long long lim = static_cast<long long>(*a.qmin) + a.cone;
+      if (lim < S) S = static_cast<int>(lim);
+    }
+    *a.span_dev = S;
+    *a.qmin = 0x7fffffff;
+  }
+}
+
 // Control block of the adaptive solve (Sec. 2.6): the first predictive span
 // is given; after each round the level advances by the chosen span and the
 // next predictive span is ceil((1 + beta) S), capped by s_max and the
@@ -319,6 +363,7 @@ __global__ __launch_bounds__(64) void k_quiet_init(QuietCtl* c, int64_t n0, int6
     c->parity = 0;
     c->s_max = s_max;
     c->beta = beta;
+    c->qmin = 0x7fffffff;
   }
 }
 
@@ -403,6 +448,18 @@ hipError_t launch_update(const UpdateArgs<T>& a, int threads, int per_thread,
 
 template <typename T>
 hipError_t launch_select(const SelectArgs<T>& a, hipStream_t s) {
+  if (a.mode == 1 && a.qmin) {
+    // four rows per work-group, at most 2048 work-groups (grid-stride)
+    if (a.n_rows > 0) {
+      const int64_t groups = std::min<int64_t>((int64_t(a.n_rows) + 3) / 4, 2048);
+      hipLaunchKernelGGL(k_select_rows<T>, dim3(static_cast<unsigned>(groups)), dim3(256), 0,
+                         s, a);
+      const hipError_t e = hipGetLastError();
+      if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(k_select_final<T>, dim3(1), dim3(64), 0, s, a);
+    return hipGetLastError();
+  }
   hipLaunchKernelGGL(k_select<T>, dim3(1), dim3(256), 0, s, a);
   return hipGetLastError();
 }
