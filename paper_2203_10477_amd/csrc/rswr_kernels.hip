@@ -331,7 +331,16 @@ __global__ __launch_bounds__(256) void k_select_rows(const SelectArgs<T> a) {
     q = q < a.cone ? q : a.cone;
     wmin = q < wmin ? q : wmin;
   }
-  if (lane == 0 && wmin != 0x7fffffff) atomicMin(a.qmin, wmin);
+  // one atomic per work-group (the waves' minimum through LDS): the atomics
+  // of one address serialise
+  __shared__ int gmin[4];
+  if (lane == 0) gmin[threadIdx.x >> 6] = wmin;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int m = gmin[0];
+    for (int w = 1; w < 4; ++w) m = gmin[w] < m ? gmin[w] : m;
+    if (m != 0x7fffffff) atomicMin(a.qmin, m);
+  }
 }
 
 template <typename T>
@@ -449,9 +458,10 @@ hipError_t launch_update(const UpdateArgs<T>& a, int threads, int per_thread,
 template <typename T>
 hipError_t launch_select(const SelectArgs<T>& a, hipStream_t s) {
   if (a.mode == 1 && a.qmin) {
-    // four rows per work-group, at most 2048 work-groups (grid-stride)
+    // at least four rows per wave, at most 512 work-groups of four waves
+    // (grid-stride)
     if (a.n_rows > 0) {
-      const int64_t groups = std::min<int64_t>((int64_t(a.n_rows) + 3) / 4, 2048);
+      const int64_t groups = std::min<int64_t>((int64_t(a.n_rows) + 15) / 16, 512);
       hipLaunchKernelGGL(k_select_rows<T>, dim3(static_cast<unsigned>(groups)), dim3(256), 0,
                          s, a);
       const hipError_t e = hipGetLastError();
