@@ -35,7 +35,7 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
 # HBM traffic of one span kernel launch on this workload, from two rocprofv3
 # --pmc passes (FETCH_SIZE, WRITE_SIZE; see profiles/), valid only for the
 # kernel sources with this SHA-256 prefix.
-TRAFFIC = {"kernel_sha": "0089565afe757c02", "bytes": 270183522}
+TRAFFIC = {"kernel_sha": "f297b915b4abaf58", "bytes": 270185881}
 
 
 def kernel_sha():
