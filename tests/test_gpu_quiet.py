@@ -52,6 +52,7 @@ CASES = [
     (3001, 10, 64, 700, 11, False, None),
     (2001, 3, 40, 400, 0, True, None),      # busy: every span at the cone
     (1001, 2, 20, 7, 0, False, None),       # fewer steps than one span
+    (40001, 600, 20, 300, 0, False, None),  # 1198 flux rows: the select spans 75 work-groups
 ]
 
 
