@@ -147,7 +147,7 @@ def time_batch(plans, probs, n_steps, reps=3):
 
 
 def autotune_batch(probs, dtype=torch.float32, sample=16, spans_timed=4, slack=1.5,
-                   measure=True, refine=True):
+                   measure=True, refine=True, sweeps=2):
     """Tile shape per size class for a batch of problems.
 
     Every problem gets the span batch_span().  Within a size class, the shapes
@@ -157,7 +157,8 @@ def autotune_batch(probs, dtype=torch.float32, sample=16, spans_timed=4, slack=1
     the least computed nodes wins).  With `refine`, each class's shortlist is
     then tried again in the complete batched solve (classes run side by side
     there), class by class, keeping a change only if the whole solve gets
-    faster.  Returns (tiles per problem, spans per problem, {class: (shape,
+    faster; `sweeps` passes over the classes (a change of one class can make
+    another class's alternative pay).  Returns (tiles per problem, spans per problem, {class: (shape,
     {shape: microseconds})})."""
     spans = [batch_span(p, dtype) for p in probs]
     classes = {}
@@ -206,7 +207,7 @@ def autotune_batch(probs, dtype=torch.float32, sample=16, spans_timed=4, slack=1
 
         cur = whole(tiles)
         order = sorted(classes, key=lambda c: -sum(probs[i].M for i in classes[c]))
-        for c in order:
+        for c in [c for _ in range(sweeps) for c in order]:
             for sh in shortlists[c]:
                 if sh == report[c][0]:
                     continue
