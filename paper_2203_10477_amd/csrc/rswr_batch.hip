@@ -17,7 +17,11 @@ __global__ __launch_bounds__(NT) void k_fused_batch(const BatchArgs<T> b) {
   constexpr int TMP = TM + (TM >> 5) + 1;
   __shared__ T st[TMP];
   __shared__ T edge[2][2][NW];
-  for (int item = blockIdx.x; item < b.n_items; item += gridDim.x) {
+  // the round's items from the last one down: problems are ordered by span
+  // count, longest first, so the prefix ends with the longest spans (the
+  // dearest tiles), which go first
+  for (int k = blockIdx.x; k < b.n_items; k += gridDim.x) {
+    const int item = b.n_items - 1 - k;
     const Tile tl = b.items[item];
     const BatchInst<T> in = b.inst[tl.inst];
     const int64_t n0 = static_cast<int64_t>(b.round) * in.S;
