@@ -107,7 +107,8 @@ def batched_section(reps):
     from paper_2203_10477_amd.autotune import autotune_batch, batch_plans
     probs, clamped = workloads.config3()
     t0 = time.perf_counter()
-    tiles, spans, report = autotune_batch(probs)
+    tiles, spans, report = autotune_batch(
+        probs, log=lambda s: print("[batched autotune]", s, file=sys.stderr, flush=True))
     tune_s = time.perf_counter() - t0
     plans = batch_plans(probs, torch.float32, tiles=tiles, spans=spans)
     b = rs.Batch(plans)

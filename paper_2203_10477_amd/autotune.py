@@ -147,7 +147,7 @@ def time_batch(plans, probs, n_steps, reps=3):
 
 
 def autotune_batch(probs, dtype=torch.float32, sample=16, spans_timed=4, slack=1.5,
-                   measure=True, refine=True, sweeps=2):
+                   measure=True, refine=True, sweeps=2, log=None):
     """Tile shape per size class for a batch of problems.
 
     Every problem gets the span batch_span().  Within a size class, the shapes
@@ -158,7 +158,8 @@ def autotune_batch(probs, dtype=torch.float32, sample=16, spans_timed=4, slack=1
     then tried again in the complete batched solve (classes run side by side
     there), class by class, keeping a change only if the whole solve gets
     faster; `sweeps` passes over the classes (a change of one class can make
-    another class's alternative pay).  Returns (tiles per problem, spans per problem, {class: (shape,
+    another class's alternative pay).  `log`, if given, receives one line
+    per class timed and per refinement trial.  Returns (tiles per problem, spans per problem, {class: (shape,
     {shape: microseconds})})."""
     spans = [batch_span(p, dtype) for p in probs]
     classes = {}
@@ -195,6 +196,8 @@ def autotune_batch(probs, dtype=torch.float32, sample=16, spans_timed=4, slack=1
             best = min(shortlist, key=lambda k: work[k])
         report[c] = (best, times)
         shortlists[c] = shortlist
+        if log:
+            log(f"size class {c}: {best[0]}x{best[1]} of {len(shortlist)} shapes")
         for i in idx:
             tiles[i] = best
     fix_unfused(tiles)
@@ -216,6 +219,8 @@ def autotune_batch(probs, dtype=torch.float32, sample=16, spans_timed=4, slack=1
                     trial[i] = sh
                 fix_unfused(trial)
                 tt = whole(trial)
+                if log:
+                    log(f"refine class {c}: {sh[0]}x{sh[1]} {tt:.3f} ms (best {cur:.3f} ms)")
                 if tt < cur:
                     cur, tiles = tt, trial
                     report[c] = (sh, report[c][1])
