@@ -238,6 +238,14 @@ rswr_status_t rswr_solve(rswr_plan_t plan, void* state, const void* f_a,
 rswr_status_t rswr_adjoint_workspace_size(rswr_plan_t plan, int32_t n_rec,
                                           size_t* bytes);
 
+/* *fused = 1 if rswr_solve_adjoint of this plan runs the fused adjoint span
+ * on the current device (the plan runs the fused span, and the fused update
+ * kernels of its shape need no scratch memory there), else 0: then each
+ * span is a predict launch and an update launch.  The results are the same
+ * bit for bit either way.  Needs a device (reads the kernels' attributes);
+ * no allocation. */
+rswr_status_t rswr_adjoint_fused(rswr_plan_t plan, int32_t* fused);
+
 /* Gradient of the receiver misfit J = sum_r sum_n (U^n[rec_r] - d_r^n)^2 of
  * an n_steps solve from level 0 (FIXED plan), given dJ/dtrace in
  * `grad_traces` [n_rec][n_steps] (2 (trace - d) for this J; any upstream

@@ -77,6 +77,7 @@ def lib():
     L.rswr_solve_workspace_size.argtypes = [vp, i32, ctypes.POINTER(sz)]
     L.rswr_checkpoint_size.argtypes = [vp, i64, ctypes.POINTER(sz)]
     L.rswr_adjoint_workspace_size.argtypes = [vp, i32, ctypes.POINTER(sz)]
+    L.rswr_adjoint_fused.argtypes = [vp, ctypes.POINTER(i32)]
     L.rswr_solve_adjoint.argtypes = [vp, vp, vp, vp, i64, vp, i32, vp, vp, vp, vp, vp, sz,
                                      vp]
     L.rswr_solve.argtypes = [vp, vp, vp, vp, i64, i64, vp, i32, vp, vp, sz, vp, vp]
@@ -92,7 +93,7 @@ def lib():
                  "rswr_plan_tiles",
                  "rswr_predict", "rswr_select", "rswr_update", "rswr_span",
                  "rswr_solve_workspace_size", "rswr_solve", "rswr_checkpoint_size",
-                 "rswr_adjoint_workspace_size", "rswr_solve_adjoint",
+                 "rswr_adjoint_workspace_size", "rswr_adjoint_fused", "rswr_solve_adjoint",
                  "rswr_adjoint_batch_workspace_size", "rswr_solve_adjoint_batch",
                  "rswr_batch_plan",
                  "rswr_batch_destroy", "rswr_batch_workspace_size", "rswr_batch_solve"):
@@ -333,6 +334,14 @@ def rswr_solve(plan, state, f_a, f_b, n_steps, n0=0, receivers=None, checkpoints
                             _dev(workspace, torch.uint8, 1, "workspace"),
                             workspace.numel(), ck, _stream()), "rswr_solve")
     return traces
+
+
+def rswr_adjoint_fused(plan):
+    """True if rswr_solve_adjoint of `plan` runs the fused adjoint span on the
+    current device (see include/rswr.h)."""
+    f = ctypes.c_int32()
+    _check(lib().rswr_adjoint_fused(plan.handle, ctypes.byref(f)), "rswr_adjoint_fused")
+    return bool(f.value)
 
 
 def rswr_solve_adjoint(plan, checkpoints, f_a, f_b, n_steps, receivers, grad_traces,

@@ -1616,6 +1616,12 @@ rswr_status_t rswr_solve(rswr_plan_t p, void* state, const void* f_a, const void
   return run_graph(p, d, key, enqueue, s);
 }
 
+rswr_status_t rswr_adjoint_fused(rswr_plan_t p, int32_t* fused) {
+  if (!p || !fused) return fail(RSWR_ERR_INVALID_ARG, "null pointer");
+  *fused = (p->fused && adj_fused_fits(*p)) ? 1 : 0;
+  return RSWR_OK;
+}
+
 rswr_status_t rswr_adjoint_workspace_size(rswr_plan_t p, int32_t n_rec, size_t* bytes) {
   if (!p || !bytes || n_rec < 0) return fail(RSWR_ERR_INVALID_ARG, "bad argument");
   *bytes = adj_ws_layout(*p, n_rec).total;
