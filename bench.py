@@ -35,7 +35,8 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
 # HBM traffic of one span kernel launch on this workload, from two rocprofv3
 # --pmc passes (FETCH_SIZE, WRITE_SIZE; see profiles/), valid only for the
 # kernel sources with this SHA-256 prefix.
-TRAFFIC = {"kernel_sha": "f297b915b4abaf58", "bytes": 270185881}
+TRAFFIC = {"kernel_sha": "f297b915b4abaf58", "tile": [64, 33], "bytes": 270185881,
+           "valu_insts": 33179678}
 
 
 def kernel_sha():
@@ -459,7 +460,14 @@ def main():
     nbytes = span_bytes(plan, 4)
     achieved = nbytes / (span_us * 1e-6) / 1e9
     sha = kernel_sha()
-    traffic = TRAFFIC["bytes"] if TRAFFIC["kernel_sha"] == sha else None
+    measured = (TRAFFIC["kernel_sha"] == sha and
+                [plan.info["tile_threads"], plan.info["tile_per_thread"]] == TRAFFIC["tile"])
+    traffic = TRAFFIC["bytes"] if measured else None
+    # VALU wave instructions per launch (counter pass of the same sources and
+    # tile) against the issue cycles of 1024 SIMDs at 2.4 GHz over the live
+    # launch time, 4 cycles per wave64 instruction
+    valu_frac = (round(TRAFFIC["valu_insts"] * 4 / (1024 * 2.4e9 * span_us * 1e-6), 4)
+                 if measured else None)
     kname = ("k_fused (predict + update of one span, all windows, one launch)" if fused
              else "k_predict + k_update (one span, all windows)")
 
@@ -478,6 +486,8 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic, "kernel": kname,
+                     "valu_insts": TRAFFIC["valu_insts"] if measured else None,
+                     "valu_issue_frac": valu_frac,
                      "avg_us": round(span_us, 2), "algorithmic_bytes": nbytes,
                      "busy_field_avg_us": round(busy_us, 2),
                      "busy_field_frac": round(nbytes / (busy_us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4)},
