@@ -269,7 +269,8 @@ __device__ __forceinline__ void lap_and_reverse(const T (&wn)[MPT], const T (&uc
     const T ur = (e == MPT - 1) ? R : ucur[e + 1];
     if (GEN) ul = (e == dl) ? ghost : ul;
     const T s = ul + ur;
-    const T lap = s - T(2) * ucur[e];
+    // s - 2u in one rounding: 2u is exact, so the fused form rounds the same
+    const T lap = fma_(T(-2), ucur[e], s);
     const T lapm = ((cnt >> e) & 1u) ? lap : T(0);
     acc = __builtin_fma(static_cast<double>(wn[e]), static_cast<double>(lapm), acc);
     if (rev) {
