@@ -61,9 +61,10 @@ def _load():
         f.argtypes = [i64, i32, vp, vp, vp, vp, dbl, dbl, vp, vp, i64, i64, vp, i32,
                       i32, i32, i32, dbl, i32, vp, vp, i64, vp, i32, i32, vp, vp, i64]
         f.restype = ctypes.c_int
-    lib.oracle_adjoint_f64.argtypes = [i64, dbl, dbl, vp, vp, i64, i32, vp, vp, i64,
-                                       i32, vp, vp, vp]
-    lib.oracle_adjoint_f64.restype = ctypes.c_int
+    for suf in ("_f64", "_f32"):
+        f = getattr(lib, "oracle_adjoint" + suf)
+        f.argtypes = [i64, dbl, dbl, vp, vp, i64, i32, vp, vp, i64, i32, vp, vp, vp, vp]
+        f.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -231,23 +232,30 @@ def rswr(lay, lam, dx, fa, fb, n_steps, mode=FIXED, span=None, beta=0.1,
     return st, tr[:, :n_steps], spans[:k]
 
 
-def adjoint(M, lam, dx, fa, fb, n_steps, rec, grad_traces, ck=64):
-    """Reverse mode of the single-domain solve from rest (FP64).
+def adjoint(M, lam, dx, fa, fb, n_steps, rec, grad_traces, ck=64, dtype=np.float64,
+            terms=False):
+    """Reverse mode of the single-domain solve from rest, in float64 or
+    float32 (the precision of W, the forward field and the Laplacian; every
+    dJ/dlam product and sum is taken in double).
 
-    Returns (dJ/df_a[0..n_steps], dJ/df_b[0..n_steps], dJ/dlam)."""
-    fa = _c(fa, np.float64)
-    fb = _c(fb, np.float64)
+    Returns (dJ/df_a[0..n_steps], dJ/df_b[0..n_steps], dJ/dlam), and with
+    terms=True also 2|lam| sum |W Lap U|, the scale of dJ/dlam's rounding."""
+    suf = _suffix(dtype)
+    fa = _c(fa, dtype)
+    fb = _c(fb, dtype)
     rec = _c(np.asarray(rec, np.int64).reshape(-1))
-    gt = _c(grad_traces, np.float64)
-    ga = np.zeros(n_steps + 1)
-    gb = np.zeros(n_steps + 1)
+    gt = _c(grad_traces, dtype)
+    ga = np.zeros(n_steps + 1, dtype)
+    gb = np.zeros(n_steps + 1, dtype)
     gl = ctypes.c_double(0.0)
-    rc = _load().oracle_adjoint_f64(M, lam, dx, _ptr(fa), _ptr(fb), n_steps, len(rec),
-                                    _ptr(rec), _ptr(gt), gt.shape[1], ck, _ptr(ga),
-                                    _ptr(gb), ctypes.byref(gl))
+    sa = ctypes.c_double(0.0)
+    rc = getattr(_load(), "oracle_adjoint" + suf)(
+        M, lam, dx, _ptr(fa), _ptr(fb), n_steps, len(rec), _ptr(rec), _ptr(gt),
+        gt.shape[1] if gt.ndim == 2 else n_steps, ck, _ptr(ga), _ptr(gb), ctypes.byref(gl),
+        ctypes.byref(sa))
     if rc != 0:
-        raise RuntimeError(f"oracle_adjoint_f64 failed ({rc})")
-    return ga, gb, gl.value
+        raise RuntimeError(f"oracle_adjoint{suf} failed ({rc})")
+    return (ga, gb, gl.value, sa.value) if terms else (ga, gb, gl.value)
 
 
 def point_values(M, lam, dx, fa, fb, n_steps, state, nodes, n0=0, src=None):

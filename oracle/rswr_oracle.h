@@ -97,16 +97,21 @@ int32_t oracle_span_paper(int32_t P, double lam, int32_t num, int32_t den);
 ORACLE_DECLARE(double, _f64)
 ORACLE_DECLARE(float, _f32)
 
-/* Reverse mode of oracle_single_f64 from the zero initial state, level 0,
- * n_steps steps: given dJ/dtrace, returns dJ/df_A[n], dJ/df_B[n]
- * (n = 0..n_steps; entry 0 is 0 because the initial condition owns level 0)
- * and dJ/dlam.  Forward states are kept every `ck` levels and each segment
- * is recomputed during the reverse sweep. */
-int oracle_adjoint_f64(int64_t M, double lam, double dx, const double* fa,
-                       const double* fb, int64_t n_steps, int32_t n_rec,
-                       const int64_t* rec, const double* grad_traces,
-                       int64_t trace_ld, int32_t ck, double* grad_fa,
-                       double* grad_fb, double* grad_lam);
+/* Reverse mode of oracle_single (same precision) from the zero initial
+ * state, level 0, n_steps steps: given dJ/dtrace, returns dJ/df_A[n],
+ * dJ/df_B[n] (n = 0..n_steps; entry 0 is 0 because the initial condition
+ * owns level 0) and dJ/dlam, and (sum_abs, nullable) the sum of the
+ * magnitudes of dJ/dlam's terms.  Forward states are kept every `ck` levels
+ * and each segment is recomputed during the reverse sweep. */
+#define ORACLE_DECLARE_ADJ(T, SUF)                                             \
+  int oracle_adjoint##SUF(int64_t M, double lam, double dx, const T* fa,       \
+                          const T* fb, int64_t n_steps, int32_t n_rec,         \
+                          const int64_t* rec, const T* grad_traces,            \
+                          int64_t trace_ld, int32_t ck, T* grad_fa,            \
+                          T* grad_fb, double* grad_lam, double* sum_abs);
+
+ORACLE_DECLARE_ADJ(double, _f64)
+ORACLE_DECLARE_ADJ(float, _f32)
 
 #ifdef __cplusplus
 }

@@ -377,17 +377,21 @@ int SFX(oracle_rswr)(int64_t M, int32_t N, const int64_t* lo,
   return k;
 }
 
-#ifndef ORACLE_F32
 /* ------------------------------------------------------------------------ */
-/* Reverse mode of the single-domain solve (FP64).  The forward map is the   */
-/* leapfrog of oracle_single from U^{-1} = U^0 = 0; the adjoint W^n =        */
-/* dJ/dU^n obeys, on interior nodes,                                         */
+/* Reverse mode of the single-domain solve.  The forward map is the leapfrog */
+/* of oracle_single from U^{-1} = U^0 = 0; the adjoint W^n = dJ/dU^n obeys,  */
+/* on interior nodes,                                                        */
 /*   W^n_j = g^n_j + k W^{n+1}_j + lam^2 (W^{n+1}_{j-1} + W^{n+1}_{j+1})      */
 /*           - W^{n+2}_j,                                                    */
 /* with W taken as zero on the two Dirichlet nodes and beyond level N_t,     */
 /* g^n_j = dJ/dtrace at receivers on node j.  Then dJ/df_A[n] = g^n_0 +       */
 /* lam^2 W^{n+1}_1, dJ/df_B[n] likewise at the right end, and                */
-/* dJ/dlam = 2 lam sum_{n,j} W^{n+1}_j (U^n_{j-1} - 2 U^n_j + U^n_{j+1}).     */
+/* dJ/dlam = 2 lam sum_{n,j} W^n_j (U^{n-1}_{j-1} - 2 U^{n-1}_j + U^{n-1}_{j+1}).*/
+/* W and the Laplacian are formed in the working precision (the pinned       */
+/* per-node order); each product W * Lap and every sum is taken in double    */
+/* (a float product is exact there), pairwise.  sum_abs (nullable) receives  */
+/* 2 |lam| sum_{n,j} |W^n_j Lap_j|: the scale against which the rounding of  */
+/* this long, cancelling sum is judged.                                      */
 /* ------------------------------------------------------------------------ */
 static double pairwise_sum(const double* x, int64_t n) {
   if (n <= 16) {
@@ -399,36 +403,39 @@ static double pairwise_sum(const double* x, int64_t n) {
   return pairwise_sum(x, h) + pairwise_sum(x + h, n - h);
 }
 
-int oracle_adjoint_f64(int64_t M, double lam, double dx, const double* fa,
-                       const double* fb, int64_t n_steps, int32_t n_rec,
-                       const int64_t* rec, const double* grad_traces,
-                       int64_t trace_ld, int32_t ck, double* grad_fa,
-                       double* grad_fb, double* grad_lam) {
+int SFX(oracle_adjoint)(int64_t M, double lam, double dx, const real* fa,
+                        const real* fb, int64_t n_steps, int32_t n_rec,
+                        const int64_t* rec, const real* grad_traces,
+                        int64_t trace_ld, int32_t ck, real* grad_fa,
+                        real* grad_fb, double* grad_lam, double* sum_abs) {
   if (ck < 1 || M < 3) return -1;
   const coef_t c = make_coef(lam, dx);
   const int64_t nck = n_steps / ck + 1;
   /* checkpoint m holds levels m*ck - 1 and m*ck */
-  double* ckpt = (double*)calloc((size_t)(nck * 2 * M), sizeof(double));
-  double* seg = (double*)malloc(sizeof(double) * (size_t)((ck + 1) * M));
-  double* w0 = (double*)calloc((size_t)M, sizeof(double)); /* W^{n+2} */
-  double* w1 = (double*)calloc((size_t)M, sizeof(double)); /* W^{n+1} */
-  double* w2 = (double*)calloc((size_t)M, sizeof(double)); /* W^n */
+  real* ckpt = (real*)calloc((size_t)(nck * 2 * M), sizeof(real));
+  real* seg = (real*)malloc(sizeof(real) * (size_t)((ck + 1) * M));
+  real* w0 = (real*)calloc((size_t)M, sizeof(real)); /* W^{n+2} */
+  real* w1 = (real*)calloc((size_t)M, sizeof(real)); /* W^{n+1} */
+  real* w2 = (real*)calloc((size_t)M, sizeof(real)); /* W^n */
   double* term = (double*)malloc(sizeof(double) * (size_t)M);
+  double* aterm = (double*)malloc(sizeof(double) * (size_t)M);
   double* lev_sum = (double*)calloc((size_t)(n_steps + 1), sizeof(double));
-  if (!ckpt || !seg || !w0 || !w1 || !w2 || !term || !lev_sum) return -2;
+  double* lev_abs = (double*)calloc((size_t)(n_steps + 1), sizeof(double));
+  if (!ckpt || !seg || !w0 || !w1 || !w2 || !term || !aterm || !lev_sum || !lev_abs)
+    return -2;
 
   /* forward sweep storing checkpoints */
   {
-    double* b0 = (double*)calloc((size_t)M, sizeof(double));
-    double* b1 = (double*)calloc((size_t)M, sizeof(double));
-    double* b2 = (double*)calloc((size_t)M, sizeof(double));
+    real* b0 = (real*)calloc((size_t)M, sizeof(real));
+    real* b1 = (real*)calloc((size_t)M, sizeof(real));
+    real* b2 = (real*)calloc((size_t)M, sizeof(real));
     for (int64_t n = 0; n < n_steps; ++n) {
       if (n % ck == 0) {
-        memcpy(ckpt + (n / ck) * 2 * M, b0, sizeof(double) * (size_t)M);
-        memcpy(ckpt + (n / ck) * 2 * M + M, b1, sizeof(double) * (size_t)M);
+        memcpy(ckpt + (n / ck) * 2 * M, b0, sizeof(real) * (size_t)M);
+        memcpy(ckpt + (n / ck) * 2 * M + M, b1, sizeof(real) * (size_t)M);
       }
       window_step(&c, M, 0, M - 1, b0, b1, b2, 0, 0, fa[n + 1], fb[n + 1], NULL, n);
-      double* t = b0;
+      real* t = b0;
       b0 = b1;
       b1 = b2;
       b2 = t;
@@ -438,22 +445,22 @@ int oracle_adjoint_f64(int64_t M, double lam, double dx, const double* fa,
     free(b2);
   }
 
-  grad_fa[0] = 0.0;
-  grad_fb[0] = 0.0;
+  grad_fa[0] = 0;
+  grad_fb[0] = 0;
   int64_t seg_base = -1; /* level held by seg[1] */
   for (int64_t n = n_steps; n >= 1; --n) {
     /* W^n from W^{n+1} (w1) and W^{n+2} (w0) */
     for (int64_t j = 1; j <= M - 2; ++j) {
-      const double wl = (j - 1 >= 1) ? w1[j - 1] : 0.0;
-      const double wr = (j + 1 <= M - 2) ? w1[j + 1] : 0.0;
+      const real wl = (j - 1 >= 1) ? w1[j - 1] : (real)0;
+      const real wr = (j + 1 <= M - 2) ? w1[j + 1] : (real)0;
       w2[j] = leap(&c, wl, w1[j], wr, w0[j]);
     }
-    w2[0] = 0.0;
-    w2[M - 1] = 0.0;
-    double ga = c.c2 * w1[1];
-    double gb = c.c2 * w1[M - 2];
+    w2[0] = 0;
+    w2[M - 1] = 0;
+    real ga = c.c2 * w1[1];
+    real gb = c.c2 * w1[M - 2];
     for (int32_t r = 0; r < n_rec; ++r) {
-      const double g = grad_traces[(int64_t)r * trace_ld + (n - 1)];
+      const real g = grad_traces[(int64_t)r * trace_ld + (n - 1)];
       const int64_t j = rec[r];
       if (j == 0)
         ga = ga + g;
@@ -470,7 +477,7 @@ int oracle_adjoint_f64(int64_t M, double lam, double dx, const double* fa,
     const int64_t cidx = m / ck;
     if (seg_base < 0 || cidx * ck != seg_base) {
       seg_base = cidx * ck;
-      memcpy(seg, ckpt + cidx * 2 * M, sizeof(double) * 2 * (size_t)M);
+      memcpy(seg, ckpt + cidx * 2 * M, sizeof(real) * 2 * (size_t)M);
       const int64_t top = (seg_base + ck - 1 < n_steps) ? seg_base + ck - 1 : n_steps;
       for (int64_t L = seg_base; L < top; ++L) {
         const int64_t t = L - seg_base + 1; /* seg[t] = U^L */
@@ -478,26 +485,32 @@ int oracle_adjoint_f64(int64_t M, double lam, double dx, const double* fa,
                     seg + (t + 1) * M, 0, 0, fa[L + 1], fb[L + 1], NULL, L);
       }
     }
-    const double* U = seg + (m - seg_base + 1) * M;
-    term[0] = 0.0;
-    term[M - 1] = 0.0;
-    for (int64_t j = 1; j <= M - 2; ++j)
-      term[j] = w2[j] * ((U[j - 1] + U[j + 1]) - 2.0 * U[j]);
+    const real* U = seg + (m - seg_base + 1) * M;
+    term[0] = term[M - 1] = 0.0;
+    aterm[0] = aterm[M - 1] = 0.0;
+    for (int64_t j = 1; j <= M - 2; ++j) {
+      const real lap = (U[j - 1] + U[j + 1]) - (real)2 * U[j];
+      term[j] = (double)w2[j] * (double)lap;
+      aterm[j] = fabs(term[j]);
+    }
     lev_sum[n] = pairwise_sum(term, M);
+    lev_abs[n] = pairwise_sum(aterm, M);
 
-    double* t = w0;
+    real* t = w0;
     w0 = w1;
     w1 = w2;
     w2 = t;
   }
   *grad_lam = 2.0 * lam * pairwise_sum(lev_sum, n_steps + 1);
+  if (sum_abs) *sum_abs = 2.0 * fabs(lam) * pairwise_sum(lev_abs, n_steps + 1);
   free(ckpt);
   free(seg);
   free(w0);
   free(w1);
   free(w2);
   free(term);
+  free(aterm);
   free(lev_sum);
+  free(lev_abs);
   return 0;
 }
-#endif

@@ -114,3 +114,88 @@ def test_checkpoint_interval_does_not_change_result():
             for ck in (1, 7, 64, 1000)]
     for o in outs[1:]:
         assert np.array_equal(o[0], outs[0][0]) and o[2] == outs[0][2]
+
+
+def _levels(M, lam, dx, fa, fb, n_steps):
+    """U^{-1} .. U^{n_steps} of the single-domain solve from rest, one
+    oracle step at a time."""
+    lev = [np.zeros(M), np.zeros(M)]
+    st = np.zeros((2, M))
+    for n in range(n_steps):
+        st, _ = oracle.single(M, lam, dx, fa, fb, 1, state=st, n0=n)
+        lev.append(st[1].copy())
+    return lev  # lev[n + 1] = U^n
+
+
+def test_lambda_terms_against_bruteforce_sensitivities(tiny):
+    """W^n_j, the sensitivity of sum_r,t w[r,t] trace[r,t] to a unit change of
+    U^n_j, taken by re-running the forward solve from the perturbed state
+    (traces are affine in the state); then dJ/dlam = 2 lam sum W Lap(U^{n-1})
+    and the magnitude sum 2 |lam| sum |W Lap(U^{n-1})| over interior nodes
+    against the oracle's reverse mode."""
+    M, n_steps, dx, fa, fb, rec, w = tiny
+    lam = 0.9
+    lev = _levels(M, lam, dx, fa, fb, n_steps)
+    tot = tot_abs = 0.0
+    for n in range(1, n_steps + 1):
+        lap = np.zeros(M)
+        u = lev[n]  # U^{n-1}
+        lap[1:-1] = (u[:-2] + u[2:]) - 2.0 * u[1:-1]
+        for j in range(1, M - 1):
+            st = np.stack([lev[n], lev[n + 1]])  # U^{n-1}, U^n
+            W = float(np.sum(w[:, n - 1] * (rec == j)))
+            if n < n_steps:
+                base, tr0 = oracle.single(M, lam, dx, fa, fb, n_steps - n, state=st, n0=n,
+                                          rec=rec)
+                st[1, j] += 1.0
+                _, tr1 = oracle.single(M, lam, dx, fa, fb, n_steps - n, state=st, n0=n,
+                                       rec=rec)
+                W += float(np.sum(w[:, n:] * (tr1 - tr0)))
+            tot += W * lap[j]
+            tot_abs += abs(W * lap[j])
+    _, _, gl, sa = oracle.adjoint(M, lam, dx, fa, fb, n_steps, rec, w, terms=True)
+    assert tot != 0.0 and tot_abs > abs(tot)
+    assert abs(gl - 2 * lam * tot) <= 1e-12 * 2 * lam * tot_abs
+    assert abs(sa - 2 * lam * tot_abs) <= 1e-12 * sa
+
+
+def test_float32_build_agrees_with_float64():
+    """The float build of the reverse mode (same operations, W and U in
+    float) against the double build: dJ/df within float rounding, dJ/dlam
+    within float rounding of its magnitude sum; causality zeros exact."""
+    M, n_steps = 301, 500
+    dx = 1.0 / (M - 1)
+    g = np.random.default_rng(12)
+    t = np.arange(n_steps + 1) * 0.9 * dx
+    fa = np.sin(2 * np.pi * 6 * t) * np.exp(-3 * t)
+    fa[0] = 0.0
+    fb = np.zeros_like(fa)
+    rec = np.array([30, 120, 250], np.int64)
+    w = g.standard_normal((3, n_steps))
+    ga64, _, gl64, sa64 = oracle.adjoint(M, 0.9, dx, fa, fb, n_steps, rec, w, terms=True)
+    ga32, gb32, gl32, sa32 = oracle.adjoint(M, 0.9, dx, fa.astype(np.float32),
+                                            fb.astype(np.float32), n_steps, rec,
+                                            w.astype(np.float32), dtype=np.float32,
+                                            terms=True)
+    assert ga32.dtype == np.float32
+    assert np.linalg.norm(ga32 - ga64) <= 1e-5 * np.linalg.norm(ga64)
+    assert abs(gl32 - gl64) <= 1e-4 * sa64
+    assert abs(sa32 - sa64) <= 1e-4 * sa64
+    cut = n_steps - rec.min()
+    assert np.all(ga32[cut + 1:] == 0.0)
+
+
+def test_float32_dot_product_identity():
+    M, n_steps = 201, 400
+    dx = 1.0 / (M - 1)
+    g = np.random.default_rng(6)
+    rec = np.sort(g.choice(np.arange(1, M - 1), 5, replace=False))
+    w = g.standard_normal((len(rec), n_steps)).astype(np.float32)
+    df = np.concatenate([[0.0], g.standard_normal(n_steps)]).astype(np.float32)
+    z = np.zeros(n_steps + 1, np.float32)
+    _, Adf = oracle.single(M, 0.9, dx, df, z, n_steps, rec=rec)
+    ga, _, _ = oracle.adjoint(M, 0.9, dx, z, z, n_steps, rec, w, dtype=np.float32)
+    lhs = np.sum(Adf.astype(np.float64) * w)
+    rhs = np.sum(df.astype(np.float64) * ga)
+    assert abs(lhs - rhs) <= 1e-5 * np.sqrt(np.sum(Adf.astype(np.float64) ** 2) *
+                                            np.sum(w.astype(np.float64) ** 2))
