@@ -62,6 +62,9 @@ def _load():
                       i32, i32, i32, dbl, i32, vp, vp, i64, vp, i32, i32, vp, vp, i64]
         f.restype = ctypes.c_int
     for suf in ("_f64", "_f32"):
+        f = getattr(lib, "oracle_rswr_many" + suf)
+        f.argtypes = [i32] + [vp] * 13
+        f.restype = None
         f = getattr(lib, "oracle_adjoint" + suf)
         f.argtypes = [i64, dbl, dbl, vp, vp, i64, i32, vp, vp, i64, i32, vp, vp, vp, vp]
         f.restype = ctypes.c_int
@@ -230,6 +233,53 @@ def rswr(lay, lam, dx, fa, fb, n_steps, mode=FIXED, span=None, beta=0.1,
     if k < 0:
         raise ValueError(f"oracle_rswr failed ({k})")
     return st, tr[:, :n_steps], spans[:k]
+
+
+def rswr_many(lays, lams, dxs, fas, fbs, n_steps, spans, states=None):
+    """FIXED-span RSWR of many independent problems from level 0 (no
+    receivers or sources), the problems spread over the threads.  lays:
+    Layout per problem; fas/fbs: sources (one dtype for all); states: start
+    states (2, M) or None (at rest).  Returns the final states."""
+    n = len(lays)
+    # largest problems first, so the threads finish together
+    order = sorted(range(n), key=lambda i: -lays[i].M * int(n_steps[i]))
+    if order != list(range(n)):
+        pick = lambda xs: [xs[i] for i in order]
+        out = rswr_many(pick(lays), pick(lams), pick(dxs), pick(fas), pick(fbs),
+                        pick(n_steps), pick(spans), None if states is None else pick(states))
+        res = [None] * n
+        for k, i in enumerate(order):
+            res[i] = out[k]
+        return res
+    dtype = np.asarray(fas[0]).dtype
+    suf = _suffix(dtype)
+    keep = []
+
+    def arr(xs, ctype):
+        a = (ctype * max(n, 1))(*xs)
+        keep.append(a)
+        return ctypes.cast(a, ctypes.c_void_p)
+
+    fa_c = [_c(a, dtype) for a in fas]
+    fb_c = [_c(b, dtype) for b in fbs]
+    st = [np.zeros((2, l.M), dtype) if states is None or states[i] is None
+          else _c(states[i], dtype).copy() for i, l in enumerate(lays)]
+    for q, f, g in zip(lays, fa_c, fb_c):
+        assert f.shape[0] >= 1 and g.shape[0] == f.shape[0]
+    for k, f in zip(n_steps, fa_c):
+        assert f.shape[0] >= int(k) + 1
+    vp = ctypes.c_void_p
+    getattr(_load(), "oracle_rswr_many" + suf)(
+        n, arr([l.M for l in lays], ctypes.c_int64), arr([l.N for l in lays], ctypes.c_int32),
+        arr([l.lo.ctypes.data for l in lays], vp), arr([l.hi.ctypes.data for l in lays], vp),
+        arr([l.own_lo.ctypes.data for l in lays], vp),
+        arr([l.own_hi.ctypes.data for l in lays], vp),
+        arr([float(x) for x in lams], ctypes.c_double),
+        arr([float(x) for x in dxs], ctypes.c_double),
+        arr([a.ctypes.data for a in fa_c], vp), arr([b.ctypes.data for b in fb_c], vp),
+        arr([int(k) for k in n_steps], ctypes.c_int64),
+        arr([int(s) for s in spans], ctypes.c_int32), arr([a.ctypes.data for a in st], vp))
+    return st
 
 
 def adjoint(M, lam, dx, fa, fb, n_steps, rec, grad_traces, ck=64, dtype=np.float64,

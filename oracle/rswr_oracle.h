@@ -97,6 +97,21 @@ int32_t oracle_span_paper(int32_t P, double lam, int32_t num, int32_t den);
 ORACLE_DECLARE(double, _f64)
 ORACLE_DECLARE(float, _f32)
 
+/* oracle_rswr (FIXED span, from level 0, no receivers or sources) of n_prob
+ * independent problems, spread over the threads; argument b of every array
+ * belongs to problem b. */
+#define ORACLE_DECLARE_MANY(T, SUF)                                            \
+  void oracle_rswr_many##SUF(int32_t n_prob, const int64_t* M, const int32_t* N, \
+                             const int64_t* const* lo, const int64_t* const* hi, \
+                             const int64_t* const* own_lo,                     \
+                             const int64_t* const* own_hi, const double* lam,  \
+                             const double* dx, const T* const* fa,             \
+                             const T* const* fb, const int64_t* n_steps,       \
+                             const int32_t* S, T* const* state);
+
+ORACLE_DECLARE_MANY(double, _f64)
+ORACLE_DECLARE_MANY(float, _f32)
+
 /* Reverse mode of oracle_single (same precision) from the zero initial
  * state, level 0, n_steps steps: given dJ/dtrace, returns dJ/df_A[n],
  * dJ/df_B[n] (n = 0..n_steps; entry 0 is 0 because the initial condition

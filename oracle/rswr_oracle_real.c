@@ -378,6 +378,27 @@ int SFX(oracle_rswr)(int64_t M, int32_t N, const int64_t* lo,
 }
 
 /* ------------------------------------------------------------------------ */
+/* Many independent FIXED-span problems (a batch): oracle_rswr of each, the   */
+/* problems spread over the threads (each problem's own loops then run on     */
+/* one thread).  Problem b: M[b] nodes, N[b] windows lo[b]/hi[b]/own_lo[b]/   */
+/* own_hi[b], lam[b], dx[b], span S[b], n_steps[b] levels from the state in  */
+/* state[b] (level 0 start), sources fa[b], fb[b].                            */
+/* ------------------------------------------------------------------------ */
+void SFX(oracle_rswr_many)(int32_t n_prob, const int64_t* M, const int32_t* N,
+                           const int64_t* const* lo, const int64_t* const* hi,
+                           const int64_t* const* own_lo,
+                           const int64_t* const* own_hi, const double* lam,
+                           const double* dx, const real* const* fa,
+                           const real* const* fb, const int64_t* n_steps,
+                           const int32_t* S, real* const* state) {
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int32_t b = 0; b < n_prob; ++b)
+    SFX(oracle_rswr)(M[b], N[b], lo[b], hi[b], own_lo[b], own_hi[b], lam[b], dx[b],
+                     fa[b], fb[b], 0, n_steps[b], state[b], 0, S[b], 0, 0, 0.1, 0,
+                     NULL, NULL, 1, NULL, 0, 0, NULL, NULL, 0);
+}
+
+/* ------------------------------------------------------------------------ */
 /* Reverse mode of the single-domain solve.  The forward map is the leapfrog */
 /* of oracle_single from U^{-1} = U^0 = 0; the adjoint W^n = dJ/dU^n obeys,  */
 /* on interior nodes,                                                        */

@@ -239,3 +239,28 @@ def test_update_windows_subset_matches_full():
     for w in (1, 3):
         sl = slice(lay.own_lo[w], lay.own_hi[w] + 1)
         assert np.array_equal(part[:, sl], full[:, sl])
+
+
+def test_rswr_many_equals_each_problem():
+    """The batch entry point runs each problem's own span loop: the states
+    equal oracle.rswr of every problem alone, bitwise, in both precisions."""
+    cases = [(601, 4, 32, 300, 1.0), (257, 2, 16, 137, 0.7), (1025, 8, 40, 211, 1.6)]
+    for dtype in (np.float64, np.float32):
+        lays, lams, dxs, fas, fbs, ns, spans = [], [], [], [], [], [], []
+        for M, N, P, n, a in cases:
+            lay = oracle.layout(M, N, P)
+            lam, dx = 0.9, 1.0 / (M - 1)
+            t = np.arange(n + 1) * lam * dx / a
+            fas.append(np.exp(-((t - 40 * dx / a) / (8 * dx / a)) ** 2).astype(dtype))
+            fbs.append((0.2 * np.sin(2 * np.pi * t / t[-1])).astype(dtype))
+            lays.append(lay)
+            lams.append(lam)
+            dxs.append(dx)
+            ns.append(n)
+            spans.append(min(lay.span_cone, oracle.span_paper(P, lam, (9, 10))))
+        out = oracle.rswr_many(lays, lams, dxs, fas, fbs, ns, spans)
+        for i in range(len(cases)):
+            ref, _, _ = oracle.rswr(lays[i], lams[i], dxs[i], fas[i], fbs[i], ns[i],
+                                    span=spans[i])
+            assert out[i].dtype == dtype
+            assert np.array_equal(out[i], ref), (dtype, i)
