@@ -234,6 +234,26 @@ rswr_status_t rswr_solve(rswr_plan_t plan, void* state, const void* f_a,
                          void* workspace, size_t ws_bytes, void* checkpoints,
                          void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the redo
+ * loop of rswr_solve without receivers or checkpoints, whose workspace (the
+ * second state buffer, the flux rows, the control block of a QUIET solve)
+ * is a device array inside the library of RSWR_NOALLOC_SCRATCH_BYTES
+ * (64 MiB) per GPU, held until the process ends.  The launches are
+ * enqueued directly on `stream` (no graph of its own, so a capturing caller
+ * records them); nothing is allocated or freed.  The plan's device tables
+ * must already be on the current device: any earlier compute call of the
+ * plan there (rswr_span, rswr_solve, ...) uploads them; else UNSUPPORTED.
+ * Arguments as rswr_solve.  Every call on one GPU uses that GPU's one
+ * array, which keeps the previous call's contents: calls that overlap in
+ * time on one GPU (two streams, two host threads) race, and the caller must
+ * order them.  Errors: INVALID_ARG, NOMEM (rswr_solve_workspace_size with no
+ * receivers exceeds the array), UNSUPPORTED, HIP. */
+#define RSWR_NOALLOC_SCRATCH_BYTES (64u << 20)
+rswr_status_t rswr_solve_noalloc(rswr_plan_t plan, void* state, const void* f_a,
+                                 const void* f_b, int64_t n0, int64_t n_steps,
+                                 void* stream);
+
 /* Bytes of device workspace rswr_solve_adjoint needs for n_rec receivers. */
 rswr_status_t rswr_adjoint_workspace_size(rswr_plan_t plan, int32_t n_rec,
                                           size_t* bytes);

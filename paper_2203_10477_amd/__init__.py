@@ -81,6 +81,7 @@ def lib():
     L.rswr_solve_adjoint.argtypes = [vp, vp, vp, vp, i64, vp, i32, vp, vp, vp, vp, vp, sz,
                                      vp]
     L.rswr_solve.argtypes = [vp, vp, vp, vp, i64, i64, vp, i32, vp, vp, sz, vp, vp]
+    L.rswr_solve_noalloc.argtypes = [vp, vp, vp, vp, i64, i64, vp]
     L.rswr_adjoint_batch_workspace_size.argtypes = [vp, i64, i32, i32, i32, ctypes.POINTER(sz)]
     L.rswr_solve_adjoint_batch.argtypes = [vp, i32, vp, vp, i64, i64, vp, i32, vp, vp, vp,
                                            vp, i32, i32, vp, sz, vp]
@@ -92,7 +93,8 @@ def lib():
     for name in ("rswr_plan", "rswr_plan_destroy", "rswr_plan_info", "rswr_plan_layout",
                  "rswr_plan_tiles",
                  "rswr_predict", "rswr_select", "rswr_update", "rswr_span",
-                 "rswr_solve_workspace_size", "rswr_solve", "rswr_checkpoint_size",
+                 "rswr_solve_workspace_size", "rswr_solve", "rswr_solve_noalloc",
+                 "rswr_checkpoint_size",
                  "rswr_adjoint_workspace_size", "rswr_adjoint_fused", "rswr_solve_adjoint",
                  "rswr_adjoint_batch_workspace_size", "rswr_solve_adjoint_batch",
                  "rswr_batch_plan",
@@ -334,6 +336,18 @@ def rswr_solve(plan, state, f_a, f_b, n_steps, n0=0, receivers=None, checkpoints
                             _dev(workspace, torch.uint8, 1, "workspace"),
                             workspace.numel(), ck, _stream()), "rswr_solve")
     return traces
+
+
+def rswr_solve_noalloc(plan, state, f_a, f_b, n_steps, n0=0):
+    """rswr_solve without receivers or checkpoints, its workspace the
+    library's own device array (no allocation; see include/rswr.h).  The
+    plan must have run a compute call on this device before.  `state`
+    [2, M] is advanced in place."""
+    _check(lib().rswr_solve_noalloc(plan.handle, _dev(state, plan.dtype, 2 * plan.M, "state"),
+                                    _dev(f_a, plan.dtype, n0 + n_steps + 1, "f_a"),
+                                    _dev(f_b, plan.dtype, n0 + n_steps + 1, "f_b"), int(n0),
+                                    int(n_steps), _stream()), "rswr_solve_noalloc")
+    return state
 
 
 def rswr_adjoint_fused(plan):

@@ -26,7 +26,9 @@ SOURCES = ["rswr_fused_ext_f32.hip", "rswr_fused_ext_f64.hip", "rswr_fused_gen.h
 
 def _compile(src, verbose):
     obj = os.path.join(CSRC, os.path.splitext(src)[0] + ".o")
-    lang = ["-x", "hip"] if src.endswith(".hip") else []
+    # every source is a HIP translation unit (the host driver holds the
+    # device array of the no-allocation solve)
+    lang = ["-x", "hip"]
     cmd = [HIPCC, *FLAGS, *lang, "-c", os.path.join(CSRC, src), "-o", obj]
     res = subprocess.run(cmd, capture_output=True, text=True)
     err = "\n".join(l for l in res.stderr.splitlines()

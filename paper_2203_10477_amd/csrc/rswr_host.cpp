@@ -65,6 +65,12 @@ struct GraphEntry {
   hipGraphExec_t exec;
 };
 
+// Workspace of rswr_solve_noalloc: a file-scope device array, one copy per
+// GPU, held until the process ends.  Host code never names it directly: its
+// device address on each GPU comes from hipGetSymbolAddress (scratch_on).
+constexpr size_t kScratchBytes = RSWR_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
 }  // namespace
 
 struct rswr_plan_s {
@@ -1614,6 +1620,80 @@ rswr_status_t rswr_solve(rswr_plan_t p, void* state, const void* f_a, const void
                      lists.n_gen,
                      lists.n_fast};
   return run_graph(p, d, key, enqueue, s);
+}
+
+}  // extern "C"
+
+namespace {
+
+// Device address of `scratch` on the current device, looked up once per
+// device (with that device current) and kept.
+rswr_status_t scratch_on(int dev, char** out) {
+  static std::mutex mu;
+  static std::map<int, char*> addr;
+  std::lock_guard<std::mutex> g(mu);
+  auto it = addr.find(dev);
+  if (it == addr.end()) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || ptr == nullptr)
+      return hip_fail(e != hipSuccess ? e : hipErrorInvalidSymbol,
+                      "hipGetSymbolAddress(scratch)");
+    it = addr.emplace(dev, static_cast<char*>(ptr)).first;
+  }
+  *out = it->second;
+  return RSWR_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+rswr_status_t rswr_solve_noalloc(rswr_plan_t p, void* state, const void* f_a, const void* f_b,
+                                 int64_t n0, int64_t n_steps, void* stream) {
+  if (!p || !state || !f_a || !f_b) return fail(RSWR_ERR_INVALID_ARG, "null pointer");
+  if (n0 < 0 || n_steps < 0) return fail(RSWR_ERR_INVALID_ARG, "negative n0 or n_steps");
+  if (!p->src_node.empty() && n0 + n_steps > p->src_ld)
+    return fail(RSWR_ERR_INVALID_ARG, "the solve runs past the source samples (src_ld)");
+  const WsLayout L = ws_layout(*p, 0);
+  if (L.total > kScratchBytes)
+    return fail(RSWR_ERR_NOMEM, "rswr_solve_noalloc: this plan needs " +
+                                    std::to_string(L.total) + " bytes of workspace, beyond "
+                                    "the library's scratch of " +
+                                    std::to_string(kScratchBytes) + " bytes per GPU");
+  if (n_steps == 0) return RSWR_OK;
+  int dev = 0;
+  RSWR_HIP(hipGetDevice(&dev));
+  DevTables* d = nullptr;
+  {
+    std::lock_guard<std::mutex> g(p->mu);
+    auto it = p->dev.find(dev);
+    if (it == p->dev.end())
+      return fail(RSWR_ERR_UNSUPPORTED,
+                  "rswr_solve_noalloc: the plan's tables are not on this device yet (they "
+                  "are uploaded by the plan's first other compute call here)");
+    d = &it->second;
+  }
+  char* ws = nullptr;
+  rswr_status_t st = scratch_on(dev, &ws);
+  if (st != RSWR_OK) return st;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  Lists lists;
+  const int32_t n_all = static_cast<int32_t>(p->tiles.size());
+  lists.gen = d->idx;
+  lists.n_gen = p->n_gen;
+  lists.fast = d->idx + p->n_gen;
+  lists.n_fast = n_all - p->n_gen;
+  if (p->mode == RSWR_SPAN_QUIET)
+    return p->dtype == RSWR_F64
+               ? enqueue_solve_quiet<double>(p, *d, state, f_a, f_b, n0, n_steps, lists,
+                                             nullptr, ws, L, s)
+               : enqueue_solve_quiet<float>(p, *d, state, f_a, f_b, n0, n_steps, lists,
+                                            nullptr, ws, L, s);
+  return p->dtype == RSWR_F64 ? enqueue_solve<double>(p, *d, state, f_a, f_b, n0, n_steps,
+                                                      lists, nullptr, ws, L, nullptr, s)
+                              : enqueue_solve<float>(p, *d, state, f_a, f_b, n0, n_steps,
+                                                     lists, nullptr, ws, L, nullptr, s);
 }
 
 rswr_status_t rswr_adjoint_fused(rswr_plan_t p, int32_t* fused) {
