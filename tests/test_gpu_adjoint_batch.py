@@ -2,7 +2,8 @@
 (rswr_solve_adjoint_batch): every problem's dJ/df_A, dJ/df_B and dJ/dlam are
 bit-identical to its own forward solve with span checkpoints followed by
 rswr_solve_adjoint, for any group size and segment length; one problem also
-against the oracle's reverse mode (FP64, <= 1e-12)."""
+against the oracle's reverse mode in the same precision (FP64: 1e-12
+relative; FP32: 1e-5, dJ/dlam against the magnitude sum of its terms)."""
 import numpy as np
 import pytest
 import torch
@@ -72,13 +73,18 @@ def test_adjoint_batch_equals_single_solves(dtype, case):
             assert torch.equal(ga[i], sa), (group, seg, i)
             assert torch.equal(gb[i], sb), (group, seg, i)
             assert torch.equal(gl[i], sl), (group, seg, i)
+    # one problem against the oracle's reverse mode in the same precision
+    npdt = NP[dtype]
+    ra, rb, rl, sa = oracle.adjoint(M, plan.info["lambda"], plan.info["dx"],
+                                    fa_np[1, :n_steps + 1].astype(npdt),
+                                    fb_np[1, :n_steps + 1].astype(npdt), n_steps, rec,
+                                    gtr[1].cpu().numpy(), dtype=npdt, terms=True)
+    a = ga[1].cpu().numpy().astype(np.float64)
+    tol = 1e-12 if dtype == torch.float64 else 1e-5
+    assert np.linalg.norm(a - ra) <= tol * np.linalg.norm(ra)
     if dtype == torch.float64:
-        ra, rb, rl = oracle.adjoint(M, plan.info["lambda"], plan.info["dx"],
-                                    fa_np[1, :n_steps + 1], fb_np[1, :n_steps + 1], n_steps,
-                                    rec, gtr[1].cpu().numpy())
-        a = ga[1].cpu().numpy()
-        assert np.linalg.norm(a - ra) <= 1e-12 * np.linalg.norm(ra)
-        assert abs(gl[1].item() - rl) <= 1e-9 * abs(rl)
+        assert abs(gl[1].item() - rl) <= 1e-12 * abs(rl)
+    assert abs(gl[1].item() - rl) <= tol * sa
 
 
 def test_adjoint_batch_rejections():
