@@ -430,6 +430,8 @@ int SFX(oracle_adjoint)(int64_t M, double lam, double dx, const real* fa,
                         int64_t trace_ld, int32_t ck, real* grad_fa,
                         real* grad_fb, double* grad_lam, double* sum_abs) {
   if (ck < 1 || M < 3) return -1;
+  for (int32_t r = 0; r < n_rec; ++r)
+    if (rec[r] < 0 || rec[r] > M - 1) return -3;
   const coef_t c = make_coef(lam, dx);
   const int64_t nck = n_steps / ck + 1;
   /* checkpoint m holds levels m*ck - 1 and m*ck */

@@ -208,6 +208,14 @@ __device__ __forceinline__ T adj_frame_step(const T (&cur)[2], T (&old)[2],
 // W^L by the leapfrog (+ sources, general tiles), the dJ/dlam terms of the
 // stored interior nodes, then U^{L-2} by the reversed leapfrog.
 // ---------------------------------------------------------------------------
+// Per-lane element mask: bit e % 32 of word e / 32 for element e (one word
+// per 32 elements, so shapes with more than 32 nodes per lane are covered).
+template <int MPT>
+struct ElemMask {
+  uint32_t w[(MPT + 31) / 32];
+  __device__ __forceinline__ bool has(int e) const { return (w[e >> 5] >> (e & 31)) & 1u; }
+};
+
 template <typename T, int NT, int MPT>
 struct AdjCtx {
   T (*edge)[4][NT / 64];
@@ -220,7 +228,7 @@ struct AdjCtx {
   int64_t base;
   int dl, d0, dM, d1, dM2;
   int sb, se, lane, wv, lmode, rmode;
-  uint32_t cnt;  // bit e: element e is stored and interior (enters dJ/dlam)
+  ElemMask<MPT> cnt;  // element e is stored and interior (enters dJ/dlam)
   bool gen, wr_fa, wr_fb;
   RecSlots rs;          // the tile's first sources (GEN, SRC)
   const T (*sg)[kMaxSpan];  // their dJ/dtrace samples of this span, by step
@@ -261,7 +269,7 @@ template <typename T, int MPT, bool GEN>
 __device__ __forceinline__ void lap_and_reverse(const T (&wn)[MPT], const T (&ucur)[MPT],
                                                 T (&uold)[MPT], T L, T R, T c2, T k,
                                                 int dl, int d0, int dM, T ghost, T pin0,
-                                                T pinM, uint32_t cnt, bool rev,
+                                                T pinM, const ElemMask<MPT>& cnt, bool rev,
                                                 double& acc) {
 #pragma unroll
   for (int e = 0; e < MPT; ++e) {
@@ -271,7 +279,7 @@ __device__ __forceinline__ void lap_and_reverse(const T (&wn)[MPT], const T (&uc
     const T s = ul + ur;
     // s - 2u in one rounding: 2u is exact, so the fused form rounds the same
     const T lap = fma_(T(-2), ucur[e], s);
-    const T lapm = ((cnt >> e) & 1u) ? lap : T(0);
+    const T lapm = cnt.has(e) ? lap : T(0);
     acc = __builtin_fma(static_cast<double>(wn[e]), static_cast<double>(lapm), acc);
     if (rev) {
       T v = fma_(c2, s, fma_(k, ucur[e], -uold[e]));
@@ -607,14 +615,14 @@ __global__ __launch_bounds__(NT) void k_adj_update(const AdjUpdateArgs<T> p0) {
     }
     __syncthreads();
   }
-  uint32_t cnt = 0;
+#pragma unroll
+  for (int i = 0; i < (MPT + 31) / 32; ++i) c.cnt.w[i] = 0u;
 #pragma unroll
   for (int e = 0; e < MPT; ++e) {
     const int64_t j = c.base + e;
     const bool counts = j >= tl.out_lo && j <= tl.out_hi && j > 0 && j < M - 1;
-    cnt |= counts ? (1u << e) : 0u;
+    c.cnt.w[e >> 5] |= counts ? (1u << (e & 31)) : 0u;
   }
-  c.cnt = cnt;
 
   double acc = 0.0;
   int tau;

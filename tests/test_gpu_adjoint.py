@@ -219,3 +219,29 @@ def test_fused_adjoint_equals_two_launch(case, dtype):
     assert np.array_equal(out[0][0], out[1][0])
     assert np.array_equal(out[0][1], out[1][1])
     assert out[0][2] == out[1][2]
+
+
+@pytest.mark.parametrize("tile", [(64, 33), (128, 33), (64, 65)])
+def test_adjoint_fp32_wide_tiles(tile):
+    """Shapes with more than 32 nodes per lane (the large case's 64x33):
+    every stored interior node's dJ/dlam term counts.  Against the oracle's
+    float build."""
+    M, N, P, n_steps = 20001, 8, 64, 400
+    say("adjoint fp32 wide tile", tile)
+    dt = torch.float32
+    plan = rs.Plan(M, N, P, tile=tile, dtype=dt)
+    g = np.random.default_rng(17)
+    t = np.arange(n_steps + 1) * 0.9 / (M - 1)
+    fa = (np.sin(2 * np.pi * 5 * t / t[-1]) * np.exp(-t)).astype(np.float32)
+    fa[0] = 0.0
+    fb = np.zeros_like(fa)
+    rec = np.array([5, 120, 260, 2500, 2501, 9000], np.int64)
+    w = g.standard_normal((len(rec), n_steps)).astype(np.float32)
+    _, ck = forward_gpu(plan, fa, fb, n_steps, rec, dt)
+    ga, _, gl = rs.rswr_solve_adjoint(plan, ck, dev(fa, dt), dev(fb, dt), n_steps, rec,
+                                      dev(w, dt))
+    ra, _, rl, sa = oracle.adjoint(M, plan.info["lambda"], plan.info["dx"], fa, fb, n_steps,
+                                   rec, w, dtype=np.float32, terms=True)
+    assert rl != 0.0
+    assert np.linalg.norm(ga.cpu().numpy().astype(np.float64) - ra) <= 1e-5 * np.linalg.norm(ra)
+    assert abs(gl.item() - rl) <= 1e-5 * sa, (gl.item(), rl, sa)
