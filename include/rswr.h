@@ -120,6 +120,14 @@ typedef struct {
   const int64_t* src_node;  /* (host) copied by rswr_plan */
   const void* src_amp;      /* (device) [n_src][src_ld] */
   int64_t src_ld;
+  /* 1: rswr_solve without receivers runs the whole loop of Sec. 2.6 as one
+   * launch where the plan allows it (rswr_plan_info_t.one_launch) and its
+   * tiles all fit on the device at once: each tile waits only for its
+   * neighbours' previous span, with no launch boundary between spans.  The
+   * results are identical; on one MI355X the span-by-span graph is the
+   * faster form for the configurations measured, so 0 (span by span) is the
+   * default. */
+  int32_t one_launch;
 } rswr_desc_t;
 
 typedef struct {
@@ -137,6 +145,10 @@ typedef struct {
                                wave holding that end (fixed span S <= 63,
                                every input at a region end); results are
                                identical either way */
+  int32_t one_launch;       /* 1: the plan asked for the one-launch loop
+                               (rswr_desc_t.one_launch) and can run it (a
+                               fused plan without general tiles or
+                               sources) */
 } rswr_plan_info_t;
 
 /* (host) Kernel shapes built into the library: up to `cap` (threads per

@@ -43,7 +43,7 @@ class _Desc(ctypes.Structure):
                 ("tile_threads", ctypes.c_int32), ("tile_per_thread", ctypes.c_int32),
                 ("no_fuse", ctypes.c_int32), ("n_src", ctypes.c_int32),
                 ("src_node", ctypes.c_void_p), ("src_amp", ctypes.c_void_p),
-                ("src_ld", ctypes.c_int64)]
+                ("src_ld", ctypes.c_int64), ("one_launch", ctypes.c_int32)]
 
 
 class _Info(ctypes.Structure):
@@ -53,7 +53,8 @@ class _Info(ctypes.Structure):
                 ("flux_ld", ctypes.c_int32), ("n_tiles", ctypes.c_int32),
                 ("tile_threads", ctypes.c_int32), ("tile_per_thread", ctypes.c_int32),
                 ("dx", ctypes.c_double), ("dt", ctypes.c_double),
-                ("lambda_", ctypes.c_double), ("fused", ctypes.c_int32)]
+                ("lambda_", ctypes.c_double), ("fused", ctypes.c_int32),
+                ("one_launch", ctypes.c_int32)]
 
 
 def lib():
@@ -128,13 +129,15 @@ class Plan:
     sources = (nodes, amp): interior point sources (the pulse sources of
     Sec. 4): nodes in 1..M-2 (host), amp a device tensor [n_src, ld] of the
     plan's dtype; the step from level n to n+1 adds amp[q, n] at nodes[q].
-    The plan keeps a reference to amp.
+    The plan keeps a reference to amp.  one_launch=True asks rswr_solve
+    (without receivers) to run the whole span loop as one launch where the
+    plan allows it (info["one_launch"]); results are identical.
     """
 
     def __init__(self, n_points, n_sub, overlap, a=1.0, courant=0.9,
                  courant_frac=(9, 10), x_a=0.0, x_b=1.0, a_ref=0.0, span=0,
                  span_mode=FIXED, beta=0.1, dtype=torch.float64, windows=None,
-                 tile=None, fuse=True, sources=None):
+                 tile=None, fuse=True, sources=None, one_launch=False):
         L = lib()
         d = _Desc()
         d.x_a, d.x_b, d.n_points = float(x_a), float(x_b), int(n_points)
@@ -154,6 +157,7 @@ class Plan:
         if tile is not None:
             d.tile_threads, d.tile_per_thread = int(tile[0]), int(tile[1])
         d.no_fuse = 0 if fuse else 1
+        d.one_launch = 1 if one_launch else 0
         self._src = None
         if sources is not None:
             nodes = np.ascontiguousarray(np.asarray(sources[0], np.int64).reshape(-1))

@@ -21,7 +21,7 @@ FLAGS = [
 SOURCES = ["rswr_fused_ext_f32.hip", "rswr_fused_ext_f64.hip", "rswr_fused_gen.hip",
            "rswr_adjoint_fused_f64.hip", "rswr_adjoint_fused_f32.hip", "rswr_adjoint.hip",
            "rswr_fused_plain.hip", "rswr_kernels.hip", "rswr_batch.hip",
-           "rswr_fused.hip", "rswr_host.cpp"]
+           "rswr_fused.hip", "rswr_persist.hip", "rswr_host.cpp"]
 
 
 def _compile(src, verbose):

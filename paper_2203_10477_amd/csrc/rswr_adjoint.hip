@@ -194,6 +194,7 @@ template hipError_t launch_adj_finish<double>(double*, double*, const double*, i
                                               const int64_t*, int32_t, int64_t, int64_t,
                                               const double*, int32_t, double, double*,
                                               hipStream_t);
+template hipError_t launch_fill<int32_t>(int32_t*, int32_t, int64_t, hipStream_t);
 template hipError_t launch_fill<float>(float*, float, int64_t, hipStream_t);
 template hipError_t launch_fill<double>(double*, double, int64_t, hipStream_t);
 

@@ -200,23 +200,65 @@ constexpr int kBufDword3 = 0x00020000;
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t range_rsrc(void* base, int bytes) {
   return __builtin_amdgcn_make_buffer_rsrc(base, 0, bytes, kBufDword3);
 }
+
+// Cache policy of the state loads and stores that the tiles of one launch
+// exchange with each other (the one-launch span loop): device scope (sc1),
+// so a value stored on one XCD is seen by a load on another without writing
+// back or invalidating the XCDs' separate L2 caches.  0: the default policy.
+constexpr int kCohAux = 16;
+
+template <int AUX = 0>
 __device__ __forceinline__ void range_store(float v, __amdgpu_buffer_rsrc_t r, int off) {
   // the whole offset sits in the vector operand (no folded instruction
   // offset), so the range check sees exactly this value
   asm("" : "+v"(off));
-  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, off, 0, 0);
+  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, off, 0, AUX);
 }
+template <int AUX = 0>
 __device__ __forceinline__ void range_store(double v, __amdgpu_buffer_rsrc_t r, int off) {
   typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
   asm("" : "+v"(off));
-  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, off, 0, 0);
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, off, 0, AUX);
+}
+
+// Device-coherent load of element idx of a row seen through `r` (a range
+// resource over the row): indices outside the row read 0.
+template <typename T>
+__device__ __forceinline__ T ld_coh(__amdgpu_buffer_rsrc_t r, int64_t idx);
+template <>
+__device__ __forceinline__ float ld_coh<float>(__amdgpu_buffer_rsrc_t r, int64_t idx) {
+  int off = static_cast<int>(idx * 4);
+  asm("" : "+v"(off));
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, kCohAux));
+}
+template <>
+__device__ __forceinline__ double ld_coh<double>(__amdgpu_buffer_rsrc_t r, int64_t idx) {
+  int off = static_cast<int>(idx * 8);
+  asm("" : "+v"(off));
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, kCohAux));
+}
+
+// A range resource over row `row` (0 or 1) of a [2][M] state.
+template <typename T>
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t state_row(const T* st, int64_t M, int row) {
+  return range_rsrc(const_cast<T*>(st) + row * M, static_cast<int>(M * sizeof(T)));
+}
+
+// load_level through a range resource over the row with the device-coherent
+// policy; nodes outside [0, M) read 0.
+template <typename T, int NT, int MPT>
+__device__ __forceinline__ void load_level_coh(__amdgpu_buffer_rsrc_t r, int64_t a,
+                                               T (&tmp)[MPT]) {
+  const int tid = static_cast<int>(threadIdx.x);
+#pragma unroll
+  for (int it = 0; it < MPT; ++it) tmp[it] = ld_coh<T>(r, a + it * NT + tid);
 }
 
 // This lane's nodes -> LDS -> unit-stride stores of the stored range
 // [a + xlo, a + xhi] (offsets relative to the region start).  Every row of
 // NT nodes stores unmasked through a resource covering exactly that range;
 // nodes outside it are dropped by the range check.
-template <typename T, int NT, int MPT>
+template <typename T, int NT, int MPT, int AUX = 0>
 __device__ __forceinline__ void stage_out(T* __restrict__ dst, int64_t a, int xlo,
                                           int xhi, T* st, const T (&v)[MPT]) {
   const int tid = static_cast<int>(threadIdx.x);
@@ -232,7 +274,7 @@ __device__ __forceinline__ void stage_out(T* __restrict__ dst, int64_t a, int xl
     for (int it = 0; it < MPT; ++it) tmp[it] = st[lds_slot<MPT>(it * NT + tid)];
 #pragma unroll
     for (int it = 0; it < MPT; ++it)
-      range_store(tmp[it], r, base + it * NT * static_cast<int>(sizeof(T)));
+      range_store<AUX>(tmp[it], r, base + it * NT * static_cast<int>(sizeof(T)));
   }
   __syncthreads();
 }

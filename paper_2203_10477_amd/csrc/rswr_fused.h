@@ -68,7 +68,8 @@ struct FusedCtx {
 // o - kFrameHalf + 2l and the next one, at the span's first level (cur) and
 // the one before (old); nodes beyond the window take their mirror image
 // (clamped into the window), a value the sample never sees.
-template <typename T>
+// COH: device-coherent loads (the one-launch loop).
+template <typename T, bool COH = false>
 __device__ __forceinline__ void frame_load(const UpdateArgs<T>& p, int64_t o, int w,
                                            int lane, T (&cur)[2], T (&old)[2]) {
   const int64_t wlo = p.lo[w], whi = p.hi[w];
@@ -77,8 +78,13 @@ __device__ __forceinline__ void frame_load(const UpdateArgs<T>& p, int64_t o, in
     int64_t j = o - kFrameHalf + 2 * lane + e;
     j = (j < wlo) ? 2 * wlo - j : ((j > whi) ? 2 * whi - j : j);
     j = j < wlo ? wlo : (j > whi ? whi : j);
-    cur[e] = p.state_in[p.M + j];
-    old[e] = p.state_in[j];
+    if constexpr (COH) {
+      cur[e] = ld_coh<T>(state_row(p.state_in, p.M, 1), j);
+      old[e] = ld_coh<T>(state_row(p.state_in, p.M, 0), j);
+    } else {
+      cur[e] = p.state_in[p.M + j];
+      old[e] = p.state_in[j];
+    }
   }
 }
 
@@ -241,7 +247,8 @@ __device__ __forceinline__ void fused_step(const UpdateArgs<T>& p,
   }
 }
 
-template <typename T, int NT, int MPT, bool GEN, bool REC, bool SRC, bool HL, bool HR>
+template <typename T, int NT, int MPT, bool GEN, bool REC, bool SRC, bool HL, bool HR,
+          bool COH>
 __device__ __forceinline__ void fused_run(const UpdateArgs<T>& p, const Tile& tl,
                                           const FusedCtx<T, NT, MPT>& c, int S,
                                           T (&u)[MPT], T (&uo)[MPT]) {
@@ -251,8 +258,8 @@ __device__ __forceinline__ void fused_run(const UpdateArgs<T>& p, const Tile& tl
   T tr[kRecSlots];
 #pragma unroll
   for (int q = 0; q < kRecSlots; ++q) tr[q] = T(0);
-  if constexpr (HL) frame_load(p, tl.a, tl.window - 1, c.lane, lc, lo);
-  if constexpr (HR) frame_load(p, tl.a + TM - 1, tl.window + 1, c.lane, rc, ro);
+  if constexpr (HL) frame_load<T, COH>(p, tl.a, tl.window - 1, c.lane, lc, lo);
+  if constexpr (HR) frame_load<T, COH>(p, tl.a + TM - 1, tl.window + 1, c.lane, rc, ro);
   int s = 0;
   for (; s + 1 < S; s += 2) {
     fused_step<T, NT, MPT, GEN, REC, SRC, HL, HR>(p, c, u, uo, lc, lo, rc, ro, fl, fr, tr, s);
@@ -276,8 +283,10 @@ __device__ __forceinline__ void fused_run(const UpdateArgs<T>& p, const Tile& tl
 // store.  `st` is the LDS staging buffer, `edge` the cross-wave slots.
 // GEN: node 0 may lie inside the region (per-element Dirichlet treatment).
 // REC: the tile may record receivers.  SRC: the tile and its frames may
-// inject interior sources.
-template <typename T, int NT, int MPT, bool GEN, bool REC, bool SRC>
+// inject interior sources.  COH: every state load and store with the
+// device-coherent policy (the one-launch loop, where tiles exchange the
+// state within one launch).
+template <typename T, int NT, int MPT, bool GEN, bool REC, bool SRC, bool COH = false>
 __device__ __forceinline__ void fused_tile(const UpdateArgs<T>& p, const Tile& tl, int slot,
                                            int S, T* st, T (*edge)[2][NT / 64]) {
   constexpr int NW = NT / 64;
@@ -288,8 +297,13 @@ __device__ __forceinline__ void fused_tile(const UpdateArgs<T>& p, const Tile& t
   T u[MPT], uo[MPT];
   {
     T t1[MPT], t0[MPT];
-    load_level<T, NT, MPT>(p.state_in + p.M, tl.a, p.M, inside, t1);  // level n0
-    load_level<T, NT, MPT>(p.state_in, tl.a, p.M, inside, t0);        // level n0-1
+    if constexpr (COH) {
+      load_level_coh<T, NT, MPT>(state_row(p.state_in, p.M, 1), tl.a, t1);  // level n0
+      load_level_coh<T, NT, MPT>(state_row(p.state_in, p.M, 0), tl.a, t0);  // level n0-1
+    } else {
+      load_level<T, NT, MPT>(p.state_in + p.M, tl.a, p.M, inside, t1);  // level n0
+      load_level<T, NT, MPT>(p.state_in, tl.a, p.M, inside, t0);        // level n0-1
+    }
     transpose_in<T, NT, MPT>(t1, st, u);
     transpose_in<T, NT, MPT>(t0, st, uo);
   }
@@ -324,8 +338,16 @@ __device__ __forceinline__ void fused_tile(const UpdateArgs<T>& p, const Tile& t
     // node 0 / M-1 at level n0 (from the state) and n0+1.. (from f_A, f_B)
     const int l = c.lane;
     T a = T(0), b = T(0);
-    if ((GEN || dirL || fA) && l <= S) a = (l == 0) ? p.state_in[p.M] : p.fa[p.n0 + l];
-    if ((GEN || dirR || fB) && l <= S) b = (l == 0) ? p.state_in[2 * p.M - 1] : p.fb[p.n0 + l];
+    if constexpr (COH) {
+      if ((dirL || fA) && l <= S)
+        a = (l == 0) ? ld_coh<T>(state_row(p.state_in, p.M, 1), 0) : p.fa[p.n0 + l];
+      if ((dirR || fB) && l <= S)
+        b = (l == 0) ? ld_coh<T>(state_row(p.state_in, p.M, 1), p.M - 1) : p.fb[p.n0 + l];
+    } else {
+      if ((GEN || dirL || fA) && l <= S) a = (l == 0) ? p.state_in[p.M] : p.fa[p.n0 + l];
+      if ((GEN || dirR || fB) && l <= S)
+        b = (l == 0) ? p.state_in[2 * p.M - 1] : p.fb[p.n0 + l];
+    }
     c.vA = a;
     c.vB = b;
   }
@@ -427,40 +449,47 @@ __device__ __forceinline__ void fused_tile(const UpdateArgs<T>& p, const Tile& t
   const bool hr = c.wv == NW - 1 && tl.rmode == kEndGhost;
   if (hl) {
     if (hr)
-      fused_run<T, NT, MPT, GEN, REC, SRC, true, true>(p, tl, c, S, u, uo);
+      fused_run<T, NT, MPT, GEN, REC, SRC, true, true, COH>(p, tl, c, S, u, uo);
     else
-      fused_run<T, NT, MPT, GEN, REC, SRC, true, false>(p, tl, c, S, u, uo);
+      fused_run<T, NT, MPT, GEN, REC, SRC, true, false, COH>(p, tl, c, S, u, uo);
   } else {
     if (hr)
-      fused_run<T, NT, MPT, GEN, REC, SRC, false, true>(p, tl, c, S, u, uo);
+      fused_run<T, NT, MPT, GEN, REC, SRC, false, true, COH>(p, tl, c, S, u, uo);
     else
-      fused_run<T, NT, MPT, GEN, REC, SRC, false, false>(p, tl, c, S, u, uo);
+      fused_run<T, NT, MPT, GEN, REC, SRC, false, false, COH>(p, tl, c, S, u, uo);
   }
 
   const int64_t rlo = tl.out_lo > tl.a ? tl.out_lo : tl.a;
   const int64_t rhi = tl.out_hi < tl.a + TM - 1 ? tl.out_hi : tl.a + TM - 1;
   const int xlo = static_cast<int>(rlo - tl.a);
   const int xhi = static_cast<int>(rhi - tl.a);
+  constexpr int AUX = COH ? kCohAux : 0;
   if (S & 1) {  // uo = level n0+S, u = n0+S-1
-    stage_out<T, NT, MPT>(p.state_out, tl.a, xlo, xhi, st, u);
-    stage_out<T, NT, MPT>(p.state_out + p.M, tl.a, xlo, xhi, st, uo);
+    stage_out<T, NT, MPT, AUX>(p.state_out, tl.a, xlo, xhi, st, u);
+    stage_out<T, NT, MPT, AUX>(p.state_out + p.M, tl.a, xlo, xhi, st, uo);
   } else {
-    stage_out<T, NT, MPT>(p.state_out, tl.a, xlo, xhi, st, uo);
-    stage_out<T, NT, MPT>(p.state_out + p.M, tl.a, xlo, xhi, st, u);
+    stage_out<T, NT, MPT, AUX>(p.state_out, tl.a, xlo, xhi, st, uo);
+    stage_out<T, NT, MPT, AUX>(p.state_out + p.M, tl.a, xlo, xhi, st, u);
   }
   // Dirichlet nodes next to the region
+  auto put = [&](int64_t j, T v) {
+    if constexpr (COH)
+      range_store<AUX>(v, range_rsrc(p.state_out + j, static_cast<int>(sizeof(T))), 0);
+    else
+      p.state_out[j] = v;
+  };
   if (dirL && c.wv == 0) {
     const T a1 = rd_lane(c.vA, S - 1), a2 = rd_lane(c.vA, S);
     if (tid == 0) {
-      p.state_out[0] = a1;
-      p.state_out[p.M] = a2;
+      put(0, a1);
+      put(p.M, a2);
     }
   }
   if (dirR && c.wv == NW - 1) {
     const T b1 = rd_lane(c.vB, S - 1), b2 = rd_lane(c.vB, S);
     if (tid == NT - 1) {
-      p.state_out[p.M - 1] = b1;
-      p.state_out[2 * p.M - 1] = b2;
+      put(p.M - 1, b1);
+      put(2 * p.M - 1, b2);
     }
   }
 }

@@ -53,6 +53,8 @@ struct DevTables {
   int32_t* src_ptr = nullptr;  // per-tile interior sources (plans with sources)
   int64_t* src_node = nullptr;
   int32_t* src_id = nullptr;
+  int32_t* dep_ptr = nullptr;  // waits of the one-launch loop (plans with persist_ok)
+  int32_t* dep = nullptr;
   hipStream_t capture = nullptr;
 };
 
@@ -93,6 +95,10 @@ struct rswr_plan_s {
   std::vector<int32_t> src_ptr;  // [3 * n_tiles + 1]
   std::vector<int64_t> src_tnode;
   std::vector<int32_t> src_tid;
+  // the one-launch loop (rswr_persist.hip): plain fused plans; per tile the
+  // tiles it waits for before each span (CSR)
+  bool persist_ok = false;
+  std::vector<int32_t> dep_ptr, dep;
   std::mutex mu;
   std::map<int, DevTables> dev;
   std::vector<GraphEntry> graphs;
@@ -391,6 +397,61 @@ rswr_status_t plan_sources(rswr_plan_s& p, const rswr_desc_t& D) {
   return RSWR_OK;
 }
 
+// Waits of the one-launch loop.  Tile t reads the glued state over its
+// region and, at an input end, over the prediction frame around it
+// ([o - kFrameHalf, o + kFrameHalf - 1]); it writes its stored range and the
+// Dirichlet node next to a Dirichlet end.  Before span k, t waits for every
+// tile whose written nodes it reads (they must have finished span k-1) and
+// for every tile that reads t's written nodes (they must have read the
+// buffer t is about to overwrite).  The written ranges are disjoint and
+// cover the grid, so each read range meets a contiguous run of them.
+void build_deps(rswr_plan_s& p) {
+  const int64_t TM = int64_t(p.threads) * p.per_thread;
+  const int64_t H = rswr::kFrameHalf;
+  const int32_t n = static_cast<int32_t>(p.tiles.size());
+  std::vector<int64_t> rlo(n), rhi(n), wlo(n), whi(n);
+  for (int32_t t = 0; t < n; ++t) {
+    const Tile& x = p.tiles[t];
+    rlo[t] = std::max<int64_t>(0, x.lmode == rswr::kEndGhost ? x.a - H : x.a);
+    rhi[t] = std::min<int64_t>(p.M - 1, x.rmode == rswr::kEndGhost ? x.a + TM - 1 + H - 1
+                                                                     : x.a + TM - 1);
+    wlo[t] = x.lmode == rswr::kEndDirichlet ? 0 : x.out_lo;
+    whi[t] = x.rmode == rswr::kEndDirichlet ? p.M - 1 : x.out_hi;
+  }
+  std::vector<int32_t> order(n);
+  std::iota(order.begin(), order.end(), 0);
+  std::sort(order.begin(), order.end(), [&](int32_t x, int32_t y) { return wlo[x] < wlo[y]; });
+  std::vector<std::vector<int32_t>> adj(n);
+  for (int32_t t = 0; t < n; ++t) {
+    // first written range that may end at or after rlo[t]
+    auto it = std::lower_bound(order.begin(), order.end(), rlo[t],
+                               [&](int32_t u, int64_t v) { return whi[u] < v; });
+    for (; it != order.end() && wlo[*it] <= rhi[t]; ++it) {
+      const int32_t u = *it;
+      if (u == t || whi[u] < rlo[t]) continue;
+      adj[t].push_back(u);
+      adj[u].push_back(t);
+    }
+  }
+  p.dep_ptr.assign(1, 0);
+  p.dep.clear();
+  for (int32_t t = 0; t < n; ++t) {
+    std::sort(adj[t].begin(), adj[t].end());
+    adj[t].erase(std::unique(adj[t].begin(), adj[t].end()), adj[t].end());
+    p.dep.insert(p.dep.end(), adj[t].begin(), adj[t].end());
+    p.dep_ptr.push_back(static_cast<int32_t>(p.dep.size()));
+  }
+}
+
+// Whether a solve without receivers runs as one launch: plans that asked
+// for it and can, when their tiles all fit on the device at once.
+bool use_persist(const rswr_plan_s& p) {
+  if (!p.persist_ok) return false;
+  const int cap = p.dtype == RSWR_F64 ? rswr::persist_capacity<double>(p.threads, p.per_thread)
+                                      : rswr::persist_capacity<float>(p.threads, p.per_thread);
+  return int64_t(p.tiles.size()) <= int64_t(cap);
+}
+
 rswr_status_t ensure_device(rswr_plan_s* p, DevTables** out, int* device) {
   int dev = 0;
   RSWR_HIP(hipGetDevice(&dev));
@@ -424,6 +485,15 @@ rswr_status_t ensure_device(rswr_plan_s* p, DevTables** out, int* device) {
         RSWR_HIP(hipMemcpy(t.src_id, p->src_tid.data(), p->src_tid.size() * sizeof(int32_t),
                            hipMemcpyHostToDevice));
       }
+    }
+    if (p->persist_ok) {
+      RSWR_HIP(hipMalloc(&t.dep_ptr, p->dep_ptr.size() * sizeof(int32_t)));
+      RSWR_HIP(hipMalloc(&t.dep, std::max<size_t>(p->dep.size(), 1) * sizeof(int32_t)));
+      RSWR_HIP(hipMemcpy(t.dep_ptr, p->dep_ptr.data(), p->dep_ptr.size() * sizeof(int32_t),
+                         hipMemcpyHostToDevice));
+      if (!p->dep.empty())
+        RSWR_HIP(hipMemcpy(t.dep, p->dep.data(), p->dep.size() * sizeof(int32_t),
+                           hipMemcpyHostToDevice));
     }
     RSWR_HIP(hipStreamCreateWithFlags(&t.capture, hipStreamNonBlocking));
     it = p->dev.emplace(dev, t).first;
@@ -548,7 +618,7 @@ size_t elem_size(const rswr_plan_s& p) { return p.dtype == RSWR_F64 ? 8 : 4; }
 
 struct WsLayout {
   size_t state = 0, flux = 0, gen_idx = 0, fast_idx = 0, rec_ptr = 0, rec_node = 0,
-         rec_id = 0, ctl = 0, total = 0;
+         rec_id = 0, ctl = 0, flags = 0, total = 0;
 };
 
 WsLayout ws_layout(const rswr_plan_s& p, int32_t n_rec) {
@@ -575,6 +645,8 @@ WsLayout ws_layout(const rswr_plan_s& p, int32_t n_rec) {
   off += round_up(size_t(std::max(n_rec, 1)) * sizeof(int32_t), 256);
   w.ctl = off;  // control block of an adaptive solve
   off += round_up(sizeof(rswr::QuietCtl), 256);
+  w.flags = off;  // one-launch loop: spans finished per tile, then the error word
+  off += round_up((nt + 1) * sizeof(int32_t), 256);
   w.total = off;
   return w;
 }
@@ -593,7 +665,7 @@ template <typename T>
 rswr_status_t enqueue_solve(rswr_plan_s* p, const DevTables& d, void* state,
                             const void* fa, const void* fb, int64_t n0, int64_t n_steps,
                             const Lists& lists, void* traces, char* ws, const WsLayout& L,
-                            void* ckpt, hipStream_t s) {
+                            void* ckpt, bool persist, hipStream_t s) {
   const int64_t M = p->M;
   const int64_t K = (n_steps + p->S - 1) / p->S;
   T* const user = static_cast<T*>(state);
@@ -613,6 +685,34 @@ rswr_status_t enqueue_solve(rswr_plan_s* p, const DevTables& d, void* state,
     RSWR_HIP(rswr::launch_copy<T>(buf, user, 2 * M, s));
     x = buf;
     y = user;
+  }
+  if (persist) {
+    // the whole loop in one launch: the tiles wait on each other's counters
+    const int32_t n_all = static_cast<int32_t>(p->tiles.size());
+    int32_t* flags = reinterpret_cast<int32_t*>(ws + L.flags);
+    RSWR_HIP(rswr::launch_fill<int32_t>(flags, 0, n_all + 1, s));
+    rswr::UpdateArgs<T> ua =
+        update_args<T>(*p, d, nullptr, fa, fb, n0, nullptr, nullptr, p->S, nullptr);
+    ua.tile_idx = d.idx;
+    ua.n_tiles = n_all;
+    rswr::PersistArgs<T> q{};
+    q.buf0 = x;
+    q.buf1 = y;
+    q.ck = ck;
+    q.ck_flux = ck_flux;
+    q.flags = flags;
+    q.err = flags + n_all;
+    q.dep_ptr = d.dep_ptr;
+    q.dep = d.dep;
+    q.st_elems = static_cast<int64_t>(st_elems);
+    q.fl_elems = static_cast<int64_t>(fl_elems);
+    q.n0 = n0;
+    q.n_end = n0 + n_steps;
+    q.n_spans = static_cast<int32_t>(K);
+    q.S = p->S;
+    RSWR_HIP(rswr::launch_fused_persist<T>(ua, q, p->threads, p->per_thread, s));
+    if (ck) RSWR_HIP(rswr::launch_copy<T>(user, ck + K * st_elems, 2 * M, s));
+    return RSWR_OK;
   }
   int64_t lev = n0;
   for (int64_t k = 0; k < K; ++k) {
@@ -1269,6 +1369,9 @@ rswr_status_t rswr_plan(const rswr_desc_t* desc, rswr_plan_t* out) {
     delete p;
     return st;
   }
+  p->persist_ok = D.one_launch != 0 && p->fused && p->n_gen == 0 && p->src_node.empty() &&
+                  2 * p->M * int64_t(elem_size(*p)) < (int64_t(1) << 31);
+  if (p->persist_ok) build_deps(*p);
   *out = p;
   return RSWR_OK;
 }
@@ -1290,6 +1393,8 @@ rswr_status_t rswr_plan_destroy(rswr_plan_t p) {
     (void)hipFree(kv.second.src_id);
     (void)hipFree(kv.second.lo);
     (void)hipFree(kv.second.hi);
+    (void)hipFree(kv.second.dep_ptr);
+    (void)hipFree(kv.second.dep);
     if (kv.second.capture) (void)hipStreamDestroy(kv.second.capture);
   }
   for (auto& g : p->graphs) (void)hipGraphExecDestroy(g.exec);
@@ -1314,6 +1419,7 @@ rswr_status_t rswr_plan_info(rswr_plan_t p, rswr_plan_info_t* info) {
   info->dt = p->dt;
   info->lambda = p->lam;
   info->fused = p->fused ? 1 : 0;
+  info->one_launch = p->persist_ok ? 1 : 0;
   return RSWR_OK;
 }
 
@@ -1593,6 +1699,7 @@ rswr_status_t rswr_solve(rswr_plan_t p, void* state, const void* f_a, const void
     lists.rec_id = reinterpret_cast<const int32_t*>(ws + L.rec_id);
   }
 
+  const bool persist = n_rec == 0 && use_persist(*p);
   auto enqueue = [&](hipStream_t q) {
     if (p->mode == RSWR_SPAN_QUIET)
       return p->dtype == RSWR_F64
@@ -1602,9 +1709,9 @@ rswr_status_t rswr_solve(rswr_plan_t p, void* state, const void* f_a, const void
                                               traces, ws, L, q);
     return p->dtype == RSWR_F64
                ? enqueue_solve<double>(p, *d, state, f_a, f_b, n0, n_steps, lists,
-                                       traces, ws, L, checkpoints, q)
+                                       traces, ws, L, checkpoints, persist, q)
                : enqueue_solve<float>(p, *d, state, f_a, f_b, n0, n_steps, lists,
-                                      traces, ws, L, checkpoints, q);
+                                      traces, ws, L, checkpoints, persist, q);
   };
   const GraphKey key{1,
                      device,
@@ -1618,7 +1725,8 @@ rswr_status_t rswr_solve(rswr_plan_t p, void* state, const void* f_a, const void
                      reinterpret_cast<int64_t>(checkpoints),
                      n_rec > 0,
                      lists.n_gen,
-                     lists.n_fast};
+                     lists.n_fast,
+                     persist};
   return run_graph(p, d, key, enqueue, s);
 }
 
@@ -1690,10 +1798,12 @@ rswr_status_t rswr_solve_noalloc(rswr_plan_t p, void* state, const void* f_a, co
                                              nullptr, ws, L, s)
                : enqueue_solve_quiet<float>(p, *d, state, f_a, f_b, n0, n_steps, lists,
                                             nullptr, ws, L, s);
-  return p->dtype == RSWR_F64 ? enqueue_solve<double>(p, *d, state, f_a, f_b, n0, n_steps,
-                                                      lists, nullptr, ws, L, nullptr, s)
-                              : enqueue_solve<float>(p, *d, state, f_a, f_b, n0, n_steps,
-                                                     lists, nullptr, ws, L, nullptr, s);
+  const bool persist = use_persist(*p);
+  return p->dtype == RSWR_F64
+             ? enqueue_solve<double>(p, *d, state, f_a, f_b, n0, n_steps, lists, nullptr, ws,
+                                     L, nullptr, persist, s)
+             : enqueue_solve<float>(p, *d, state, f_a, f_b, n0, n_steps, lists, nullptr, ws,
+                                    L, nullptr, persist, s);
 }
 
 rswr_status_t rswr_adjoint_fused(rswr_plan_t p, int32_t* fused) {

@@ -118,6 +118,27 @@ struct UpdateArgs {
   T c2, k, q, r;
 };
 
+// The whole span loop in one launch (rswr_persist.hip): span k reads
+// buf0 (k even) or buf1 and writes the other, or, with checkpoints, reads
+// ck[k] and writes ck[k+1] (and its flux rows to ck_flux[k]).  flags[t]
+// counts the spans tile t has finished (zero on entry); dep_ptr / dep list,
+// per tile, the tiles it waits for before each span; err is set if a wait
+// gave up.
+template <typename T>
+struct PersistArgs {
+  T* buf0;
+  T* buf1;
+  T* ck;
+  T* ck_flux;
+  int32_t* flags;
+  int32_t* err;
+  const int32_t* dep_ptr;
+  const int32_t* dep;
+  int64_t st_elems, fl_elems;
+  int64_t n0, n_end;
+  int32_t n_spans, S;
+};
+
 template <typename T>
 struct SelectArgs {
   const T* flux;
@@ -253,6 +274,14 @@ hipError_t launch_fused_batch(const BatchArgs<T>& a, int threads, int per_thread
                               hipStream_t s);
 template <typename T>
 hipError_t launch_copy_many(const CopyJob<T>* jobs, int32_t n_jobs, hipStream_t s);
+// The whole loop in one launch (plain tiles of a fused plan, one work-group
+// per tile, all resident): persist_capacity gives the resident work-groups
+// of the shape's kernel on the current device (0: shape not built).
+template <typename T>
+int persist_capacity(int threads, int per_thread);
+template <typename T>
+hipError_t launch_fused_persist(const UpdateArgs<T>& a, const PersistArgs<T>& q, int threads,
+                                int per_thread, hipStream_t s);
 template <typename T>
 hipError_t launch_select(const SelectArgs<T>& a, hipStream_t s);
 // Adaptive solve on the device: set up the control block, advance it after
