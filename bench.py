@@ -60,27 +60,61 @@ def span_bytes(plan, elem):
     return elem * (2 * sum_n + 2 * M + flux)
 
 
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(prob, target_s):
-    """The CPU oracle's literal RSWR on the first spans of the same workload."""
-    import numpy as np
+    """The CPU oracle on bounded samples of the same workload: its literal
+    RSWR (whole-window predict + update, FP32) on all host threads and on
+    one, and its plain single-domain leapfrog (one thread: the lower bound of
+    any CPU solve).  Each leg runs spans from the state after one warm-up
+    span, for about target_s seconds."""
     import oracle
     lay = oracle.layout(prob.M, prob.N, prob.P)
     S = min(lay.span_cone, oracle.span_paper(prob.P, prob.lam, prob.courant_frac))
     fa, fb = prob.sources()
-    st = prob.state0()
-    t0 = time.perf_counter()
-    st, _, _ = oracle.rswr(lay, prob.lam, prob.dx, fa, fb, S, span=S, state=st)
-    one = time.perf_counter() - t0
-    spans = max(1, min(500, int(target_s / max(one, 1e-3)) - 1))
-    t0 = time.perf_counter()
-    oracle.rswr(lay, prob.lam, prob.dx, fa, fb, spans * S, span=S, state=st, n0=S)
-    dt = time.perf_counter() - t0
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return {"value": prob.M * spans * S / dt / 1e9, "unit": "GLUPS", "cores": threads,
-            "kind": "oracle",
-            "sample": f"literal RSWR (whole-window predict + update, FP32) on all "
-                      f"{prob.N} windows of the same {prob.M}-node workload for {spans} "
-                      f"spans of {S} steps after one warm-up span; {dt:.1f} s"}
+    all_threads = oracle.threads()
+    st, _, _ = oracle.rswr(lay, prob.lam, prob.dx, fa, fb, S, span=S, state=prob.state0())
+
+    def leg(run, first_guess):
+        t0 = time.perf_counter()
+        run(first_guess)
+        one = (time.perf_counter() - t0) / first_guess
+        spans = max(1, min(500, int(target_s / max(one, 1e-4))))
+        t0 = time.perf_counter()
+        run(spans)
+        dt = time.perf_counter() - t0
+        return prob.M * spans * S / dt / 1e9, spans, dt
+
+    rswr_run = lambda k: oracle.rswr(lay, prob.lam, prob.dx, fa, fb, k * S, span=S, state=st,
+                                     n0=S)
+    single_run = lambda k: oracle.single(prob.M, prob.lam, prob.dx, fa, fb, k * S, state=st,
+                                         n0=S)
+    all_v, all_spans, all_dt = leg(rswr_run, 1)
+    oracle.threads(1)
+    try:
+        one_v, one_spans, one_dt = leg(rswr_run, 1)
+        sd_v, sd_spans, sd_dt = leg(single_run, 1)
+    finally:
+        oracle.threads(all_threads)
+    return {"value": round(all_v, 3), "unit": "GLUPS", "cores": all_threads, "kind": "oracle",
+            "sample": f"literal RSWR (whole-window predict + update, FP32) on all {prob.N} "
+                      f"windows of the same {prob.M}-node workload, {all_spans} spans of {S} "
+                      f"steps after one warm-up span, {all_threads} threads, {all_dt:.1f} s",
+            "nproc": os.cpu_count(), "cpu_model": cpu_model(),
+            "legs": {"rswr_all_threads": {"glups": round(all_v, 3), "threads": all_threads,
+                                          "spans": all_spans, "s": round(all_dt, 1)},
+                     "rswr_one_thread": {"glups": round(one_v, 3), "threads": 1,
+                                         "spans": one_spans, "s": round(one_dt, 1)},
+                     "single_domain_one_thread": {"glups": round(sd_v, 3), "threads": 1,
+                                                  "spans": sd_spans, "s": round(sd_dt, 1)}}}
 
 
 def timed(fn, reps):
@@ -108,9 +142,17 @@ def batched_section(reps):
     from paper_2203_10477_amd.autotune import autotune_batch, batch_plans
     probs, clamped = workloads.config3()
     t0 = time.perf_counter()
-    tiles, spans, report = autotune_batch(
-        probs, log=lambda s: print("[batched autotune]", s, file=sys.stderr, flush=True))
+    trials = []
+
+    def log(line):
+        if line.startswith("refine"):
+            trials.append(line)
+        else:
+            print("[batched autotune]", line, file=sys.stderr, flush=True)
+    tiles, spans, report = autotune_batch(probs, log=log)
     tune_s = time.perf_counter() - t0
+    print(f"[batched autotune] {len(trials)} refinement trials in {tune_s:.0f} s",
+          file=sys.stderr, flush=True)
     plans = batch_plans(probs, torch.float32, tiles=tiles, spans=spans)
     b = rs.Batch(plans)
     # all states in one buffer, so one fill restores the start (at rest)
@@ -144,6 +186,88 @@ def batched_section(reps):
             "rounds": max(-(-q.n_steps // s) for q, s in zip(probs, spans)),
             "windows_clamped": clamped, "autotune_s": round(tune_s, 1),
             "shapes": {str(c): f"{v[0][0]}x{v[0][1]}" for c, v in report.items()}}
+
+
+def plain_2p20_section(reps):
+    """The 2^20-node case (64 windows, overlap 64, span 35, 10^4 steps,
+    Ricker source) in FP64 and FP32: the whole solve, tile autotuned on one
+    span, span by span in one recorded graph; beside it the same plan as
+    one launch for the whole loop.  GLUPS and the fraction of the HBM
+    roofline of the algorithmic bytes of the whole solve."""
+    import numpy as np
+    import torch
+    import paper_2203_10477_amd as rs
+    import workloads
+    from paper_2203_10477_amd.autotune import autotune
+    out = {}
+    for name, npdt, dtype, elem in (("fp64", np.float64, torch.float64, 8),
+                                    ("fp32", np.float32, torch.float32, 4)):
+        prob = workloads.config2(npdt)
+        tile, _ = autotune(prob.M, prob.N, prob.P, dtype=dtype, reps=5)
+        fa = torch.as_tensor(prob.sources()[0], device="cuda")
+        fb = torch.as_tensor(prob.sources()[1], device="cuda")
+        st = torch.zeros(2, prob.M, dtype=dtype, device="cuda")
+        zero_ms = timed(lambda: st.zero_(), reps)
+        res = {}
+        for form, one in (("span_by_span", False), ("one_launch", True)):
+            plan = rs.Plan(prob.M, prob.N, prob.P, dtype=dtype, tile=tile, one_launch=one)
+            ws = torch.empty(plan.workspace_bytes(0), dtype=torch.uint8, device="cuda")
+            ms = timed(lambda: (st.zero_(), rs.rswr_solve(plan, st, fa, fb, prob.n_steps,
+                                                           workspace=ws)), reps) - zero_ms
+            if not torch.isfinite(st).all():
+                raise RuntimeError(f"non-finite state after the 2^20-node {name} {form} solve")
+            K = -(-prob.n_steps // plan.span)
+            nbytes = span_bytes(plan, elem) * K
+            res[form] = {"glups": round(prob.M * prob.n_steps / (ms * 1e-3) / 1e9, 2),
+                         "ms": round(ms, 3),
+                         "hbm_frac": round(nbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+        out[name] = {"tile": list(tile), "span": plan.span, "spans": K,
+                     "algorithmic_bytes_per_span": span_bytes(plan, elem), **res}
+    prob = workloads.config2(np.float64)
+    return {"workload": f"plain RSWR {prob.M} nodes, {prob.N} windows, overlap {prob.P}, "
+                        f"{prob.n_steps} steps, Ricker", **out}
+
+
+def spot_check_section(plan32, prob, fa, fb):
+    """FP64 spot check of the large FP32 run on 1% of its spans: at span
+    boundaries k = 0, 100, ..., the run's own FP32 state (the solve
+    restarted at level k S gives the run's bits) is advanced one span in FP32
+    and, from the same state and the same FP32 boundary samples, in FP64 on
+    the GPU (the FP64 span kernel, bitwise equal to the oracle's FP64 span
+    in the tests); the relative L2 difference of the two results."""
+    import torch
+    import paper_2203_10477_amd as rs
+    S = plan32.span
+    n = prob.n_steps
+    K = -(-n // S)
+    plan64 = rs.Plan(prob.M, prob.N, prob.P, dtype=torch.float64)
+    fa64, fb64 = fa.double(), fb.double()
+    st = torch.zeros(2, prob.M, dtype=torch.float32, device="cuda")
+    lev, errs = 0, {}
+    for k in range(0, K, 100):
+        if k * S > lev:
+            rs.rswr_solve(plan32, st, fa, fb, k * S - lev, n0=lev)
+            lev = k * S
+        one = min(S, n - lev)
+        o32 = rs.rswr_span(plan32, st, fa, fb, lev, span=one)
+        o64 = rs.rswr_span(plan64, st.double(), fa64, fb64, lev, span=one)
+        d = (o32.double() - o64).norm() / o64.norm().clamp_min(1e-300)
+        errs[k] = float(d.item())
+    return {"spans_checked": list(errs), "max_rel_l2": max(errs.values()),
+            "rel_l2": {str(k): v for k, v in errs.items()}, "bound": 1e-5,
+            "ok": max(errs.values()) <= 1e-5}
+
+
+def stream_copy_gbs(n_bytes=4 << 30, reps=10):
+    """Achievable HBM bandwidth: a device-to-device copy of n_bytes, read +
+    write bytes per second."""
+    import torch
+    a = torch.empty(n_bytes // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    a.fill_(1.0)
+    ms = timed(lambda: b.copy_(a), reps)
+    del a, b
+    return round(2 * n_bytes / (ms * 1e-3) / 1e9, 1)
 
 
 def adjoint_section(reps):
@@ -347,7 +471,7 @@ def main():
     ap.add_argument("--tile", default="", help="threads x nodes-per-lane, e.g. 320x13 "
                     "(default: autotuned)")
     ap.add_argument("--section", choices=("batched", "adjoint", "sources", "adjoint_batch",
-                                          "quiet"),
+                                          "quiet", "plain_2p20"),
                     default=None,
                     help="run one of the other forms alone and print its figures "
                          "(for profiling)")
@@ -378,6 +502,8 @@ def main():
         elif args.section == "quiet":
             tile = tuple(int(v) for v in args.tile.split("x")) if args.tile else None
             out = quiet_section(reps, tile)
+        elif args.section == "plain_2p20":
+            out = plain_2p20_section(reps)
         else:
             tile = tuple(int(v) for v in args.tile.split("x")) if args.tile else None
             out = sources_section(reps, tile)
@@ -495,7 +621,10 @@ def main():
                  "hbm_frac_whole_step": round(nbytes * n_spans / (ms_step * 1e-3)
                                               / 1e9 / HBM_PEAK_GBS, 4)},
     }
+    line["fp64_spot_check"] = spot_check_section(plan, prob, fa, fb)
+    line["roofline"]["measured_copy_gbs"] = stream_copy_gbs()
     if not args.no_forms:
+        line["plain_2p20"] = plain_2p20_section(max(1, args.steps))
         line["batched"] = batched_section(max(1, args.steps))
         line["batched"]["vs_plain"] = round(line["batched"]["value"] / glups, 4)
         line["adjoint"] = adjoint_section(max(1, args.steps))

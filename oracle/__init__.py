@@ -42,6 +42,8 @@ def _load():
     lib.oracle_check_layout.restype = ctypes.c_int
     lib.oracle_span_cone.argtypes = [i32, vp, vp]
     lib.oracle_span_cone.restype = i32
+    lib.oracle_threads.argtypes = [ctypes.c_int]
+    lib.oracle_threads.restype = ctypes.c_int
     lib.oracle_span_paper.argtypes = [i32, dbl, i32, i32]
     lib.oracle_span_paper.restype = i32
     for suf in ("_f64", "_f32"):
@@ -98,6 +100,12 @@ def _src(src, dtype):
     nodes = _c(np.asarray(src[0], np.int64).reshape(-1))
     amp = _c(np.asarray(src[1]).reshape(len(nodes), -1), dtype)
     return (nodes, amp), len(nodes), _ptr(nodes), _ptr(amp), amp.shape[1]
+
+
+def threads(n=0):
+    """Set the threads of the oracle's parallel loops (n >= 1); returns the
+    number in force."""
+    return int(_load().oracle_threads(int(n)))
 
 
 class Layout:

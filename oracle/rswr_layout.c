@@ -97,3 +97,11 @@ int32_t oracle_span_paper(int32_t P, double lam, int32_t num, int32_t den) {
   while (2.0 * (double)(s + 1) * lam < (double)P) ++s;
   return (int32_t)s;
 }
+
+/* Threads the oracle's parallel loops use from now on (n >= 1); returns the
+ * number in force.  For timing the oracle on one core or on all. */
+#include <omp.h>
+int oracle_threads(int n) {
+  if (n >= 1) omp_set_num_threads(n);
+  return omp_get_max_threads();
+}

@@ -55,6 +55,9 @@ int oracle_check_layout(int64_t M, int32_t N, const int64_t* lo,
  * smallest distance between an input and an output boundary of one window.
  * Returns INT32_MAX for N = 1. */
 int32_t oracle_span_cone(int32_t N, const int64_t* lo, const int64_t* hi);
+/* Threads of the oracle's parallel loops from now on (n >= 1; n < 1 only
+ * queries); returns the number in force. */
+int oracle_threads(int n);
 /* Waveform Time Span Theorem (Sec. 2.4, Eq. (10)) in steps: the largest S
  * with 2 S lam < P; exact integers when lam = num/den is given (num > 0). */
 int32_t oracle_span_paper(int32_t P, double lam, int32_t num, int32_t den);
