@@ -264,13 +264,16 @@ __device__ __forceinline__ void adj_chunk(const T (&cur)[MPT], T (&old)[MPT], T 
 }
 
 // dJ/dlam terms W^L_j (U_{j-1} + U_{j+1} - 2 U_j) of the counted elements,
-// accumulated in double; then (if rev) U^{L-2} into uold.
+// accumulated in double (FP32: a step's terms of this lane summed in FP32,
+// at most MPT of them, then added in double); then (if rev) U^{L-2} into
+// uold.
 template <typename T, int MPT, bool GEN>
 __device__ __forceinline__ void lap_and_reverse(const T (&wn)[MPT], const T (&ucur)[MPT],
                                                 T (&uold)[MPT], T L, T R, T c2, T k,
                                                 int dl, int d0, int dM, T ghost, T pin0,
                                                 T pinM, const ElemMask<MPT>& cnt, bool rev,
                                                 double& acc) {
+  T step = T(0);
 #pragma unroll
   for (int e = 0; e < MPT; ++e) {
     T ul = (e == 0) ? L : ucur[e - 1];
@@ -280,7 +283,10 @@ __device__ __forceinline__ void lap_and_reverse(const T (&wn)[MPT], const T (&uc
     // s - 2u in one rounding: 2u is exact, so the fused form rounds the same
     const T lap = fma_(T(-2), ucur[e], s);
     const T lapm = cnt.has(e) ? lap : T(0);
-    acc = __builtin_fma(static_cast<double>(wn[e]), static_cast<double>(lapm), acc);
+    if constexpr (sizeof(T) == 4)
+      step = fma_(wn[e], lapm, step);
+    else
+      acc = __builtin_fma(static_cast<double>(wn[e]), static_cast<double>(lapm), acc);
     if (rev) {
       T v = fma_(c2, s, fma_(k, ucur[e], -uold[e]));
       if (GEN) {
@@ -290,6 +296,7 @@ __device__ __forceinline__ void lap_and_reverse(const T (&wn)[MPT], const T (&uc
       uold[e] = v;
     }
   }
+  if constexpr (sizeof(T) == 4) acc += static_cast<double>(step);
 }
 
 // GEN: general tiles (per-element treatments at the window's own ends).
