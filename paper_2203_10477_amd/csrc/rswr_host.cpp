@@ -1310,10 +1310,10 @@ rswr_status_t rswr_plan(const rswr_desc_t* desc, rswr_plan_t* out) {
   if (p->mode == RSWR_SPAN_FIXED) {
     if (D.span > 0) {
       if (D.span > p->S_cone) {
+        const std::string msg = "span " + std::to_string(D.span) +
+                                " exceeds the light-cone limit " + std::to_string(p->S_cone);
         delete p;
-        return fail(RSWR_ERR_SPAN, "span " + std::to_string(D.span) +
-                                       " exceeds the light-cone limit " +
-                                       std::to_string(p->S_cone));
+        return fail(RSWR_ERR_SPAN, msg);
       }
       p->S = D.span;
     } else {
