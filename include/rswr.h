@@ -64,7 +64,7 @@ typedef enum {
   RSWR_ERR_NOMEM = 5,       /* host or device allocation failed, or the
                                workspace is too small */
   RSWR_ERR_HIP = 6,         /* HIP runtime error (launch or device fault) */
-  RSWR_ERR_NONFINITE = 7,   /* reserved */
+  /* 7 is not used */
   RSWR_ERR_UNSUPPORTED = 8  /* valid request outside the built kernels */
 } rswr_status_t;
 
@@ -89,8 +89,9 @@ typedef struct {
   double a_ref;             /* speed that fixes dt = courant dx / a_ref;
                                0 means a (then lam = courant) */
   double courant;           /* C in (0, 1] */
-  int32_t courant_num;      /* optional exact C = num/den for the span rule */
-  int32_t courant_den;      /* (0, 0) = use `courant` */
+  int32_t courant_num;      /* optional exact C = num/den for the span rule; */
+  int32_t courant_den;      /* must equal `courant` to rounding (else
+                               INVALID_ARG); (0, 0) = use `courant` */
   int32_t n_sub;            /* N >= 1 windows, Sec. 3 */
   int32_t overlap;          /* P, overlap width in grid intervals, even,
                                Eq. (5); ignored with explicit windows */

@@ -10,6 +10,7 @@ without a GPU for the compute calls) every call raises.
 """
 import ctypes
 import os
+from fractions import Fraction
 
 import numpy as np
 import torch
@@ -22,7 +23,7 @@ F32, F64 = 0, 1
 FIXED, QUIET = 0, 1
 STATUS = {0: "RSWR_OK", 1: "RSWR_ERR_INVALID_ARG", 2: "RSWR_ERR_UNSTABLE",
           3: "RSWR_ERR_LAYOUT", 4: "RSWR_ERR_SPAN", 5: "RSWR_ERR_NOMEM",
-          6: "RSWR_ERR_HIP", 7: "RSWR_ERR_NONFINITE", 8: "RSWR_ERR_UNSUPPORTED"}
+          6: "RSWR_ERR_HIP", 8: "RSWR_ERR_UNSUPPORTED"}
 
 
 class RSWRError(RuntimeError):
@@ -123,7 +124,8 @@ class Plan:
     n_points, n_sub, overlap: M grid nodes, N windows, overlap P in grid
     intervals (Sec. 2.2 Eqs. (4)-(5), Sec. 3).  courant = a dt / dx with dt
     fixed by a_ref (default a); courant_frac = (num, den) makes the span rule
-    of Eq. (10) exact in integers.  windows = (lo, hi) gives explicit windows.
+    of Eq. (10) exact in integers ("auto": the fraction with denominator up
+    to 1000 whose double equals courant, if any; None: the rule in double).  windows = (lo, hi) gives explicit windows.
     tile = (threads, nodes per lane) picks a built kernel shape; fuse=False
     keeps predict and update as separate launches in rswr_solve.
     sources = (nodes, amp): interior point sources (the pulse sources of
@@ -135,13 +137,17 @@ class Plan:
     """
 
     def __init__(self, n_points, n_sub, overlap, a=1.0, courant=0.9,
-                 courant_frac=(9, 10), x_a=0.0, x_b=1.0, a_ref=0.0, span=0,
+                 courant_frac="auto", x_a=0.0, x_b=1.0, a_ref=0.0, span=0,
                  span_mode=FIXED, beta=0.1, dtype=torch.float64, windows=None,
                  tile=None, fuse=True, sources=None, one_launch=False):
         L = lib()
         d = _Desc()
         d.x_a, d.x_b, d.n_points = float(x_a), float(x_b), int(n_points)
         d.a, d.a_ref, d.courant = float(a), float(a_ref), float(courant)
+        if isinstance(courant_frac, str) and courant_frac == "auto":
+            fr = Fraction(float(courant)).limit_denominator(1000)
+            courant_frac = ((fr.numerator, fr.denominator)
+                            if fr > 0 and float(fr) == float(courant) else None)
         num, den = courant_frac if courant_frac is not None else (0, 0)
         d.courant_num, d.courant_den = int(num), int(den)
         d.n_sub, d.overlap = int(n_sub), int(overlap)
@@ -437,6 +443,8 @@ class ProblemSpec:
 
     def __init__(self, n_points, n_sub, overlap, n_steps, receivers, f_b=None,
                  courant=0.9, a_ref=1.0, dtype=torch.float64, x_a=0.0, x_b=1.0):
+        if not a_ref > 0:
+            raise ValueError("a_ref must be positive: it fixes dt while a varies")
         self.n_points, self.n_sub, self.overlap = n_points, n_sub, overlap
         self.n_steps, self.courant, self.a_ref = n_steps, courant, a_ref
         self.receivers = np.asarray(receivers, np.int64)

@@ -538,17 +538,16 @@ __global__ __launch_bounds__(NT) void k_adj_update(const AdjUpdateArgs<T> p0) {
     sBu[s] = (s == 0) ? p.u_beg[2 * M - 1] : p.fb[p.n_k + s];
   }
 
-  const bool inside = tl.a >= 0 && tl.a + TM <= M;
   T wc[MPT], wp[MPT], uc[MPT], up[MPT];
   {
     T t[MPT];
-    load_level<T, NT, MPT>(p.w_in + M, tl.a, M, inside, t);
+    load_level<T, NT, MPT>(p.w_in + M, tl.a, M, t);
     transpose_in<T, NT, MPT>(t, st, wc);  // W^{n_e+1}
-    load_level<T, NT, MPT>(p.w_in, tl.a, M, inside, t);
+    load_level<T, NT, MPT>(p.w_in, tl.a, M, t);
     transpose_in<T, NT, MPT>(t, st, wp);  // W^{n_e+2}
-    load_level<T, NT, MPT>(p.u_end, tl.a, M, inside, t);
+    load_level<T, NT, MPT>(p.u_end, tl.a, M, t);
     transpose_in<T, NT, MPT>(t, st, uc);  // U^{n_e-1}
-    load_level<T, NT, MPT>(p.u_end + M, tl.a, M, inside, t);
+    load_level<T, NT, MPT>(p.u_end + M, tl.a, M, t);
     transpose_in<T, NT, MPT>(t, st, up);  // U^{n_e}
   }
 

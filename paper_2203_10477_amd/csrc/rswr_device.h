@@ -152,30 +152,33 @@ __device__ __forceinline__ int lds_slot(int x) {
     return pad32(x);
 }
 
-// Issue every load of a level before the first wait.  Regions fully inside
-// [0, M) read through a wave-uniform base pointer with 32-bit lane offsets;
-// edge regions clamp the index into [0, M) and replace the out-of-range
-// nodes by zero afterwards, so no load sits behind a branch either way.
+// Issue every load of a level before the first wait: node a + it*NT + tid
+// into tmp[it], through a range resource over the region's nodes that lie
+// in [0, M) -- 32-bit offsets from the first of them, and every node outside
+// the range (before node 0, after node M-1) reads as zero in hardware, with
+// no clamp, select or branch.  The offsets may be negative (regions that
+// start before node 0): as unsigned values they lie far beyond the range.
 template <typename T, int NT, int MPT>
 __device__ __forceinline__ void load_level(const T* __restrict__ src, int64_t a,
-                                           int64_t M, bool inside, T (&tmp)[MPT]) {
+                                           int64_t M, T (&tmp)[MPT]) {
+  constexpr int TM = NT * MPT;
   const int tid = static_cast<int>(threadIdx.x);
-  if (inside) {
-    const T* __restrict__ b = src + a;
+  const int64_t lo = a < 0 ? 0 : a;
+  const int64_t hi = a + TM < M ? a + TM : M;
+  const int n = hi > lo ? static_cast<int>(hi - lo) : 0;
+  const __amdgpu_buffer_rsrc_t r =
+      __builtin_amdgcn_make_buffer_rsrc(const_cast<T*>(src) + lo, 0, n * sizeof(T), 0x00020000);
+  const int shift = static_cast<int>(a - lo);  // <= 0
 #pragma unroll
-    for (int it = 0; it < MPT; ++it) tmp[it] = b[it * NT + tid];
-  } else {
-#pragma unroll
-    for (int it = 0; it < MPT; ++it) {
-      const int64_t j = a + it * NT + tid;
-      const int64_t jc = j < 0 ? 0 : (j >= M ? M - 1 : j);
-      tmp[it] = src[jc];
-    }
-#pragma unroll
-    for (int it = 0; it < MPT; ++it) {
-      const int64_t j = a + it * NT + tid;
-      tmp[it] = (j >= 0 && j < M) ? tmp[it] : T(0);
-    }
+  for (int it = 0; it < MPT; ++it) {
+    int off = (shift + it * NT + tid) * static_cast<int>(sizeof(T));
+    // the whole offset in the vector operand: a part folded into the
+    // instruction or scalar offset would escape the range check
+    asm("" : "+v"(off));
+    if constexpr (sizeof(T) == 4)
+      tmp[it] = __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+    else
+      tmp[it] = __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
   }
 }
 

@@ -64,26 +64,33 @@ struct FusedCtx {
   bool keep;          // the caller keeps the predicted fluxes
 };
 
-// Frame around output node o of window w: lane l holds nodes
-// o - kFrameHalf + 2l and the next one, at the span's first level (cur) and
-// the one before (old); nodes beyond the window take their mirror image
-// (clamped into the window), a value the sample never sees.
-// COH: device-coherent loads (the one-launch loop).
-template <typename T, bool COH = false>
-__device__ __forceinline__ void frame_load(const UpdateArgs<T>& p, int64_t o, int w,
-                                           int lane, T (&cur)[2], T (&old)[2]) {
-  const int64_t wlo = p.lo[w], whi = p.hi[w];
+// Frame around output node o of window [wlo, whi]: lane l holds nodes
+// o - kFrameHalf + 2l and the next one (j[0], j[1]); nodes beyond the window
+// take their mirror image (clamped into the window), a value the sample
+// never sees.
+__device__ __forceinline__ void frame_index(int64_t o, int64_t wlo, int64_t whi, int lane,
+                                            int64_t (&j)[2]) {
 #pragma unroll
   for (int e = 0; e < 2; ++e) {
-    int64_t j = o - kFrameHalf + 2 * lane + e;
-    j = (j < wlo) ? 2 * wlo - j : ((j > whi) ? 2 * whi - j : j);
-    j = j < wlo ? wlo : (j > whi ? whi : j);
+    int64_t x = o - kFrameHalf + 2 * lane + e;
+    x = (x < wlo) ? 2 * wlo - x : ((x > whi) ? 2 * whi - x : x);
+    j[e] = x < wlo ? wlo : (x > whi ? whi : x);
+  }
+}
+
+// The frame's nodes j at the span's first level (cur) and the one before
+// (old).  COH: device-coherent loads (the one-launch loop).
+template <typename T, bool COH = false>
+__device__ __forceinline__ void frame_load(const UpdateArgs<T>& p, const int64_t (&j)[2],
+                                           T (&cur)[2], T (&old)[2]) {
+#pragma unroll
+  for (int e = 0; e < 2; ++e) {
     if constexpr (COH) {
-      cur[e] = ld_coh<T>(state_row(p.state_in, p.M, 1), j);
-      old[e] = ld_coh<T>(state_row(p.state_in, p.M, 0), j);
+      cur[e] = ld_coh<T>(state_row(p.state_in, p.M, 1), j[e]);
+      old[e] = ld_coh<T>(state_row(p.state_in, p.M, 0), j[e]);
     } else {
-      cur[e] = p.state_in[p.M + j];
-      old[e] = p.state_in[j];
+      cur[e] = p.state_in[p.M + j[e]];
+      old[e] = p.state_in[j[e]];
     }
   }
 }
@@ -247,19 +254,18 @@ __device__ __forceinline__ void fused_step(const UpdateArgs<T>& p,
   }
 }
 
-template <typename T, int NT, int MPT, bool GEN, bool REC, bool SRC, bool HL, bool HR,
-          bool COH>
+// The S steps of one tile and of the frames its wave carries (lc / lo: the
+// left frame's levels n0 / n0-1, rc / ro: the right frame's), then the
+// per-span results the caller keeps.
+template <typename T, int NT, int MPT, bool GEN, bool REC, bool SRC, bool HL, bool HR>
 __device__ __forceinline__ void fused_run(const UpdateArgs<T>& p, const Tile& tl,
                                           const FusedCtx<T, NT, MPT>& c, int S,
-                                          T (&u)[MPT], T (&uo)[MPT]) {
-  constexpr int TM = NT * MPT;
-  T lc[2], lo[2], rc[2], ro[2];
+                                          T (&u)[MPT], T (&uo)[MPT], T (&lc)[2], T (&lo)[2],
+                                          T (&rc)[2], T (&ro)[2]) {
   T fl = T(0), fr = T(0);
   T tr[kRecSlots];
 #pragma unroll
   for (int q = 0; q < kRecSlots; ++q) tr[q] = T(0);
-  if constexpr (HL) frame_load<T, COH>(p, tl.a, tl.window - 1, c.lane, lc, lo);
-  if constexpr (HR) frame_load<T, COH>(p, tl.a + TM - 1, tl.window + 1, c.lane, rc, ro);
   int s = 0;
   for (; s + 1 < S; s += 2) {
     fused_step<T, NT, MPT, GEN, REC, SRC, HL, HR>(p, c, u, uo, lc, lo, rc, ro, fl, fr, tr, s);
@@ -279,35 +285,114 @@ __device__ __forceinline__ void fused_run(const UpdateArgs<T>& p, const Tile& tl
   }
 }
 
-// One tile over S levels: load, step (with the frames its waves carry),
-// store.  `st` is the LDS staging buffer, `edge` the cross-wave slots.
+// Which ends of tile tl touch node 0 / M-1, and whether its frames (the
+// predicting neighbours' states around its input ends, each spanning
+// [o - kFrameHalf, o + kFrameHalf - 1]) hold node 0 or M-1.
+struct TileEnds {
+  bool dirL, dirR, fA, fB;
+};
+
+template <typename T, int NT, int MPT>
+__device__ __forceinline__ TileEnds tile_ends(const UpdateArgs<T>& p, const Tile& tl) {
+  constexpr int TM = NT * MPT;
+  const int64_t oL = tl.a, oR = tl.a + TM - 1;
+  TileEnds e;
+  e.dirL = tl.lmode == kEndDirichlet;
+  e.dirR = tl.rmode == kEndDirichlet;
+  e.fA = tl.lmode == kEndGhost && tl.window == 1 && oL - kFrameHalf <= 0;
+  e.fB = tl.rmode == kEndGhost && oR + kFrameHalf - 1 >= p.M - 1 &&
+         p.hi[tl.window + 1] == p.M - 1;
+  return e;
+}
+
+// Everything a tile reads before its first step: both levels of the region
+// (unit stride: t1[it] and t0[it] hold node a + it*NT + tid at levels n0 and
+// n0-1), the frames of the input ends this wave carries, and nodes 0 / M-1
+// at levels n0..n0+S, one level per lane.  Every load is issued before the
+// first wait.
+template <typename T, int NT, int MPT>
+struct TileInput {
+  T t1[MPT], t0[MPT];
+  T lc[2], lo[2], rc[2], ro[2];
+  T vA, vB;
+  TileEnds ends;
+};
+
+// The bulk of a tile's reads, all issued without a wait: the two levels of
+// the region, the frames (nodes jl / jr, frame_index) of the input ends this
+// wave carries (carryL / carryR), and the values of nodes 0 / M-1.
+// COH: device-coherent loads (the one-launch loop).
+template <typename T, int NT, int MPT, bool GEN, bool COH>
+__device__ __forceinline__ void tile_fetch_at(const UpdateArgs<T>& p, const Tile& tl,
+                                              const TileEnds& e, bool carryL, bool carryR,
+                                              const int64_t (&jl)[2], const int64_t (&jr)[2],
+                                              int S, TileInput<T, NT, MPT>& in) {
+  const int lane = threadIdx.x & 63;
+  in.ends = e;
+  if constexpr (COH) {
+    load_level_coh<T, NT, MPT>(state_row(p.state_in, p.M, 1), tl.a, in.t1);  // level n0
+    load_level_coh<T, NT, MPT>(state_row(p.state_in, p.M, 0), tl.a, in.t0);  // level n0-1
+  } else {
+    load_level<T, NT, MPT>(p.state_in + p.M, tl.a, p.M, in.t1);  // level n0
+    load_level<T, NT, MPT>(p.state_in, tl.a, p.M, in.t0);        // level n0-1
+  }
+  if (carryL) frame_load<T, COH>(p, jl, in.lc, in.lo);
+  if (carryR) frame_load<T, COH>(p, jr, in.rc, in.ro);
+  // node 0 / M-1 at level n0 (from the state) and n0+1.. (from f_A, f_B)
+  T a = T(0), b = T(0);
+  if constexpr (COH) {
+    if ((e.dirL || e.fA) && lane <= S)
+      a = (lane == 0) ? ld_coh<T>(state_row(p.state_in, p.M, 1), 0) : p.fa[p.n0 + lane];
+    if ((e.dirR || e.fB) && lane <= S)
+      b = (lane == 0) ? ld_coh<T>(state_row(p.state_in, p.M, 1), p.M - 1) : p.fb[p.n0 + lane];
+  } else {
+    if ((GEN || e.dirL || e.fA) && lane <= S)
+      a = (lane == 0) ? p.state_in[p.M] : p.fa[p.n0 + lane];
+    if ((GEN || e.dirR || e.fB) && lane <= S)
+      b = (lane == 0) ? p.state_in[2 * p.M - 1] : p.fb[p.n0 + lane];
+  }
+  in.vA = a;
+  in.vB = b;
+}
+
+// Every read of a tile before its first step, for a wave that carries the
+// left (HL) / right (HR) input's frame.  The reads whose values address
+// other reads (the frames' window bounds, the window right of the tile) come
+// first and are consumed before a scheduling barrier, so no wait for them
+// waits for the bulk.
+template <typename T, int NT, int MPT, bool GEN, bool COH, bool HL, bool HR>
+__device__ __forceinline__ void tile_fetch(const UpdateArgs<T>& p, const Tile& tl, int S,
+                                           TileInput<T, NT, MPT>& in) {
+  constexpr int TM = NT * MPT;
+  const int lane = threadIdx.x & 63;
+  int64_t jl[2] = {0, 0}, jr[2] = {0, 0};
+  if constexpr (HL) frame_index(tl.a, p.lo[tl.window - 1], p.hi[tl.window - 1], lane, jl);
+  if constexpr (HR)
+    frame_index(tl.a + TM - 1, p.lo[tl.window + 1], p.hi[tl.window + 1], lane, jr);
+  const TileEnds e = tile_ends<T, NT, MPT>(p, tl);
+  asm volatile("" : "+v"(jl[0]), "+v"(jl[1]), "+v"(jr[0]), "+v"(jr[1]));
+  int flags = (e.dirL ? 1 : 0) | (e.dirR ? 2 : 0) | (e.fA ? 4 : 0) | (e.fB ? 8 : 0);
+  asm volatile("" : "+v"(flags));
+  __builtin_amdgcn_sched_barrier(0);
+  tile_fetch_at<T, NT, MPT, GEN, COH>(p, tl, e, HL, HR, jl, jr, S, in);
+}
+
+// The steps of a tile whose input is in registers: u / uo hold this lane's
+// MPT consecutive nodes at levels n0 / n0-1 on entry and n0+S / n0+S-1 (S
+// even) or n0+S-1 / n0+S (S odd) on exit; lc .. ro are the frames of the
+// left (HL) / right (HR) input this wave carries, vA / vB the values of
+// nodes 0 / M-1 (tile_fetch).  `edge`: the cross-wave slots.
 // GEN: node 0 may lie inside the region (per-element Dirichlet treatment).
 // REC: the tile may record receivers.  SRC: the tile and its frames may
-// inject interior sources.  COH: every state load and store with the
-// device-coherent policy (the one-launch loop, where tiles exchange the
-// state within one launch).
-template <typename T, int NT, int MPT, bool GEN, bool REC, bool SRC, bool COH = false>
-__device__ __forceinline__ void fused_tile(const UpdateArgs<T>& p, const Tile& tl, int slot,
-                                           int S, T* st, T (*edge)[2][NT / 64]) {
+// inject interior sources.
+template <typename T, int NT, int MPT, bool GEN, bool REC, bool SRC, bool HL, bool HR>
+__device__ __forceinline__ void tile_run(const UpdateArgs<T>& p, const Tile& tl, int slot,
+                                         int S, T (*edge)[2][NT / 64], T (&u)[MPT],
+                                         T (&uo)[MPT], T (&lc)[2], T (&lo)[2], T (&rc)[2],
+                                         T (&ro)[2], T vA, T vB, const TileEnds& ends) {
   constexpr int NW = NT / 64;
   constexpr int TM = NT * MPT;
-  static_assert(NT % 64 == 0 && MPT >= 2, "shape");
   const int tid = threadIdx.x;
-  const bool inside = tl.a >= 0 && tl.a + TM <= p.M;
-  T u[MPT], uo[MPT];
-  {
-    T t1[MPT], t0[MPT];
-    if constexpr (COH) {
-      load_level_coh<T, NT, MPT>(state_row(p.state_in, p.M, 1), tl.a, t1);  // level n0
-      load_level_coh<T, NT, MPT>(state_row(p.state_in, p.M, 0), tl.a, t0);  // level n0-1
-    } else {
-      load_level<T, NT, MPT>(p.state_in + p.M, tl.a, p.M, inside, t1);  // level n0
-      load_level<T, NT, MPT>(p.state_in, tl.a, p.M, inside, t0);        // level n0-1
-    }
-    transpose_in<T, NT, MPT>(t1, st, u);
-    transpose_in<T, NT, MPT>(t0, st, uo);
-  }
-
   FusedCtx<T, NT, MPT> c;
   c.edge = edge;
   c.lane = tid & 63;
@@ -315,17 +400,13 @@ __device__ __forceinline__ void fused_tile(const UpdateArgs<T>& p, const Tile& t
   c.base = tl.a + static_cast<int64_t>(tid) * MPT;
   c.a = tl.a;
   c.tid = tid;
-  const bool dirL = tl.lmode == kEndDirichlet, dirR = tl.rmode == kEndDirichlet;
+  const bool dirL = ends.dirL, dirR = ends.dirR;
   c.dirL = dirL && c.wv == 0;
   c.dirR = dirR && c.wv == NW - 1;
-  // frames around the input ends (left: o = a, right: o = a + TM - 1); a
-  // frame spans [o - kFrameHalf, o + kFrameHalf - 1]
+  // frames around the input ends (left: o = a, right: o = a + TM - 1)
   const int64_t oL = tl.a, oR = tl.a + TM - 1;
-  const bool fA = tl.lmode == kEndGhost && tl.window == 1 && oL - kFrameHalf <= 0;
-  const bool fB = tl.rmode == kEndGhost && oR + kFrameHalf - 1 >= p.M - 1 &&
-                  p.hi[tl.window + 1] == p.M - 1;
-  c.fdirL = fA && c.wv == 0;
-  c.fdirR = fB && c.wv == NW - 1;
+  c.fdirL = ends.fA && c.wv == 0;
+  c.fdirR = ends.fB && c.wv == NW - 1;
 #pragma unroll
   for (int e = 0; e < 2; ++e) {
     c.fmL[e] = oL - kFrameHalf + 2 * c.lane + e == 0;
@@ -334,23 +415,8 @@ __device__ __forceinline__ void fused_tile(const UpdateArgs<T>& p, const Tile& t
   c.keep = p.flux_out != nullptr;
   c.nq = in_vgpr(-p.q);
   c.pq = in_vgpr(p.q);
-  {
-    // node 0 / M-1 at level n0 (from the state) and n0+1.. (from f_A, f_B)
-    const int l = c.lane;
-    T a = T(0), b = T(0);
-    if constexpr (COH) {
-      if ((dirL || fA) && l <= S)
-        a = (l == 0) ? ld_coh<T>(state_row(p.state_in, p.M, 1), 0) : p.fa[p.n0 + l];
-      if ((dirR || fB) && l <= S)
-        b = (l == 0) ? ld_coh<T>(state_row(p.state_in, p.M, 1), p.M - 1) : p.fb[p.n0 + l];
-    } else {
-      if ((GEN || dirL || fA) && l <= S) a = (l == 0) ? p.state_in[p.M] : p.fa[p.n0 + l];
-      if ((GEN || dirR || fB) && l <= S)
-        b = (l == 0) ? p.state_in[2 * p.M - 1] : p.fb[p.n0 + l];
-    }
-    c.vA = a;
-    c.vB = b;
-  }
+  c.vA = vA;
+  c.vB = vB;
   c.d0 = -1000;
   c.gen = false;
   if (GEN) {
@@ -445,24 +511,59 @@ __device__ __forceinline__ void fused_tile(const UpdateArgs<T>& p, const Tile& t
     c.work = __builtin_amdgcn_readfirstlane(w);
   }
 
-  const bool hl = c.wv == 0 && tl.lmode == kEndGhost;
-  const bool hr = c.wv == NW - 1 && tl.rmode == kEndGhost;
-  if (hl) {
-    if (hr)
-      fused_run<T, NT, MPT, GEN, REC, SRC, true, true, COH>(p, tl, c, S, u, uo);
-    else
-      fused_run<T, NT, MPT, GEN, REC, SRC, true, false, COH>(p, tl, c, S, u, uo);
-  } else {
-    if (hr)
-      fused_run<T, NT, MPT, GEN, REC, SRC, false, true, COH>(p, tl, c, S, u, uo);
-    else
-      fused_run<T, NT, MPT, GEN, REC, SRC, false, false, COH>(p, tl, c, S, u, uo);
-  }
+  fused_run<T, NT, MPT, GEN, REC, SRC, HL, HR>(p, tl, c, S, u, uo, lc, lo, rc, ro);
+}
 
+// A tile's stored range as offsets from its region start.
+template <int TM>
+__device__ __forceinline__ void stored_range(const Tile& tl, int& xlo, int& xhi) {
   const int64_t rlo = tl.out_lo > tl.a ? tl.out_lo : tl.a;
   const int64_t rhi = tl.out_hi < tl.a + TM - 1 ? tl.out_hi : tl.a + TM - 1;
-  const int xlo = static_cast<int>(rlo - tl.a);
-  const int xhi = static_cast<int>(rhi - tl.a);
+  xlo = static_cast<int>(rlo - tl.a);
+  xhi = static_cast<int>(rhi - tl.a);
+}
+
+// Node 0 / M-1 at the span's last two levels (a1, a2 / b1, b2), written by
+// lane 0 of the first wave / the last lane of the last wave of a tile whose
+// region borders it.  COH: device-coherent stores.
+template <typename T, int NT, bool COH>
+__device__ __forceinline__ void dirichlet_put(const UpdateArgs<T>& p, bool dirL, bool dirR,
+                                              T a1, T a2, T b1, T b2) {
+  constexpr int AUX = COH ? kCohAux : 0;
+  auto put = [&](int64_t j, T v) {
+    if constexpr (COH)
+      range_store<AUX>(v, range_rsrc(p.state_out + j, static_cast<int>(sizeof(T))), 0);
+    else
+      p.state_out[j] = v;
+  };
+  const int tid = threadIdx.x;
+  if (dirL && tid == 0) {
+    put(0, a1);
+    put(p.M, a2);
+  }
+  if (dirR && tid == NT - 1) {
+    put(p.M - 1, b1);
+    put(2 * p.M - 1, b2);
+  }
+}
+
+// The steps and the stores of a tile whose input is in registers
+// (tile_run, then the stored range of both levels through the LDS buffer
+// `st`, and the Dirichlet nodes next to the region).  COH: device-coherent
+// stores (the one-launch loop, where tiles exchange the state within one
+// launch).
+template <typename T, int NT, int MPT, bool GEN, bool REC, bool SRC, bool COH, bool HL,
+          bool HR>
+__device__ __forceinline__ void tile_steps(const UpdateArgs<T>& p, const Tile& tl, int slot,
+                                           int S, T* st, T (*edge)[2][NT / 64], T (&u)[MPT],
+                                           T (&uo)[MPT], T (&lc)[2], T (&lo)[2], T (&rc)[2],
+                                           T (&ro)[2], T vA, T vB, const TileEnds& ends) {
+  constexpr int NW = NT / 64;
+  constexpr int TM = NT * MPT;
+  tile_run<T, NT, MPT, GEN, REC, SRC, HL, HR>(p, tl, slot, S, edge, u, uo, lc, lo, rc, ro,
+                                              vA, vB, ends);
+  int xlo, xhi;
+  stored_range<TM>(tl, xlo, xhi);
   constexpr int AUX = COH ? kCohAux : 0;
   if (S & 1) {  // uo = level n0+S, u = n0+S-1
     stage_out<T, NT, MPT, AUX>(p.state_out, tl.a, xlo, xhi, st, u);
@@ -471,26 +572,60 @@ __device__ __forceinline__ void fused_tile(const UpdateArgs<T>& p, const Tile& t
     stage_out<T, NT, MPT, AUX>(p.state_out, tl.a, xlo, xhi, st, uo);
     stage_out<T, NT, MPT, AUX>(p.state_out + p.M, tl.a, xlo, xhi, st, u);
   }
-  // Dirichlet nodes next to the region
-  auto put = [&](int64_t j, T v) {
-    if constexpr (COH)
-      range_store<AUX>(v, range_rsrc(p.state_out + j, static_cast<int>(sizeof(T))), 0);
-    else
-      p.state_out[j] = v;
-  };
-  if (dirL && c.wv == 0) {
-    const T a1 = rd_lane(c.vA, S - 1), a2 = rd_lane(c.vA, S);
-    if (tid == 0) {
-      put(0, a1);
-      put(p.M, a2);
-    }
+  // Dirichlet nodes next to the region (readlane in wave-uniform flow)
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  T a1 = T(0), a2 = T(0), b1 = T(0), b2 = T(0);
+  const bool pl = ends.dirL && wv == 0, pr = ends.dirR && wv == NW - 1;
+  if (pl) {
+    a1 = rd_lane(vA, S - 1);
+    a2 = rd_lane(vA, S);
   }
-  if (dirR && c.wv == NW - 1) {
-    const T b1 = rd_lane(c.vB, S - 1), b2 = rd_lane(c.vB, S);
-    if (tid == NT - 1) {
-      put(p.M - 1, b1);
-      put(2 * p.M - 1, b2);
-    }
+  if (pr) {
+    b1 = rd_lane(vB, S - 1);
+    b2 = rd_lane(vB, S);
+  }
+  dirichlet_put<T, NT, COH>(p, pl, pr, a1, a2, b1, b2);
+}
+
+// One tile over S levels for a wave that carries the left (HL) / right (HR)
+// input's frame: load, step, store.
+template <typename T, int NT, int MPT, bool GEN, bool REC, bool SRC, bool COH, bool HL,
+          bool HR>
+__device__ __forceinline__ void fused_tile_v(const UpdateArgs<T>& p, const Tile& tl, int slot,
+                                             int S, T* st, T (*edge)[2][NT / 64]) {
+  TileInput<T, NT, MPT> in;
+  tile_fetch<T, NT, MPT, GEN, COH, HL, HR>(p, tl, S, in);
+  T u[MPT], uo[MPT];
+  transpose_in<T, NT, MPT>(in.t1, st, u);
+  transpose_in<T, NT, MPT>(in.t0, st, uo);
+  tile_steps<T, NT, MPT, GEN, REC, SRC, COH, HL, HR>(p, tl, slot, S, st, edge, u, uo, in.lc,
+                                                     in.lo, in.rc, in.ro, in.vA, in.vB,
+                                                     in.ends);
+}
+
+// One tile over S levels: load, step (with the frames its waves carry),
+// store.  The frames a wave carries (wave-uniform) pick one of four whole
+// code paths, chosen before the first load: each path's registers are
+// allocated on their own, where four step loops after one shared load
+// would hold the values of every path at once.
+template <typename T, int NT, int MPT, bool GEN, bool REC, bool SRC, bool COH = false>
+__device__ __forceinline__ void fused_tile(const UpdateArgs<T>& p, const Tile& tl, int slot,
+                                           int S, T* st, T (*edge)[2][NT / 64]) {
+  constexpr int NW = NT / 64;
+  static_assert(NT % 64 == 0 && MPT >= 2, "shape");
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const bool hl = wv == 0 && tl.lmode == kEndGhost;
+  const bool hr = wv == NW - 1 && tl.rmode == kEndGhost;
+  if (hl) {
+    if (hr)
+      fused_tile_v<T, NT, MPT, GEN, REC, SRC, COH, true, true>(p, tl, slot, S, st, edge);
+    else
+      fused_tile_v<T, NT, MPT, GEN, REC, SRC, COH, true, false>(p, tl, slot, S, st, edge);
+  } else {
+    if (hr)
+      fused_tile_v<T, NT, MPT, GEN, REC, SRC, COH, false, true>(p, tl, slot, S, st, edge);
+    else
+      fused_tile_v<T, NT, MPT, GEN, REC, SRC, COH, false, false>(p, tl, slot, S, st, edge);
   }
 }
 

@@ -561,9 +561,6 @@ rswr::UpdateArgs<T> update_args(const rswr_plan_s& p, const DevTables& d,
   return a;
 }
 
-// The two update launches of one span: general tiles (and, in a solve, the
-// tiles holding receivers) through the general kernel, the rest through the
-// plain one.
 // The two update launches of one span on the two-launch path: general
 // tiles (and, in a solve, the tiles holding receivers) through the general
 // kernel, the rest through the plain one.
@@ -1233,7 +1230,6 @@ const char* rswr_status_string(rswr_status_t s) {
     case RSWR_ERR_SPAN: return "span beyond the light-cone limit";
     case RSWR_ERR_NOMEM: return "out of memory or workspace too small";
     case RSWR_ERR_HIP: return "HIP runtime error";
-    case RSWR_ERR_NONFINITE: return "non-finite value";
     case RSWR_ERR_UNSUPPORTED: return "unsupported configuration";
   }
   return "unknown status";
@@ -1267,6 +1263,10 @@ rswr_status_t rswr_plan(const rswr_desc_t* desc, rswr_plan_t* out) {
   if (D.span < 0) return fail(RSWR_ERR_INVALID_ARG, "span must be >= 0");
   if ((D.courant_num > 0) != (D.courant_den > 0))
     return fail(RSWR_ERR_INVALID_ARG, "courant_num and courant_den go together");
+  if (D.courant_num > 0 &&
+      !(std::fabs(double(D.courant_num) / double(D.courant_den) - D.courant) <=
+        4 * std::numeric_limits<double>::epsilon() * std::fabs(D.courant)))
+    return fail(RSWR_ERR_INVALID_ARG, "courant_num / courant_den differs from courant");
   const double a_ref = D.a_ref > 0 ? D.a_ref : D.a;
   const double lam = D.courant * (D.a / a_ref);
   if (!(D.courant > 0) || !(lam <= 1.0))

@@ -191,12 +191,11 @@ __global__ __launch_bounds__(NT) void k_update(const UpdateArgs<T> p0) {
     sB[s] = (s == 0) ? p.state_in[2 * p.M - 1] : p.fb[p.n0 + s];
   }
 
-  const bool inside = tl.a >= 0 && tl.a + TM <= p.M;
   T u[MPT], uo[MPT];
   {
     T t1[MPT], t0[MPT];
-    load_level<T, NT, MPT>(p.state_in + p.M, tl.a, p.M, inside, t1);  // level n0
-    load_level<T, NT, MPT>(p.state_in, tl.a, p.M, inside, t0);        // level n0-1
+    load_level<T, NT, MPT>(p.state_in + p.M, tl.a, p.M, t1);  // level n0
+    load_level<T, NT, MPT>(p.state_in, tl.a, p.M, t0);        // level n0-1
     transpose_in<T, NT, MPT>(t1, st, u);
     transpose_in<T, NT, MPT>(t0, st, uo);
   }

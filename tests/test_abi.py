@@ -230,3 +230,14 @@ def test_source_plan_rules():
     for kw in ({"no_fuse": 1}, {"span_mode": 1}):
         st, _ = raw_plan(4097, 8, 64, [100], **kw)
         assert rs.STATUS[st] == "RSWR_ERR_UNSUPPORTED", kw
+
+
+def test_courant_fraction_must_match_courant():
+    # Eq. (10): 2 S lam < P.  At C = 1 and P = 20 the rule gives S = 9; a
+    # stale fraction of 9/10 would give 11.
+    assert rs.Plan(1001, 2, 20, courant=1.0).info["span_paper"] == 9
+    assert rs.Plan(1001, 2, 20, courant=0.9).info["span_paper"] == 11
+    with pytest.raises(rs.RSWRError):
+        rs.Plan(1001, 2, 20, courant=1.0, courant_frac=(9, 10))
+    with pytest.raises(ValueError):
+        rs.ProblemSpec(1001, 2, 20, 100, [3], a_ref=0.0)

@@ -123,6 +123,51 @@ def test_fused_solve_bitwise(dtype, case):
         assert np.array_equal(fl_f[k][rows, :S_k], fl_t[k][rows, :S_k]), k
 
 
+GRID_CASES = [
+    # M, N, P, tile, n_steps: one to four waves per tile, and grids of
+    # several thousand tiles
+    (4097, 8, 64, (64, 8), 300),
+    (20001, 16, 64, (256, 16), 177),
+    (2001, 3, 20, (128, 8), 150),
+    (3000001, 64, 64, (64, 8), 90),
+    (3000001, 96, 64, (64, 16), 75),
+]
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+@pytest.mark.parametrize("case", range(len(GRID_CASES)))
+def test_fused_grids_bitwise(dtype, case):
+    """Fused solves on small and large grids: the state bitwise equal to the
+    oracle's RSWR and to the two-launch path, with and without checkpoints
+    (checkpoint states equal too)."""
+    M, N, P, tile, n_steps = GRID_CASES[case]
+    say("fused-grid", dtype, GRID_CASES[case])
+    plan = rs.Plan(M, N, P, tile=tile, dtype=dtype)
+    two = rs.Plan(M, N, P, tile=tile, dtype=dtype, fuse=False)
+    assert plan.info["fused"] == 1 and two.info["fused"] == 0
+    npdt = NP[dtype]
+    st0, fa, fb = busy(M, n_steps, seed=100 + case)
+    st0, fa, fb = st0.astype(npdt), fa.astype(npdt), fb.astype(npdt)
+    fa_d, fb_d = dev(fa, dtype), dev(fb, dtype)
+    outs, cks = [], []
+    for p in (plan, two):
+        s = dev(st0, dtype)
+        rs.rswr_solve(p, s, fa_d, fb_d, n_steps)
+        ck = p.checkpoint_buffer(n_steps)
+        s2 = dev(st0, dtype)
+        rs.rswr_solve(p, s2, fa_d, fb_d, n_steps, checkpoints=ck)
+        torch.cuda.synchronize()
+        outs.append(host(s))
+        assert np.array_equal(host(s2), outs[-1])
+        cks.append(host(p.checkpoint_states(ck, n_steps)))
+    assert np.array_equal(outs[0], outs[1])
+    assert np.array_equal(cks[0], cks[1])
+    lay = lay_of(plan)
+    ref, _, _ = oracle.rswr(lay, plan.info["lambda"], plan.info["dx"], fa, fb, n_steps,
+                            span=plan.span, state=st0)
+    assert np.array_equal(outs[0], ref)
+
+
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
 def test_span_entry_point(dtype):
     """rswr_span: one whole span, fused and two-launch, against the oracle's
