@@ -33,10 +33,11 @@ METRIC = "grid-point updates/sec (GLUPS) + % HBM roofline, plain vs batched vs a
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
 
 # HBM traffic of one span kernel launch on this workload, from two rocprofv3
-# --pmc passes (FETCH_SIZE, WRITE_SIZE; see profiles/), valid only for the
+# --pmc passes (FETCH_SIZE, WRITE_SIZE; see profiles/), and the VALU wave
+# instructions of a full 35-step span (SQ_INSTS_VALU), valid only for the
 # kernel sources with this SHA-256 prefix.
-TRAFFIC = {"kernel_sha": "f297b915b4abaf58", "tile": [64, 33], "bytes": 270185881,
-           "valu_insts": 33179678}
+TRAFFIC = {"kernel_sha": "4eb89f57708e8645", "tile": [64, 33], "bytes": 270271638,
+           "valu_insts": 33058905}
 
 
 def kernel_sha():
@@ -576,24 +577,26 @@ def main():
         raise ValueError("kernel-reps too large for the source length")
     sm = sm0.clone()
     rs.rswr_solve(plan, sm, fa, fb, R * S, workspace=ws)  # records the graph
-    sm.copy_(sm0)
-    torch.cuda.synchronize()
-    ev0.record()
-    rs.rswr_solve(plan, sm, fa, fb, R * S, workspace=ws)
-    ev1.record()
-    torch.cuda.synchronize()
-    busy_us = ev0.elapsed_time(ev1) * 1e3 / R
+    busy = []
+    for _ in range(3):  # the median of three replays (busy data varies more)
+        sm.copy_(sm0)
+        torch.cuda.synchronize()
+        ev0.record()
+        rs.rswr_solve(plan, sm, fa, fb, R * S, workspace=ws)
+        ev1.record()
+        torch.cuda.synchronize()
+        busy.append(ev0.elapsed_time(ev1) * 1e3 / R)
+    busy_us = sorted(busy)[1]
     nbytes = span_bytes(plan, 4)
     achieved = nbytes / (span_us * 1e-6) / 1e9
     sha = kernel_sha()
     measured = (TRAFFIC["kernel_sha"] == sha and
                 [plan.info["tile_threads"], plan.info["tile_per_thread"]] == TRAFFIC["tile"])
     traffic = TRAFFIC["bytes"] if measured else None
-    # VALU wave instructions per launch (counter pass of the same sources and
-    # tile) against the issue cycles of 1024 SIMDs at 2.4 GHz over the live
-    # launch time, 4 cycles per wave64 instruction
-    valu_frac = (round(TRAFFIC["valu_insts"] * 4 / (1024 * 2.4e9 * span_us * 1e-6), 4)
-                 if measured else None)
+    # VALU wave instructions per wave and step (counter pass of the same
+    # sources and tile; 8192 waves, 35 steps)
+    valu_wave_step = (round(TRAFFIC["valu_insts"] / (plan.info["n_tiles"] * S), 1)
+                      if measured else None)
     kname = ("k_fused (predict + update of one span, all windows, one launch)" if fused
              else "k_predict + k_update (one span, all windows)")
 
@@ -613,7 +616,7 @@ def main():
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic, "kernel": kname,
                      "valu_insts": TRAFFIC["valu_insts"] if measured else None,
-                     "valu_issue_frac": valu_frac,
+                     "valu_insts_per_wave_step": valu_wave_step,
                      "avg_us": round(span_us, 2), "algorithmic_bytes": nbytes,
                      "busy_field_avg_us": round(busy_us, 2),
                      "busy_field_frac": round(nbytes / (busy_us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4)},

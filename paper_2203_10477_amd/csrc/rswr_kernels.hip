@@ -17,18 +17,14 @@ namespace rswr {
 // window's own ends inside that range keep their exact treatment (Dirichlet
 // data, or the zero-flux ghost of the prediction), the cut ends carry zero
 // data that cannot reach o +- 1 in time.  So this trapezoid reproduces the
-// whole-window prediction bit for bit.
+// whole-window prediction bit for bit; so does the register frame below,
+// which k_predict uses for spans up to 159 levels.
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ __launch_bounds__(64) void k_predict(const PredictArgs<T> p0) {
-  PredictArgs<T> p = p0;
-  if (p0.n0_dev) p.n0 = *p0.n0_dev;
-  if (p0.shat_dev) p.shat = *p0.shat_dev;
-  if (p.shat <= 0) return;
+__device__ __forceinline__ void predict_trapezoid(const PredictArgs<T>& p, int i, int side) {
   extern __shared__ unsigned char smem_raw[];
   T* const sm = reinterpret_cast<T*>(smem_raw);
   __shared__ T sda[kMaxSpan], sdb[kMaxSpan];
-  const int i = blockIdx.x >> 1, side = blockIdx.x & 1;
   const int w = i + side;
   const int64_t o = (side == 0) ? p.lo[i + 1] : p.hi[i];
   const int64_t wlo = p.lo[w], whi = p.hi[w];
@@ -76,6 +72,149 @@ __global__ __launch_bounds__(64) void k_predict(const PredictArgs<T> p0) {
     u0 = u1;
     u1 = t;
   }
+}
+
+// Element e (wave-uniform) of a frame's K nodes in this lane, and frame node
+// `at` := x: bit masks, not an index (an indexed access, or a select chain
+// the compiler folds into one, would move the frame to scratch memory).
+template <typename T, int K>
+__device__ __forceinline__ T frame_elem(const T (&v)[K], int e) {
+  return pick<T, K>(v, e);
+}
+
+template <typename T, int K>
+__device__ __forceinline__ void frame_put(T (&v)[K], int at, T x, int lane) {
+  using U = typename Bits<T>::U;
+  const int l = at / K, e = at % K;
+  const U xb = __builtin_bit_cast(U, x);
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const U m = static_cast<U>(0) - static_cast<U>(lane == l && k == e);
+    v[k] = __builtin_bit_cast(T, (__builtin_bit_cast(U, v[k]) & ~m) | (xb & m));
+  }
+}
+
+// The ghost node g (frame offset, -1: none) := fma(sq, 0, node src).
+template <typename T, int K>
+__device__ __forceinline__ void frame_ghost(T (&v)[K], int g, int src, T sq, int lane) {
+  if (g >= 0) {
+    const T x = rd_lane(frame_elem<T, K>(v, src % K), src / K);
+    frame_put<T, K>(v, g, fma_(sq, T(0), x), lane);
+  }
+}
+
+// Where a predict frame's nodes need their own treatment (frame offsets,
+// -1: not in the frame) and the Dirichlet data of levels n0+1.. (lane s of
+// register s / 64).
+template <typename T>
+struct FrameEnds {
+  int gl, gr, d0, d1;
+  T dA[3], dB[3];
+};
+
+// One level of a predict frame: records F[s] (lane s % 64 of fr[s / 64]),
+// then, unless it is the last sample, writes level n+1 over `old`.
+template <typename T, int K>
+__device__ __forceinline__ bool frame_level(const PredictArgs<T>& p, const FrameEnds<T>& fe,
+                                            const T (&cur)[K], T (&old)[K], T (&fr)[3], int s,
+                                            int lane) {
+  const T l1 = lane_shift_z<kWaveShr1>(cur[K - 1]);
+  // o + 1: lane 32, element 1; o - 1: lane 31, element K-1
+  const T F = rd_lane((cur[1] - l1) * p.r, 32);
+  const int r = s >> 6, l = s & 63;
+  frame_put<T, 3>(fr, 3 * l + r, F, lane);  // sample s: fr[s / 64] in lane s % 64
+  if (s == p.shat - 1) return false;
+  const T r0 = lane_shift_z<kWaveShl1>(cur[0]);
+#pragma unroll
+  for (int e = 0; e < K; ++e) {
+    const T ul = (e == 0) ? l1 : cur[e - 1];
+    const T ur = (e == K - 1) ? r0 : cur[e + 1];
+    old[e] = leap(p.c2, p.k, ul, cur[e], ur, old[e]);
+  }
+  if (fe.d0 >= 0) frame_put<T, K>(old, fe.d0, rd_lane(pick<T, 3>(fe.dA, r), l), lane);
+  if (fe.d1 >= 0) frame_put<T, K>(old, fe.d1, rd_lane(pick<T, 3>(fe.dB, r), l), lane);
+  frame_ghost<T, K>(old, fe.gl, fe.gl + 2, -p.q, lane);
+  frame_ghost<T, K>(old, fe.gr, fe.gr - 2, p.q, lane);
+  return true;
+}
+
+// The same prediction on a register frame: one wave, K nodes per lane, the
+// 64K nodes o - 32K .. o + 32K - 1 around the output node o; nodes beyond
+// the predicting window load their mirror image (clamped into the window).
+// The window's nodes step exactly as in the whole-window prediction: node 0
+// / M-1 take the Dirichlet data, and the ghost node outside an input end is
+// set every level to the zero-flux ghost of Eqs. (6)-(7), fma(-+q, 0, u)
+// of the node two inside, so whatever the nodes beyond it hold never
+// reaches the window.  The frame's own cut ends (zero data) reach o +- 1
+// only after 32K - 1 levels, so 32K >= shat + 1 makes every sample equal
+// to the whole-window prediction bit for bit.  No LDS and no barrier: a
+// level is three operations per node and two lane shifts.
+template <typename T, int K>
+__device__ __forceinline__ void predict_frame(const PredictArgs<T>& p, int i, int side) {
+  constexpr int H = 32 * K;
+  static_assert(K >= 2, "the output node's neighbours lie in lanes 31 and 32");
+  const int lane = threadIdx.x;
+  const int w = i + side;
+  const int64_t o = (side == 0) ? p.lo[i + 1] : p.hi[i];
+  const int64_t wlo = p.lo[w], whi = p.hi[w];
+  const int64_t f0 = o - H;  // the frame's first node
+  T ca[K], cb[K];  // levels n, n-1 (their roles alternate)
+#pragma unroll
+  for (int e = 0; e < K; ++e) {
+    int64_t x = f0 + K * lane + e;
+    x = (x < wlo) ? 2 * wlo - x : ((x > whi) ? 2 * whi - x : x);
+    x = x < wlo ? wlo : (x > whi ? whi : x);
+    ca[e] = p.state[p.M + x];
+    cb[e] = p.state[x];
+  }
+  auto pos = [&](int64_t j) -> int {
+    const int64_t d = j - f0;
+    return (d >= 0 && d < 64 * K) ? static_cast<int>(d) : -1;
+  };
+  FrameEnds<T> fe;
+  fe.gl = (w > 0) ? pos(wlo - 1) : -1;
+  fe.gr = (w < p.N - 1) ? pos(whi + 1) : -1;
+  fe.d0 = (w == 0) ? pos(0) : -1;
+  fe.d1 = (w == p.N - 1) ? pos(p.M - 1) : -1;
+#pragma unroll
+  for (int r = 0; r < 3; ++r) {
+    const int s = lane + 64 * r;
+    fe.dA[r] = (fe.d0 >= 0 && s + 1 < p.shat) ? p.fa[p.n0 + 1 + s] : T(0);
+    fe.dB[r] = (fe.d1 >= 0 && s + 1 < p.shat) ? p.fb[p.n0 + 1 + s] : T(0);
+  }
+  frame_ghost<T, K>(ca, fe.gl, fe.gl + 2, -p.q, lane);
+  frame_ghost<T, K>(ca, fe.gr, fe.gr - 2, p.q, lane);
+  T fr[3] = {T(0), T(0), T(0)};
+  for (int s = 0; s < p.shat; s += 2) {
+    if (!frame_level<T, K>(p, fe, ca, cb, fr, s, lane)) break;
+    if (!frame_level<T, K>(p, fe, cb, ca, fr, s + 1, lane)) break;
+  }
+  T* const row = p.flux + static_cast<int64_t>(2 * i + side) * p.ld;
+#pragma unroll
+  for (int r = 0; r < 3; ++r)
+    if (lane + 64 * r < p.shat) row[lane + 64 * r] = fr[r];
+}
+
+// One wave per (interface i, side): the frame for spans up to 159 levels,
+// the LDS trapezoid beyond.
+template <typename T>
+__global__ __launch_bounds__(64) void k_predict(const PredictArgs<T> p0) {
+  PredictArgs<T> p = p0;
+  if (p0.n0_dev) p.n0 = *p0.n0_dev;
+  if (p0.shat_dev) p.shat = *p0.shat_dev;
+  const int shat = p.shat;
+  if (shat <= 0) return;
+  const int i = blockIdx.x >> 1, side = blockIdx.x & 1;
+  if (shat <= 63)
+    predict_frame<T, 2>(p, i, side);
+  else if (shat <= 95)
+    predict_frame<T, 3>(p, i, side);
+  else if (shat <= 127)
+    predict_frame<T, 4>(p, i, side);
+  else if (shat <= 159)
+    predict_frame<T, 5>(p, i, side);
+  else
+    predict_trapezoid<T>(p, i, side);
 }
 
 // ---------------------------------------------------------------------------

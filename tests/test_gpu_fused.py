@@ -80,7 +80,7 @@ FUSE_CASES = [
 def test_fused_solve_bitwise(dtype, case):
     M, N, P, win, tile, n_steps, n0, span = FUSE_CASES[case]
     if dtype == torch.float64 and tile is not None and tile[1] > 22:
-        pytest.skip("shape not built for FP64")
+        tile = (64, 16)  # the shape holds no FP64 kernel: the widest FP64 one-wave shape
     say("fused-solve", dtype, FUSE_CASES[case])
     plan = rs.Plan(M, N, P, windows=win, tile=tile, span=span, dtype=dtype)
     two = rs.Plan(M, N, P, windows=win, tile=tile, span=span, dtype=dtype, fuse=False)

@@ -83,6 +83,30 @@ def test_predict_bitwise(dtype, case):
 
 
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_predict_every_frame_width(dtype):
+    """The predict runs on register frames of 2..5 nodes per lane for spans up
+    to 159 levels and on the LDS trapezoid beyond: spans on both sides of
+    every width change, reaching the predicting windows' input ghosts and
+    node 0 / M-1, bitwise against the oracle's whole-window prediction."""
+    M, N, P = 1201, 8, 128
+    say("predict-widths", dtype)
+    plan = rs.Plan(M, N, P, span_mode=rs.QUIET, dtype=dtype)
+    lay = lay_of(plan)
+    cap = plan.info["span"]
+    assert cap >= 200, cap
+    npdt = NP[dtype]
+    st, fa, fb = busy(M, cap + 20, seed=11)
+    st, fa, fb = st.astype(npdt), fa.astype(npdt), fb.astype(npdt)
+    st_d, fa_d, fb_d = dev(st, dtype), dev(fa, dtype), dev(fb, dtype)
+    n0 = 9
+    for shat in (1, 2, 40, 63, 64, 95, 96, 127, 128, 159, 160, 200, cap):
+        ref = oracle.predict(lay, plan.info["lambda"], plan.info["dx"], fa, fb, n0, shat, st)
+        fl = rs.rswr_predict(plan, st_d, fa_d, fb_d, n0, shat)
+        got = host(fl)[:, :, :shat]
+        assert np.array_equal(got, ref[:, :, :shat]), shat
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
 def test_predict_beyond_cone_reaches_window_ends(dtype):
     """QUIET plans predict up to twice the light-cone span; the trapezoid then
     reaches the windows' own input boundaries (zero-flux ghosts)."""

@@ -79,7 +79,7 @@ CASES = [
 def test_solve_with_sources_bitwise(dtype, case):
     M, N, P, win, tile, n_steps, n0, span = CASES[case]
     if dtype == torch.float64 and tile is not None and tile[1] > 22:
-        pytest.skip("shape not built for FP64")
+        tile = (64, 16)  # the shape holds no FP64 kernel: the widest FP64 one-wave shape
     say("sources-solve", dtype, CASES[case])
     npdt = NP[dtype]
     g = np.random.default_rng(40 + case)
