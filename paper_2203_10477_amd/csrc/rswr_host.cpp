@@ -342,7 +342,15 @@ bool choose_shape(rswr_plan_s& p) {
     if (!build_tiles(p, TM, p.S_max, tiles)) continue;
     double nt = 0;
     for (const Tile& t : tiles) nt += t.general ? 2.0 : 1.0;
-    const double cost = nt * TM * std::max(1.0, 512.0 / double(tiles.size()));
+    // beyond 33 nodes per lane (FP32) or 16 (FP64) a lane's two levels take
+    // so many registers that a SIMD holds two waves or fewer; a tile of
+    // several waves exchanges its inner ends through LDS with a barrier every
+    // step.  Either runs a span 15-25 % slower than a one-wave shape of
+    // about the same work (2^24-node FP32 case: 64x33 68 us, 128x33 77,
+    // 64x65 80, 320x13 85).
+    const bool wide = sh.per_thread > (p.dtype == RSWR_F64 ? 16 : 33);
+    const double cost = nt * TM * std::max(1.0, 512.0 / double(tiles.size())) *
+                        (wide ? 1.25 : 1.0) * (sh.threads > 64 ? 1.25 : 1.0);
     if (!found || cost < best) {
       best = cost;
       found = true;

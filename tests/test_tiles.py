@@ -91,8 +91,15 @@ def test_random_layouts():
 def test_large_case_shape():
     plan = rs.Plan(2 ** 24, 4096, 64, dtype=__import__("torch").float32)
     assert plan.span == 35
-    # one work-group per window, plus one for window 0 (narrower than a tile:
-    # its nodes next to the Dirichlet node come from a second, left-anchored
-    # tile); no general tiles
-    assert plan.info["n_tiles"] == 4097
+    # the default shape is the one-wave 64x33 (wider or multi-wave shapes
+    # run fewer waves per SIMD or a barrier per step): two tiles per window,
+    # one carrying each input's frame; no general tiles
+    assert (plan.info["tile_threads"], plan.info["tile_per_thread"]) == (64, 33)
+    assert plan.info["n_tiles"] == 2 * 4096
     assert plan.tiles()[:, 7].sum() == 0
+    # the widest shape: one tile per window, plus one for window 0 (narrower
+    # than a tile: its nodes next to the Dirichlet node come from a second,
+    # left-anchored tile)
+    wide = rs.Plan(2 ** 24, 4096, 64, dtype=__import__("torch").float32, tile=(64, 65))
+    assert wide.info["n_tiles"] == 4097
+    assert wide.tiles()[:, 7].sum() == 0
