@@ -61,6 +61,7 @@ struct FusedCtx {
   bool dirL, dirR;    // this wave's lane 0 / lane 63 borders a Dirichlet node
   bool fdirL, fdirR;  // this wave's left frame holds node 0 / right frame node M-1
   bool fmL[2], fmR[2];  // which of this lane's frame elements is that node
+  bool fmLc[2], fmRc[2];  // the same in the compact frame (one node per lane)
   bool keep;          // the caller keeps the predicted fluxes
 };
 
@@ -106,6 +107,41 @@ __device__ __forceinline__ T frame_step(const T (&cur)[2], T (&old)[2], T c2, T 
   old[0] = leap(c2, k, l1, cur[0], cur[1], old[0]);
   old[1] = leap(c2, k, cur[0], cur[1], r0, old[1]);
   return f;
+}
+
+// The compact frame: once at most 31 levels are left, the samples need only
+// the nodes within 31 of o, so lane l keeps node o - 32 + l alone (its cut
+// ends reach o +- 1 after 31 levels).  One level: the same samples and the
+// same stencil as frame_step.
+template <typename T>
+__device__ __forceinline__ T frame_step1(const T (&cur)[2], T (&old)[2], T c2, T k, T r) {
+  const T l = lane_shift_z<kWaveShr1>(cur[0]);
+  const T rr = lane_shift_z<kWaveShl1>(cur[0]);
+  const T f = rd_lane((rr - l) * r, 32);  // o + 1 is lane 33, o - 1 lane 31
+  old[0] = leap(c2, k, l, cur[0], rr, old[0]);
+  return f;
+}
+
+// v in lane `src` (per lane), through the lane permute (no LDS storage).
+__device__ __forceinline__ float lane_gather(float v, int src) {
+  return __builtin_bit_cast(float,
+                            __builtin_amdgcn_ds_bpermute(src << 2, __builtin_bit_cast(int, v)));
+}
+__device__ __forceinline__ double lane_gather(double v, int src) {
+  const uint64_t b = __builtin_bit_cast(uint64_t, v);
+  const uint64_t lo = static_cast<uint32_t>(
+      __builtin_amdgcn_ds_bpermute(src << 2, static_cast<int>(static_cast<uint32_t>(b))));
+  const uint64_t hi = static_cast<uint32_t>(
+      __builtin_amdgcn_ds_bpermute(src << 2, static_cast<int>(static_cast<uint32_t>(b >> 32))));
+  return __builtin_bit_cast(double, lo | (hi << 32));
+}
+
+// Two nodes per lane (node o - 64 + 2l + e) -> one (node o - 32 + l, in v[0]).
+template <typename T>
+__device__ __forceinline__ void frame_compact(T (&v)[2], int lane) {
+  const int src = 16 + (lane >> 1);
+  const T a = lane_gather(v[0], src), b = lane_gather(v[1], src);
+  v[0] = (lane & 1) ? b : a;
 }
 
 // A frame of window 0 may hold node 0, one of window N-1 node M-1: those
@@ -163,7 +199,8 @@ __device__ __forceinline__ void frame_sources(const UpdateArgs<T>& p,
 // keeps the fluxes.  The lane shifts fill the wave's ends with zero: the
 // zero data of a cut region end; input ghosts, Dirichlet values and the
 // neighbouring wave's node replace it where they apply.
-template <typename T, int NT, int MPT, bool GEN, bool REC, bool SRC, bool HL, bool HR>
+template <typename T, int NT, int MPT, bool GEN, bool REC, bool SRC, bool HL, bool HR,
+          int FK = 2>
 __device__ __forceinline__ void fused_step(const UpdateArgs<T>& p,
                                            const FusedCtx<T, NT, MPT>& c,
                                            const T (&cur)[MPT], T (&old)[MPT],
@@ -177,10 +214,11 @@ __device__ __forceinline__ void fused_step(const UpdateArgs<T>& p,
   // neighbouring wave's node; the lane shifts below put them in place
   T L0 = T(0), R0 = T(0);
   if constexpr (HL) {
-    const T F = frame_step(lc, lo, p.c2, p.k, p.r);
+    const T F = (FK == 2) ? frame_step(lc, lo, p.c2, p.k, p.r)
+                          : frame_step1(lc, lo, p.c2, p.k, p.r);
     if (c.fdirL) {
       const T d = rd_lane(c.vA, s + 1);
-      frame_dirichlet(true, c.fmL, d, lo);
+      frame_dirichlet(true, FK == 2 ? c.fmL : c.fmLc, d, lo);
     }
     if (SRC && (uni(c.work) & (kWFrame << 0)))
       frame_sources(p, c, 0, c.a - kFrameHalf, s, lo);
@@ -188,10 +226,11 @@ __device__ __forceinline__ void fused_step(const UpdateArgs<T>& p,
     L0 = fma_(c.nq, F, cur[1]);
   }
   if constexpr (HR) {
-    const T F = frame_step(rc, ro, p.c2, p.k, p.r);
+    const T F = (FK == 2) ? frame_step(rc, ro, p.c2, p.k, p.r)
+                          : frame_step1(rc, ro, p.c2, p.k, p.r);
     if (c.fdirR) {
       const T d = rd_lane(c.vB, s + 1);
-      frame_dirichlet(true, c.fmR, d, ro);
+      frame_dirichlet(true, FK == 2 ? c.fmR : c.fmRc, d, ro);
     }
     if (SRC && (uni(c.work) & (kWFrame << 1)))
       frame_sources(p, c, 1, c.a + NT * MPT - 1 - kFrameHalf, s, ro);
@@ -267,12 +306,41 @@ __device__ __forceinline__ void fused_run(const UpdateArgs<T>& p, const Tile& tl
 #pragma unroll
   for (int q = 0; q < kRecSlots; ++q) tr[q] = T(0);
   int s = 0;
-  for (; s + 1 < S; s += 2) {
-    fused_step<T, NT, MPT, GEN, REC, SRC, HL, HR>(p, c, u, uo, lc, lo, rc, ro, fl, fr, tr, s);
-    fused_step<T, NT, MPT, GEN, REC, SRC, HL, HR>(p, c, uo, u, lo, lc, ro, rc, fl, fr, tr, s + 1);
+  if constexpr (!GEN && !REC && !SRC && (HL || HR)) {
+    // the full frame while more than 31 levels are left (from an even step,
+    // so the level roles are the entry ones), then the compact frame
+    const int s0 = S > 31 ? (S - 30) & ~1 : 0;
+    for (; s < s0; s += 2) {
+      fused_step<T, NT, MPT, GEN, REC, SRC, HL, HR>(p, c, u, uo, lc, lo, rc, ro, fl, fr, tr, s);
+      fused_step<T, NT, MPT, GEN, REC, SRC, HL, HR>(p, c, uo, u, lo, lc, ro, rc, fl, fr, tr,
+                                                    s + 1);
+    }
+    if constexpr (HL) {
+      frame_compact(lc, c.lane);
+      frame_compact(lo, c.lane);
+    }
+    if constexpr (HR) {
+      frame_compact(rc, c.lane);
+      frame_compact(ro, c.lane);
+    }
+    for (; s + 1 < S; s += 2) {
+      fused_step<T, NT, MPT, GEN, REC, SRC, HL, HR, 1>(p, c, u, uo, lc, lo, rc, ro, fl, fr, tr,
+                                                       s);
+      fused_step<T, NT, MPT, GEN, REC, SRC, HL, HR, 1>(p, c, uo, u, lo, lc, ro, rc, fl, fr, tr,
+                                                       s + 1);
+    }
+    if (s < S)
+      fused_step<T, NT, MPT, GEN, REC, SRC, HL, HR, 1>(p, c, u, uo, lc, lo, rc, ro, fl, fr, tr,
+                                                       s);
+  } else {
+    for (; s + 1 < S; s += 2) {
+      fused_step<T, NT, MPT, GEN, REC, SRC, HL, HR>(p, c, u, uo, lc, lo, rc, ro, fl, fr, tr, s);
+      fused_step<T, NT, MPT, GEN, REC, SRC, HL, HR>(p, c, uo, u, lo, lc, ro, rc, fl, fr, tr,
+                                                    s + 1);
+    }
+    if (s < S)
+      fused_step<T, NT, MPT, GEN, REC, SRC, HL, HR>(p, c, u, uo, lc, lo, rc, ro, fl, fr, tr, s);
   }
-  if (s < S)
-    fused_step<T, NT, MPT, GEN, REC, SRC, HL, HR>(p, c, u, uo, lc, lo, rc, ro, fl, fr, tr, s);
   // per-span results, one value per lane and step: no stores in the loop
   if (p.flux_out != nullptr && c.lane < S) {
     if constexpr (HL) p.flux_out[static_cast<int64_t>(2 * tl.fl) * p.ld + c.lane] = fl;
@@ -412,6 +480,9 @@ __device__ __forceinline__ void tile_run(const UpdateArgs<T>& p, const Tile& tl,
     c.fmL[e] = oL - kFrameHalf + 2 * c.lane + e == 0;
     c.fmR[e] = oR - kFrameHalf + 2 * c.lane + e == p.M - 1;
   }
+  c.fmLc[0] = oL - kFrameHalf / 2 + c.lane == 0;
+  c.fmRc[0] = oR - kFrameHalf / 2 + c.lane == p.M - 1;
+  c.fmLc[1] = c.fmRc[1] = false;
   c.keep = p.flux_out != nullptr;
   c.nq = in_vgpr(-p.q);
   c.pq = in_vgpr(p.q);
