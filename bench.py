@@ -36,8 +36,8 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
 # --pmc passes (FETCH_SIZE, WRITE_SIZE; see profiles/), and the VALU wave
 # instructions of a full 35-step span (SQ_INSTS_VALU), valid only for the
 # kernel sources with this SHA-256 prefix.
-TRAFFIC = {"kernel_sha": "4eb89f57708e8645", "tile": [64, 33], "bytes": 270271638,
-           "valu_insts": 33058905}
+TRAFFIC = {"kernel_sha": "453a503eb47ed17f", "tile": [64, 33], "bytes": 270410823,
+           "valu_insts": 32596057}
 
 
 def kernel_sha():
