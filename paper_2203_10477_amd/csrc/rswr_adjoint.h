@@ -16,6 +16,8 @@
 // stored forward flux waveforms as ghost data.
 #pragma once
 
+#include <type_traits>
+
 #include "rswr_device.h"
 
 namespace rswr {
@@ -154,13 +156,15 @@ __device__ __forceinline__ void adj_frame_load(const T* w, const int64_t* lo,
 }
 
 // Step s of the frame (cur = W^{L+1}, old = W^{L+2}, L = n_e - s): returns
-// the centred flux at o (wave-uniform); if `adv`, writes W^L over old.
+// the centred flux at o (wave-uniform); if `adv`, writes W^L over old with
+// the sources held in registers added; adj_frame_extra then adds the rest.
+// The register sources of the fused update (NS = kAdjFuseSrc) are added by
+// selects only, so a step of the frame is straight-line code that the
+// compiler can interleave with the tile's own step.
 template <typename T, int NS>
 __device__ __forceinline__ T adj_frame_step(const T (&cur)[2], T (&old)[2],
-                                            const AdjFrame<T, NS>& f, const int64_t* rec_node,
-                                            int n_rec, const T* gtr, int64_t gtr_ld, int64_t M,
-                                            int64_t n_e, T c2, T k, T r, int s, int lane,
-                                            bool adv) {
+                                            const AdjFrame<T, NS>& f, T c2, T k, T r, int s,
+                                            int lane, bool adv) {
   const T l1 = lane_shift_z<kWaveShr1>(cur[1]);
   const T r0 = lane_shift_z<kWaveShl1>(cur[0]);
   const T F = rd_lane((cur[1] - l1) * r, kFrameHalf / 2);
@@ -169,36 +173,49 @@ __device__ __forceinline__ T adj_frame_step(const T (&cur)[2], T (&old)[2],
     T n1 = leap(c2, k, cur[0], cur[1], r0, old[1]);
     n0 = f.dir[0] ? T(0) : n0;
     n1 = f.dir[1] ? T(0) : n1;
-    const int ns = uni(f.nsrc);
+    const int ns = NS > kAdjFuseSrc ? uni(f.nsrc) : f.nsrc;
 #pragma unroll
     for (int q = 0; q < NS; ++q) {
-      if (q < ns) {
+      if (NS <= kAdjFuseSrc || q < ns) {
+        // the source's lane for each of the two elements (-1: none)
         const T g = rd_lane(f.sg[q], s);
-        const int x = uni(f.sx[q]);
-        if (x & 1)
-          n1 = (lane == (x >> 1)) ? n1 + g : n1;
-        else
-          n0 = (lane == (x >> 1)) ? n0 + g : n0;
-      }
-    }
-    if (uni(f.first_extra) < n_rec) {
-      const int64_t L = n_e - s;  // level just computed
-      for (int r = f.first_extra; r < n_rec; ++r) {
-        const int64_t j = rec_node[r];
-        if (j > 0 && j < M - 1 && j >= f.A && j <= f.B) {
-          const T g = gtr[static_cast<int64_t>(r) * gtr_ld + (L - 1)];
-          const int x = static_cast<int>(j - f.base);
-          if (x & 1)
-            n1 = (lane == (x >> 1)) ? n1 + g : n1;
-          else
-            n0 = (lane == (x >> 1)) ? n0 + g : n0;
-        }
+        const int x = f.sx[q];
+        const int t1 = (q < ns && (x & 1)) ? (x >> 1) : -1;
+        const int t0 = (q < ns && !(x & 1)) ? (x >> 1) : -1;
+        n1 = (lane == t1) ? n1 + g : n1;
+        n0 = (lane == t0) ? n0 + g : n0;
       }
     }
     old[0] = n0;
     old[1] = n1;
   }
   return F;
+}
+
+// The frame's sources beyond those in registers, read from memory and added
+// to W^L (in old) in receiver order after a step of adj_frame_step.
+template <typename T, int NS>
+__device__ __forceinline__ void adj_frame_extra(T (&old)[2], const AdjFrame<T, NS>& f,
+                                                const int64_t* rec_node, int n_rec,
+                                                const T* gtr, int64_t gtr_ld, int64_t M,
+                                                int64_t n_e, int s, int lane) {
+  if (uni(f.first_extra) < n_rec) {
+    const int64_t L = n_e - s;  // level just computed
+    T n0 = old[0], n1 = old[1];
+    for (int r = f.first_extra; r < n_rec; ++r) {
+      const int64_t j = rec_node[r];
+      if (j > 0 && j < M - 1 && j >= f.A && j <= f.B) {
+        const T g = gtr[static_cast<int64_t>(r) * gtr_ld + (L - 1)];
+        const int x = static_cast<int>(j - f.base);
+        if (x & 1)
+          n1 = (lane == (x >> 1)) ? n1 + g : n1;
+        else
+          n0 = (lane == (x >> 1)) ? n0 + g : n0;
+      }
+    }
+    old[0] = n0;
+    old[1] = n1;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -241,6 +258,10 @@ struct AdjCtx {
   // readlane); wvu: the wave index as a scalar
   T vLu, vRu, vAu, vBu;
   int wvu;
+  // fused update: the slot sources' dJ/dtrace samples (lane s: step s) and
+  // the element each lane adds them to (-1: none)
+  T vsg[kRecSlots];
+  int vse[kRecSlots];
 };
 
 // W (or a reversed U) one level: old <- leap(cur) with the general tile's
@@ -304,7 +325,12 @@ __device__ __forceinline__ void lap_and_reverse(const T (&wn)[MPT], const T (&uc
 // the sources and write dJ/df; neither: the plain step.
 // FR: fused update; fwL / fwR are this step's samples of the W frames the
 // wave carries (used only by a wave whose region end is an input ghost).
-template <typename T, int NT, int MPT, bool GEN, bool SRC, bool FR>
+// ENDS >= 0: which of those frames the wave carries (bit 0 left, bit 1
+// right) is fixed at compile time; -1: read from the tile's end modes.
+// REV >= 0: whether the step rebuilds U^{L-2} (1) or not (0, the span's
+// last step), fixed at compile time; -1: from tau.
+template <typename T, int NT, int MPT, bool GEN, bool SRC, bool FR, int ENDS = -1,
+          int REV = -1>
 __device__ __forceinline__ void adj_step(const AdjUpdateArgs<T>& p,
                                          const AdjCtx<T, NT, MPT>& c,
                                          const T (&wc)[MPT], T (&wp)[MPT],
@@ -329,6 +355,9 @@ __device__ __forceinline__ void adj_step(const AdjUpdateArgs<T>& p,
       }
       __syncthreads();
     }
+    // a wave at the tile's left (right) end carries that end's frame
+    // exactly when the end is an input ghost, so with ENDS fixed only the
+    // Dirichlet case is left to test
     T Lw0, Lu0, Rw0, Ru0;
     if (NW > 1 && c.wvu > 0) {
       Lw0 = c.edge[par][1][c.wvu - 1];
@@ -337,9 +366,12 @@ __device__ __forceinline__ void adj_step(const AdjUpdateArgs<T>& p,
       const int m = uni(c.lmode);
       Lw0 = T(0);
       Lu0 = T(0);
-      if (m == kEndGhost) {
+      if ((ENDS >= 0) ? (ENDS & 1) != 0 : m == kEndGhost) {
         Lw0 = fma_(-p.q, fwL, wc[1]);
         Lu0 = fma_(-p.q, rd_lane(c.vLu, mi), uc[1]);
+      } else if (ENDS >= 0) {
+        const T d = rd_lane(c.vAu, mi);
+        Lu0 = (m == kEndDirichlet) ? d : T(0);
       } else if (m == kEndDirichlet) {
         Lu0 = rd_lane(c.vAu, mi);
       }
@@ -351,9 +383,12 @@ __device__ __forceinline__ void adj_step(const AdjUpdateArgs<T>& p,
       const int m = uni(c.rmode);
       Rw0 = T(0);
       Ru0 = T(0);
-      if (m == kEndGhost) {
+      if ((ENDS >= 0) ? (ENDS & 2) != 0 : m == kEndGhost) {
         Rw0 = fma_(p.q, fwR, wc[MPT - 2]);
         Ru0 = fma_(p.q, rd_lane(c.vRu, mi), uc[MPT - 2]);
+      } else if (ENDS >= 0) {
+        const T d = rd_lane(c.vBu, mi);
+        Ru0 = (m == kEndDirichlet) ? d : T(0);
       } else if (m == kEndDirichlet) {
         Ru0 = rd_lane(c.vBu, mi);
       }
@@ -404,13 +439,13 @@ __device__ __forceinline__ void adj_step(const AdjUpdateArgs<T>& p,
   } else if (SRC) {  // into lane tau of gf, stored after the loop
 #pragma unroll
     for (int g = 0; g < 2; ++g) {
-      if (c.gwv[g] == c.wv) {
+      if (c.gwv[g] == c.wvu) {
         const T x = rd_lane(elem_at(wc, c.gelem[g]), c.glane[g]);
         gf[g] = wr_lane(p.c2 * x, tau, gf[g], c.lane);
       }
     }
   }
-  const bool rev = tau < S - 1;
+  const bool rev = REV >= 0 ? REV != 0 : tau < S - 1;
   if (GEN && c.gen) {
     const int rn = c.dl + 1;
     const T rw = (rn == MPT) ? Rw : pick<T, MPT>(wc, rn);
@@ -433,8 +468,16 @@ __device__ __forceinline__ void adj_step(const AdjUpdateArgs<T>& p,
     for (int q = 0; q < kRecSlots; ++q) {
       if (GEN) {
         if (q < c.rs.n) inject(c.rs.node[q], c.sg[q][tau]);
-      } else if (q < c.rs.n && c.swv[q] == c.wv) {
-        add_at(wp, c.selem[q], c.sg[q][tau], c.lane == c.slane[q]);
+      } else if (q < c.rs.n && c.swv[q] == c.wvu) {
+        if constexpr (FR) {
+          // a compare per element: no select over the array to fetch and
+          // put back the one element
+          const T g = rd_lane(c.vsg[q], tau);
+#pragma unroll
+          for (int e = 0; e < MPT; ++e) wp[e] = (c.vse[q] == e) ? wp[e] + g : wp[e];
+        } else {
+          add_at(wp, c.selem[q], c.sg[q][tau], c.lane == c.slane[q]);
+        }
       }
     }
     for (int r = c.sb + kRecSlots; r < c.se; ++r)
@@ -454,22 +497,37 @@ __device__ __forceinline__ void adj_step(const AdjUpdateArgs<T>& p,
   }
 }
 
+// Which input-end frames wave wv of tile tl carries in the fused update
+// (bit 0 left, bit 1 right): the tile's ends that are input ghosts, held
+// by its first and last wave.  Wave-uniform.
+template <int NT>
+__device__ __forceinline__ int adj_ends(int wv, const Tile& tl) {
+  constexpr int NW = NT / 64;
+  return __builtin_amdgcn_readfirstlane(((wv == 0 && tl.lmode == kEndGhost) ? 1 : 0) |
+                                        ((wv == NW - 1 && tl.rmode == kEndGhost) ? 2 : 0));
+}
+
 // The span's S steps; returns tau (tau < S: the last step left W^{n_k+1}
 // in wp, else in wc).  FR (fused update): a wave holding the tile's left
 // (hl) or right (hr) input end advances that end's W frame with the tile
 // (the arithmetic of k_adj_predict_frame, so the same samples bit for bit)
 // and takes each step's ghost flux from it; hl / hr are wave-uniform.
-template <typename T, int NT, int MPT, bool GEN, bool SRC, bool FR>
+// ENDS >= 0: the caller has read hl / hr (bits 0 / 1) and each is fixed at
+// compile time; -1: read here.
+template <typename T, int NT, int MPT, bool GEN, bool SRC, bool FR, int ENDS = -1>
 __device__ __forceinline__ int adj_run(const AdjUpdateArgs<T>& p, const AdjCtx<T, NT, MPT>& c,
                                        const Tile& tl, T (&wc)[MPT], T (&wp)[MPT],
                                        T (&uc)[MPT], T (&up)[MPT], int S, double& acc) {
   T gf[2] = {T(0), T(0)};
-  constexpr int NW = NT / 64;
-  const int ends = __builtin_amdgcn_readfirstlane(
-      ((c.wv == 0 && tl.lmode == kEndGhost) ? 1 : 0) |
-      ((c.wv == NW - 1 && tl.rmode == kEndGhost) ? 2 : 0));
-  const bool hl = FR && (uni(ends) & 1) != 0;
-  const bool hr = FR && (uni(ends) & 2) != 0;
+  bool hl, hr;
+  if constexpr (ENDS >= 0) {
+    hl = FR && (ENDS & 1) != 0;
+    hr = FR && (ENDS & 2) != 0;
+  } else {
+    const int ends = adj_ends<NT>(c.wv, tl);
+    hl = FR && (uni(ends) & 1) != 0;
+    hr = FR && (uni(ends) & 2) != 0;
+  }
   T flc[2], flo[2], frc[2], fro[2];  // the frames' two levels, swapped each step
   AdjFrame<T, kAdjFuseSrc> fa, fb;
   if (hl)
@@ -478,23 +536,36 @@ __device__ __forceinline__ int adj_run(const AdjUpdateArgs<T>& p, const AdjCtx<T
   if (hr)
     adj_frame_load(p.w_in, p.lo, p.hi, p.rec_all, p.n_rec_all, p.gtr, p.gtr_ld, p.M, p.n_e,
                    p.hi[tl.fr], tl.fr + 1, S, c.lane, frc, fro, fb);
-  auto step = [&](T (&w0)[MPT], T (&w1)[MPT], T (&u0)[MPT], T (&u1)[MPT], T (&lc)[2],
-                  T (&lo)[2], T (&rc)[2], T (&ro)[2], int t) {
+  // rev: whether the step also rebuilds the forward level two back (every
+  // step but the span's last), fixed per call so a step has no test on it;
+  // the frames' sources beyond the registers come after the tile's step,
+  // off its dependence chain (the frames' new level is needed next step)
+  auto step = [&](auto rev, T (&w0)[MPT], T (&w1)[MPT], T (&u0)[MPT], T (&u1)[MPT],
+                  T (&lc)[2], T (&lo)[2], T (&rc)[2], T (&ro)[2], int t) {
     T fwL = T(0), fwR = T(0);
+    if (hl) fwL = adj_frame_step(lc, lo, fa, p.c2, p.k, p.r, t, c.lane, true);
+    if (hr) fwR = adj_frame_step(rc, ro, fb, p.c2, p.k, p.r, t, c.lane, true);
+    adj_step<T, NT, MPT, GEN, SRC, FR, ENDS, decltype(rev)::value>(p, c, w0, w1, u0, u1, gf, t,
+                                                                   S, acc, fwL, fwR);
     if (hl)
-      fwL = adj_frame_step(lc, lo, fa, p.rec_all, p.n_rec_all, p.gtr, p.gtr_ld, p.M, p.n_e,
-                           p.c2, p.k, p.r, t, c.lane, true);
+      adj_frame_extra(lo, fa, p.rec_all, p.n_rec_all, p.gtr, p.gtr_ld, p.M, p.n_e, t, c.lane);
     if (hr)
-      fwR = adj_frame_step(rc, ro, fb, p.rec_all, p.n_rec_all, p.gtr, p.gtr_ld, p.M, p.n_e,
-                           p.c2, p.k, p.r, t, c.lane, true);
-    adj_step<T, NT, MPT, GEN, SRC, FR>(p, c, w0, w1, u0, u1, gf, t, S, acc, fwL, fwR);
+      adj_frame_extra(ro, fb, p.rec_all, p.n_rec_all, p.gtr, p.gtr_ld, p.M, p.n_e, t, c.lane);
   };
+  using Rev = std::integral_constant<int, 1>;
+  using Last = std::integral_constant<int, 0>;
   int tau = 0;
-  for (; tau + 1 < S; tau += 2) {
-    step(wc, wp, uc, up, flc, flo, frc, fro, tau);
-    step(wp, wc, up, uc, flo, flc, fro, frc, tau + 1);
+  for (; tau + 2 < S; tau += 2) {
+    step(Rev{}, wc, wp, uc, up, flc, flo, frc, fro, tau);
+    step(Rev{}, wp, wc, up, uc, flo, flc, fro, frc, tau + 1);
   }
-  if (tau < S) step(wc, wp, uc, up, flc, flo, frc, fro, tau);
+  if (tau + 1 < S) {  // the last two steps
+    step(Rev{}, wc, wp, uc, up, flc, flo, frc, fro, tau);
+    step(Last{}, wp, wc, up, uc, flo, flc, fro, frc, tau + 1);
+    tau += 2;
+  } else {  // the last step (S odd): W^{n_k+1} is left in wp
+    step(Last{}, wc, wp, uc, up, flc, flo, frc, fro, tau);
+  }
   if (SRC && c.lane < S) {  // dJ/df of levels n_e - lane
     if (c.gwv[0] == c.wv) p.grad_fa[p.n_e - c.lane] = gf[0];
     if (c.gwv[1] == c.wv) p.grad_fb[p.n_e - c.lane] = gf[1];
@@ -622,6 +693,16 @@ __global__ __launch_bounds__(NT) void k_adj_update(const AdjUpdateArgs<T> p0) {
     __syncthreads();
   }
 #pragma unroll
+  for (int q = 0; q < kRecSlots; ++q) {
+    c.vsg[q] = T(0);
+    c.vse[q] = (q < c.rs.n && c.swv[q] == c.wv && c.lane == c.slane[q]) ? c.selem[q] : -1;
+  }
+  if constexpr (FR && MIX) {
+#pragma unroll
+    for (int q = 0; q < kRecSlots; ++q)
+      if (q < c.rs.n && c.lane < S) c.vsg[q] = sg[q][c.lane];
+  }
+#pragma unroll
   for (int i = 0; i < (MPT + 31) / 32; ++i) c.cnt.w[i] = 0u;
 #pragma unroll
   for (int e = 0; e < MPT; ++e) {
@@ -634,6 +715,28 @@ __global__ __launch_bounds__(NT) void k_adj_update(const AdjUpdateArgs<T> p0) {
   int tau;
   if constexpr (GEN) {
     tau = adj_run<T, NT, MPT, true, false, FR>(p, c, tl, wc, wp, uc, up, S, acc);
+  } else if constexpr (MIX && FR) {
+    // a code path per combination of carried frames: no tests on them in
+    // the steps
+    const bool src = c.se > c.sb || c.wr_fa || c.wr_fb;
+    switch (adj_ends<NT>(c.wv, tl)) {
+      case 0:
+        tau = src ? adj_run<T, NT, MPT, false, true, FR, 0>(p, c, tl, wc, wp, uc, up, S, acc)
+                  : adj_run<T, NT, MPT, false, false, FR, 0>(p, c, tl, wc, wp, uc, up, S, acc);
+        break;
+      case 1:
+        tau = src ? adj_run<T, NT, MPT, false, true, FR, 1>(p, c, tl, wc, wp, uc, up, S, acc)
+                  : adj_run<T, NT, MPT, false, false, FR, 1>(p, c, tl, wc, wp, uc, up, S, acc);
+        break;
+      case 2:
+        tau = src ? adj_run<T, NT, MPT, false, true, FR, 2>(p, c, tl, wc, wp, uc, up, S, acc)
+                  : adj_run<T, NT, MPT, false, false, FR, 2>(p, c, tl, wc, wp, uc, up, S, acc);
+        break;
+      default:
+        tau = src ? adj_run<T, NT, MPT, false, true, FR, 3>(p, c, tl, wc, wp, uc, up, S, acc)
+                  : adj_run<T, NT, MPT, false, false, FR, 3>(p, c, tl, wc, wp, uc, up, S, acc);
+        break;
+    }
   } else if constexpr (MIX) {
     if (c.se > c.sb || c.wr_fa || c.wr_fb)
       tau = adj_run<T, NT, MPT, false, true, FR>(p, c, tl, wc, wp, uc, up, S, acc);

@@ -26,12 +26,14 @@ __global__ __launch_bounds__(64) void k_adj_predict_frame(const AdjPredictArgs<T
                  shat, lane, a, b, f);
   T fl = T(0);
   for (int s = 0; s < shat; s += 2) {
-    T F = adj_frame_step(a, b, f, p.rec_node, p.n_rec, p.gtr, p.gtr_ld, p.M, p.n_e, p.c2,
-                         p.k, p.r, s, lane, s < shat - 1);
+    T F = adj_frame_step(a, b, f, p.c2, p.k, p.r, s, lane, s < shat - 1);
+    if (s < shat - 1)
+      adj_frame_extra(b, f, p.rec_node, p.n_rec, p.gtr, p.gtr_ld, p.M, p.n_e, s, lane);
     fl = (lane == s) ? F : fl;
     if (s + 1 < shat) {
-      F = adj_frame_step(b, a, f, p.rec_node, p.n_rec, p.gtr, p.gtr_ld, p.M, p.n_e, p.c2, p.k,
-                         p.r, s + 1, lane, s + 1 < shat - 1);
+      F = adj_frame_step(b, a, f, p.c2, p.k, p.r, s + 1, lane, s + 1 < shat - 1);
+      if (s + 1 < shat - 1)
+        adj_frame_extra(a, f, p.rec_node, p.n_rec, p.gtr, p.gtr_ld, p.M, p.n_e, s + 1, lane);
       fl = (lane == s + 1) ? F : fl;
     }
   }
