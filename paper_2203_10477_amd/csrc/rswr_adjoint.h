@@ -233,6 +233,38 @@ struct ElemMask {
   __device__ __forceinline__ bool has(int e) const { return (w[e >> 5] >> (e & 31)) & 1u; }
 };
 
+// The first kRecSlots sources [b, e) of a tile's list: the loads go out
+// together (indices clamped into the list), one wait for all.
+__device__ __forceinline__ RecSlots adj_slots(const int64_t* node, const int32_t* id, int b,
+                                              int e) {
+  RecSlots r;
+  r.n = (e - b < kRecSlots) ? e - b : kRecSlots;
+#pragma unroll
+  for (int q = 0; q < kRecSlots; ++q) {
+    r.node[q] = kNoNode;
+    r.id[q] = 0;
+  }
+  if (r.n > 0) {
+#pragma unroll
+    for (int q = 0; q < kRecSlots; ++q) {
+      const int i = b + (q < r.n ? q : r.n - 1);
+      const int64_t nd = node[i];
+      const int32_t d = id[i];
+      r.node[q] = q < r.n ? nd : kNoNode;
+      r.id[q] = q < r.n ? d : 0;
+    }
+  }
+  return r;
+}
+
+// A load through a global (not generic) address: it counts only against
+// the vector memory counter, so waits for scalar loads do not wait for it.
+template <typename T>
+__device__ __forceinline__ T gload(const T* ptr) {
+  typedef const __attribute__((address_space(1))) T* GPtr;
+  return *(GPtr)(ptr);
+}
+
 template <typename T, int NT, int MPT>
 struct AdjCtx {
   T (*edge)[4][NT / 64];
@@ -258,8 +290,8 @@ struct AdjCtx {
   // readlane); wvu: the wave index as a scalar
   T vLu, vRu, vAu, vBu;
   int wvu;
-  // fused update: the slot sources' dJ/dtrace samples (lane s: step s) and
-  // the element each lane adds them to (-1: none)
+  // fused update of short rows: the slot sources' dJ/dtrace samples (lane
+  // s: step s) and the element each lane adds them to (-1: none)
   T vsg[kRecSlots];
   int vse[kRecSlots];
 };
@@ -469,9 +501,10 @@ __device__ __forceinline__ void adj_step(const AdjUpdateArgs<T>& p,
       if (GEN) {
         if (q < c.rs.n) inject(c.rs.node[q], c.sg[q][tau]);
       } else if (q < c.rs.n && c.swv[q] == c.wvu) {
-        if constexpr (FR) {
-          // a compare per element: no select over the array to fetch and
-          // put back the one element
+        if constexpr (FR && MPT * sizeof(T) <= 32) {
+          // short rows (fused update): the sample from a lane, a compare per
+          // element, no select over the array to fetch and put back the one
+          // element
           const T g = rd_lane(c.vsg[q], tau);
 #pragma unroll
           for (int e = 0; e < MPT; ++e) wp[e] = (c.vse[q] == e) ? wp[e] + g : wp[e];
@@ -517,7 +550,11 @@ __device__ __forceinline__ int adj_ends(int wv, const Tile& tl) {
 template <typename T, int NT, int MPT, bool GEN, bool SRC, bool FR, int ENDS = -1>
 __device__ __forceinline__ int adj_run(const AdjUpdateArgs<T>& p, const AdjCtx<T, NT, MPT>& c,
                                        const Tile& tl, T (&wc)[MPT], T (&wp)[MPT],
-                                       T (&uc)[MPT], T (&up)[MPT], int S, double& acc) {
+                                       T (&uc)[MPT], T (&up)[MPT], T (&flc)[2], T (&flo)[2],
+                                       T (&frc)[2], T (&fro)[2],
+                                       const AdjFrame<T, kAdjFuseSrc>& fa,
+                                       const AdjFrame<T, kAdjFuseSrc>& fb, int S,
+                                       double& acc) {
   T gf[2] = {T(0), T(0)};
   bool hl, hr;
   if constexpr (ENDS >= 0) {
@@ -528,14 +565,8 @@ __device__ __forceinline__ int adj_run(const AdjUpdateArgs<T>& p, const AdjCtx<T
     hl = FR && (uni(ends) & 1) != 0;
     hr = FR && (uni(ends) & 2) != 0;
   }
-  T flc[2], flo[2], frc[2], fro[2];  // the frames' two levels, swapped each step
-  AdjFrame<T, kAdjFuseSrc> fa, fb;
-  if (hl)
-    adj_frame_load(p.w_in, p.lo, p.hi, p.rec_all, p.n_rec_all, p.gtr, p.gtr_ld, p.M, p.n_e,
-                   p.lo[tl.fl + 1], tl.fl, S, c.lane, flc, flo, fa);
-  if (hr)
-    adj_frame_load(p.w_in, p.lo, p.hi, p.rec_all, p.n_rec_all, p.gtr, p.gtr_ld, p.M, p.n_e,
-                   p.hi[tl.fr], tl.fr + 1, S, c.lane, frc, fro, fb);
+  // flc / flo, frc / fro: the frames' two levels (loaded by the caller where
+  // hl / hr hold), swapped each step
   // rev: whether the step also rebuilds the forward level two back (every
   // step but the span's last), fixed per call so a step has no test on it;
   // the frames' sources beyond the registers come after the tile's step,
@@ -597,29 +628,88 @@ __global__ __launch_bounds__(NT) void k_adj_update(const AdjUpdateArgs<T> p0) {
   int S = p.span < kMaxSpan ? p.span : kMaxSpan;
   if (S <= 0) return;
   const int64_t M = p.M;
+  const int lane = tid & 63;
+  // short rows: the four levels and the frames are read at once
+  constexpr bool kEarlyLoads = MPT * sizeof(T) <= 32;
 
-  for (int s = tid; s < S; s += NT) {
-    const int64_t rr = static_cast<int64_t>(2 * tl.fr + 1) * p.ld + s;
-    const int64_t rl = static_cast<int64_t>(2 * tl.fl + 0) * p.ld + s;
-    sRw[s] = (!FR && tl.fr >= 0) ? p.afl[rr] : T(0);
-    sLw[s] = (!FR && tl.fl >= 0) ? p.afl[rl] : T(0);
-    sRu[s] = (tl.fr >= 0) ? p.ffl[rr] : T(0);
-    sLu[s] = (tl.fl >= 0) ? p.ffl[rl] : T(0);
-    sAu[s] = (s == 0) ? p.u_beg[M] : p.fa[p.n_k + s];
-    sBu[s] = (s == 0) ? p.u_beg[2 * M - 1] : p.fb[p.n_k + s];
+  // The tile's reads that depend on the tile alone go out together, so one
+  // memory latency covers them: the source list range, the fused update's
+  // lane-staged rows, this tile's dJ/dlam partial, the four levels; then
+  // the LDS rows (two-launch update and general tiles) and the transposes.
+  const int sb = ((GEN || MIX) && p.src_ptr) ? p.src_ptr[slot] : 0;
+  const int se = ((GEN || MIX) && p.src_ptr) ? p.src_ptr[slot + 1] : 0;
+  T vLu = T(0), vRu = T(0), vAu = T(0), vBu = T(0);
+  if (FR && lane < S) {
+    if (tl.fl >= 0) vLu = gload(p.ffl + static_cast<int64_t>(2 * tl.fl + 0) * p.ld + lane);
+    if (tl.fr >= 0) vRu = gload(p.ffl + static_cast<int64_t>(2 * tl.fr + 1) * p.ld + lane);
+    vAu = (lane == 0) ? gload(p.u_beg + M) : gload(p.fa + p.n_k + lane);
+    vBu = (lane == 0) ? gload(p.u_beg + 2 * M - 1) : gload(p.fb + p.n_k + lane);
   }
+  // (short rows: this tile's dJ/dlam partial is read now, not at the end)
+  const double lam0 = (kEarlyLoads && tid == 0) ? gload(p.lam_part + tix) : 0.0;
+  auto stage_rows = [&]() {
+    for (int s = tid; s < S; s += NT) {
+      const int64_t rr = static_cast<int64_t>(2 * tl.fr + 1) * p.ld + s;
+      const int64_t rl = static_cast<int64_t>(2 * tl.fl + 0) * p.ld + s;
+      const T a = (!FR && tl.fr >= 0) ? gload(p.afl + rr) : T(0);
+      const T b = (!FR && tl.fl >= 0) ? gload(p.afl + rl) : T(0);
+      const T cr = (tl.fr >= 0) ? gload(p.ffl + rr) : T(0);
+      const T cl = (tl.fl >= 0) ? gload(p.ffl + rl) : T(0);
+      const T da = (s == 0) ? gload(p.u_beg + M) : gload(p.fa + p.n_k + s);
+      const T db = (s == 0) ? gload(p.u_beg + 2 * M - 1) : gload(p.fb + p.n_k + s);
+      sRw[s] = a;
+      sLw[s] = b;
+      sRu[s] = cr;
+      sLu[s] = cl;
+      sAu[s] = da;
+      sBu[s] = db;
+    }
+  };
+  // the fused update of a plain tile reads none of the LDS rows
+  constexpr bool kRows = !FR || GEN;
+  // fused update: the W frames of the tile's input ends, carried by its
+  // first (left) and last (right) wave
+  T flc[2], flo[2], frc[2], fro[2];
+  AdjFrame<T, kAdjFuseSrc> fa, fb;
+  auto load_frames = [&]() {
+    if constexpr (FR) {
+      const int ends = adj_ends<NT>(tid >> 6, tl);
+      if (ends & 1)
+        adj_frame_load(p.w_in, p.lo, p.hi, p.rec_all, p.n_rec_all, p.gtr, p.gtr_ld, M, p.n_e,
+                       p.lo[tl.fl + 1], tl.fl, S, lane, flc, flo, fa);
+      if (ends & 2)
+        adj_frame_load(p.w_in, p.lo, p.hi, p.rec_all, p.n_rec_all, p.gtr, p.gtr_ld, M, p.n_e,
+                       p.hi[tl.fr], tl.fr + 1, S, lane, frc, fro, fb);
+    }
+  };
 
   T wc[MPT], wp[MPT], uc[MPT], up[MPT];
-  {
+  if constexpr (kEarlyLoads) {
+    T t0[MPT], t1[MPT], t2[MPT], t3[MPT];
+    load_level<T, NT, MPT>(p.w_in + M, tl.a, M, t0);
+    load_level<T, NT, MPT>(p.w_in, tl.a, M, t1);
+    load_level<T, NT, MPT>(p.u_end, tl.a, M, t2);
+    load_level<T, NT, MPT>(p.u_end + M, tl.a, M, t3);
+    if constexpr (kRows) stage_rows();
+    load_frames();
+    transpose_in<T, NT, MPT>(t0, st, wc);  // W^{n_e+1}
+    transpose_in<T, NT, MPT>(t1, st, wp);  // W^{n_e+2}
+    transpose_in<T, NT, MPT>(t2, st, uc);  // U^{n_e-1}
+    transpose_in<T, NT, MPT>(t3, st, up);  // U^{n_e}
+  } else {
+    // (longer rows: one level in flight at a time and the frames after the
+    // levels, to bound the registers)
+    if constexpr (kRows) stage_rows();
     T t[MPT];
     load_level<T, NT, MPT>(p.w_in + M, tl.a, M, t);
-    transpose_in<T, NT, MPT>(t, st, wc);  // W^{n_e+1}
+    transpose_in<T, NT, MPT>(t, st, wc);
     load_level<T, NT, MPT>(p.w_in, tl.a, M, t);
-    transpose_in<T, NT, MPT>(t, st, wp);  // W^{n_e+2}
+    transpose_in<T, NT, MPT>(t, st, wp);
     load_level<T, NT, MPT>(p.u_end, tl.a, M, t);
-    transpose_in<T, NT, MPT>(t, st, uc);  // U^{n_e-1}
+    transpose_in<T, NT, MPT>(t, st, uc);
     load_level<T, NT, MPT>(p.u_end + M, tl.a, M, t);
-    transpose_in<T, NT, MPT>(t, st, up);  // U^{n_e}
+    transpose_in<T, NT, MPT>(t, st, up);
+    load_frames();
   }
 
   AdjCtx<T, NT, MPT> c;
@@ -636,14 +726,10 @@ __global__ __launch_bounds__(NT) void k_adj_update(const AdjUpdateArgs<T> p0) {
   c.wvu = __builtin_amdgcn_readfirstlane(tid >> 6);
   c.lmode = __builtin_amdgcn_readfirstlane(tl.lmode);
   c.rmode = __builtin_amdgcn_readfirstlane(tl.rmode);
-  c.vLu = c.vRu = c.vAu = c.vBu = T(0);
-  if (FR && c.lane < S) {
-    const int s = c.lane;
-    if (tl.fl >= 0) c.vLu = p.ffl[static_cast<int64_t>(2 * tl.fl + 0) * p.ld + s];
-    if (tl.fr >= 0) c.vRu = p.ffl[static_cast<int64_t>(2 * tl.fr + 1) * p.ld + s];
-    c.vAu = (s == 0) ? p.u_beg[M] : p.fa[p.n_k + s];
-    c.vBu = (s == 0) ? p.u_beg[2 * M - 1] : p.fb[p.n_k + s];
-  }
+  c.vLu = vLu;
+  c.vRu = vRu;
+  c.vAu = vAu;
+  c.vBu = vBu;
   auto rel = [](int64_t node, int64_t base) -> int {
     const int64_t d = node - base;
     return (d < -2 || d > MPT + 1) ? -1000 : static_cast<int>(d);
@@ -660,9 +746,9 @@ __global__ __launch_bounds__(NT) void k_adj_update(const AdjUpdateArgs<T> p0) {
                       (c.dM >= 0 && c.dM < MPT);
     c.gen = GEN && (__any(mine) != 0);
   }
-  c.sb = ((GEN || MIX) && p.src_ptr) ? p.src_ptr[slot] : 0;
-  c.se = ((GEN || MIX) && p.src_ptr) ? p.src_ptr[slot + 1] : 0;
-  c.rs = (GEN || MIX) ? load_slots(p.src_node, p.src_id, c.sb, c.se) : RecSlots{0, {}, {}};
+  c.sb = sb;
+  c.se = se;
+  c.rs = (GEN || MIX) ? adj_slots(p.src_node, p.src_id, c.sb, c.se) : RecSlots{0, {}, {}};
   c.sg = sg;
   {
     // wave-uniform positions: tile offset x lies in thread x / MPT,
@@ -681,8 +767,25 @@ __global__ __launch_bounds__(NT) void k_adj_update(const AdjUpdateArgs<T> p0) {
     place(c.wr_fa, 1, c.gwv[0], c.glane[0], c.gelem[0]);
     place(c.wr_fb, M - 2, c.gwv[1], c.glane[1], c.gelem[1]);
   }
-  if (GEN || MIX) {
-    // dJ/dtrace of the slot sources at levels n_e-1-tau, tau = 0..S-1
+  // dJ/dtrace of the slot sources at levels n_e-1-tau, tau = 0..S-1: one
+  // per lane for the fused update of a plain tile with short rows, in LDS
+  // otherwise
+  constexpr bool kLaneSrc = FR && MIX && kEarlyLoads;
+#pragma unroll
+  for (int q = 0; q < kRecSlots; ++q) {
+    c.vsg[q] = T(0);
+    c.vse[q] = (kLaneSrc && q < c.rs.n && c.swv[q] == c.wv && c.lane == c.slane[q])
+                   ? c.selem[q]
+                   : -1;
+  }
+  if constexpr (kLaneSrc) {
+#pragma unroll
+    for (int q = 0; q < kRecSlots; ++q) {
+      if (q < c.rs.n && c.lane < S)
+        c.vsg[q] = gload(p.gtr + static_cast<int64_t>(c.rs.id[q]) * p.gtr_ld + (p.n_e - 1) -
+                         c.lane);
+    }
+  } else if constexpr (GEN || MIX) {
 #pragma unroll
     for (int q = 0; q < kRecSlots; ++q) {
       if (q < c.rs.n) {
@@ -691,16 +794,6 @@ __global__ __launch_bounds__(NT) void k_adj_update(const AdjUpdateArgs<T> p0) {
       }
     }
     __syncthreads();
-  }
-#pragma unroll
-  for (int q = 0; q < kRecSlots; ++q) {
-    c.vsg[q] = T(0);
-    c.vse[q] = (q < c.rs.n && c.swv[q] == c.wv && c.lane == c.slane[q]) ? c.selem[q] : -1;
-  }
-  if constexpr (FR && MIX) {
-#pragma unroll
-    for (int q = 0; q < kRecSlots; ++q)
-      if (q < c.rs.n && c.lane < S) c.vsg[q] = sg[q][c.lane];
   }
 #pragma unroll
   for (int i = 0; i < (MPT + 31) / 32; ++i) c.cnt.w[i] = 0u;
@@ -712,38 +805,61 @@ __global__ __launch_bounds__(NT) void k_adj_update(const AdjUpdateArgs<T> p0) {
   }
 
   double acc = 0.0;
+  // run<SRC, ENDS>: the span's steps on the path for those (GEN: ENDS -1)
+  auto run = [&](auto src, auto ends) -> int {
+    return adj_run<T, NT, MPT, GEN, decltype(src)::value, FR, decltype(ends)::value>(
+        p, c, tl, wc, wp, uc, up, flc, flo, frc, fro, fa, fb, S, acc);
+  };
+  using Plain = std::false_type;
+  using Src = std::true_type;
   int tau;
   if constexpr (GEN) {
-    tau = adj_run<T, NT, MPT, true, false, FR>(p, c, tl, wc, wp, uc, up, S, acc);
+    tau = run(Plain{}, std::integral_constant<int, -1>{});
   } else if constexpr (MIX && FR) {
-    // a code path per combination of carried frames: no tests on them in
-    // the steps
+    // a code path per carried frame, so the steps test for none; a wave
+    // carrying both (a window no wider than a tile), and on longer rows one
+    // with sources, take the path that tests for them, which needs fewer
+    // registers than both fixed
     const bool src = c.se > c.sb || c.wr_fa || c.wr_fb;
-    switch (adj_ends<NT>(c.wv, tl)) {
-      case 0:
-        tau = src ? adj_run<T, NT, MPT, false, true, FR, 0>(p, c, tl, wc, wp, uc, up, S, acc)
-                  : adj_run<T, NT, MPT, false, false, FR, 0>(p, c, tl, wc, wp, uc, up, S, acc);
-        break;
-      case 1:
-        tau = src ? adj_run<T, NT, MPT, false, true, FR, 1>(p, c, tl, wc, wp, uc, up, S, acc)
-                  : adj_run<T, NT, MPT, false, false, FR, 1>(p, c, tl, wc, wp, uc, up, S, acc);
-        break;
-      case 2:
-        tau = src ? adj_run<T, NT, MPT, false, true, FR, 2>(p, c, tl, wc, wp, uc, up, S, acc)
-                  : adj_run<T, NT, MPT, false, false, FR, 2>(p, c, tl, wc, wp, uc, up, S, acc);
-        break;
-      default:
-        tau = src ? adj_run<T, NT, MPT, false, true, FR, 3>(p, c, tl, wc, wp, uc, up, S, acc)
-                  : adj_run<T, NT, MPT, false, false, FR, 3>(p, c, tl, wc, wp, uc, up, S, acc);
-        break;
+    const int ends = adj_ends<NT>(c.wv, tl);
+    using Any = std::integral_constant<int, -1>;
+    using E0 = std::integral_constant<int, 0>;
+    using E1 = std::integral_constant<int, 1>;
+    using E2 = std::integral_constant<int, 2>;
+    if constexpr (MPT * sizeof(T) <= 32) {
+      if (ends == 3) {
+        tau = src ? run(Src{}, Any{}) : run(Plain{}, Any{});
+      } else if (ends == 0) {
+        tau = src ? run(Src{}, E0{}) : run(Plain{}, E0{});
+      } else if (ends == 1) {
+        tau = src ? run(Src{}, E1{}) : run(Plain{}, E1{});
+      } else {
+        tau = src ? run(Src{}, E2{}) : run(Plain{}, E2{});
+      }
+    } else if constexpr (MPT * sizeof(T) <= 64) {
+      if (src) {
+        tau = run(Src{}, Any{});
+      } else if (ends == 3) {
+        tau = run(Plain{}, Any{});
+      } else if (ends == 0) {
+        tau = run(Plain{}, E0{});
+      } else if (ends == 1) {
+        tau = run(Plain{}, E1{});
+      } else {
+        tau = run(Plain{}, E2{});
+      }
+    } else {
+      // rows of 128 bytes and more: one path that tests for the frames
+      // (fewest registers; the state itself fills most of them)
+      tau = src ? run(Src{}, Any{}) : run(Plain{}, Any{});
     }
   } else if constexpr (MIX) {
     if (c.se > c.sb || c.wr_fa || c.wr_fb)
-      tau = adj_run<T, NT, MPT, false, true, FR>(p, c, tl, wc, wp, uc, up, S, acc);
+      tau = run(Src{}, std::integral_constant<int, -1>{});
     else
-      tau = adj_run<T, NT, MPT, false, false, FR>(p, c, tl, wc, wp, uc, up, S, acc);
+      tau = run(Plain{}, std::integral_constant<int, -1>{});
   } else {
-    tau = adj_run<T, NT, MPT, false, false, FR>(p, c, tl, wc, wp, uc, up, S, acc);
+    tau = run(Plain{}, std::integral_constant<int, -1>{});
   }
   const int64_t rlo = tl.out_lo > tl.a ? tl.out_lo : tl.a;
   const int64_t rhi = tl.out_hi < tl.a + TM - 1 ? tl.out_hi : tl.a + TM - 1;
@@ -773,7 +889,7 @@ __global__ __launch_bounds__(NT) void k_adj_update(const AdjUpdateArgs<T> p0) {
   if (tid == 0) {
     double t = 0.0;
     for (int w = 0; w < NW; ++w) t += red[w];
-    p.lam_part[tix] += t;
+    p.lam_part[tix] = (kEarlyLoads ? lam0 : p.lam_part[tix]) + t;
   }
 }
 
