@@ -225,12 +225,14 @@ __device__ __forceinline__ void adj_frame_extra(T (&old)[2], const AdjFrame<T, N
 // W^L by the leapfrog (+ sources, general tiles), the dJ/dlam terms of the
 // stored interior nodes, then U^{L-2} by the reversed leapfrog.
 // ---------------------------------------------------------------------------
-// Per-lane element mask: bit e % 32 of word e / 32 for element e (one word
-// per 32 elements, so shapes with more than 32 nodes per lane are covered).
-template <int MPT>
-struct ElemMask {
-  uint32_t w[(MPT + 31) / 32];
-  __device__ __forceinline__ bool has(int e) const { return (w[e >> 5] >> (e & 31)) & 1u; }
+// A lane's counted elements (stored interior nodes, whose dJ/dlam terms
+// count): one run lo .. lo + n - 1 of its MPT consecutive nodes, since the
+// nodes counted are those of the intersection of two node ranges.  The
+// test is made per step on values re-read through an empty asm statement:
+// a mask per element hoisted out of the step loop would need a register
+// pair each (with 33 nodes per lane, more than the scalar file holds).
+struct ElemRun {
+  int lo, n;
 };
 
 // The first kRecSlots sources [b, e) of a tile's list: the loads go out
@@ -277,7 +279,7 @@ struct AdjCtx {
   int64_t base;
   int dl, d0, dM, d1, dM2;
   int sb, se, lane, wv, lmode, rmode;
-  ElemMask<MPT> cnt;  // element e is stored and interior (enters dJ/dlam)
+  ElemRun cnt;  // elements stored and interior (enter dJ/dlam)
   bool gen, wr_fa, wr_fb;
   RecSlots rs;          // the tile's first sources (GEN, SRC)
   const T (*sg)[kMaxSpan];  // their dJ/dtrace samples of this span, by step
@@ -324,9 +326,11 @@ template <typename T, int MPT, bool GEN>
 __device__ __forceinline__ void lap_and_reverse(const T (&wn)[MPT], const T (&ucur)[MPT],
                                                 T (&uold)[MPT], T L, T R, T c2, T k,
                                                 int dl, int d0, int dM, T ghost, T pin0,
-                                                T pinM, const ElemMask<MPT>& cnt, bool rev,
+                                                T pinM, const ElemRun& cnt, bool rev,
                                                 double& acc) {
   T step = T(0);
+  int clo = cnt.lo, cn = cnt.n;
+  asm volatile("" : "+v"(clo), "+v"(cn));
 #pragma unroll
   for (int e = 0; e < MPT; ++e) {
     T ul = (e == 0) ? L : ucur[e - 1];
@@ -335,7 +339,8 @@ __device__ __forceinline__ void lap_and_reverse(const T (&wn)[MPT], const T (&uc
     const T s = ul + ur;
     // s - 2u in one rounding: 2u is exact, so the fused form rounds the same
     const T lap = fma_(T(-2), ucur[e], s);
-    const T lapm = cnt.has(e) ? lap : T(0);
+    const bool counted = static_cast<unsigned>(e - clo) < static_cast<unsigned>(cn);
+    const T lapm = counted ? lap : T(0);
     if constexpr (sizeof(T) == 4)
       step = fma_(wn[e], lapm, step);
     else
@@ -608,7 +613,16 @@ __device__ __forceinline__ int adj_run(const AdjUpdateArgs<T>& p, const AdjCtx<T
 // nodes 1 / M-2 take the SRC step, the rest the plain one (a uniform branch
 // per work-group).  FR: fused update (no adjoint flux rows: the tiles
 // predict their input ends themselves; fused plans only).
-template <typename T, int NT, int MPT, bool GEN, bool MIX, bool FR>
+// PART (MIX only): 0 every tile; 1 the tiles without sources and not
+// holding nodes 1 / M-2; 2 the others.  Launched as parts 1 and 2, each
+// kernel is allocated the registers of its own path: on long rows the
+// source path needs more than the registers that keep two waves per SIMD.
+template <typename T, int MPT>
+constexpr bool adj_split_mix() {
+  return MPT * sizeof(T) > 64;
+}
+
+template <typename T, int NT, int MPT, bool GEN, bool MIX, bool FR, int PART = 0>
 __global__ __launch_bounds__(NT) void k_adj_update(const AdjUpdateArgs<T> p0) {
   const AdjUpdateArgs<T> p = batch_problem(p0);
   constexpr int NW = NT / 64;
@@ -638,6 +652,11 @@ __global__ __launch_bounds__(NT) void k_adj_update(const AdjUpdateArgs<T> p0) {
   // the LDS rows (two-launch update and general tiles) and the transposes.
   const int sb = ((GEN || MIX) && p.src_ptr) ? p.src_ptr[slot] : 0;
   const int se = ((GEN || MIX) && p.src_ptr) ? p.src_ptr[slot + 1] : 0;
+  if constexpr (MIX && PART != 0) {
+    const bool src = se > sb || (tl.out_lo <= 1 && 1 <= tl.out_hi) ||
+                     (tl.out_lo <= M - 2 && M - 2 <= tl.out_hi);
+    if (src != (PART == 2)) return;  // the other part's tile
+  }
   T vLu = T(0), vRu = T(0), vAu = T(0), vBu = T(0);
   if (FR && lane < S) {
     if (tl.fl >= 0) vLu = gload(p.ffl + static_cast<int64_t>(2 * tl.fl + 0) * p.ld + lane);
@@ -795,13 +814,14 @@ __global__ __launch_bounds__(NT) void k_adj_update(const AdjUpdateArgs<T> p0) {
     }
     __syncthreads();
   }
-#pragma unroll
-  for (int i = 0; i < (MPT + 31) / 32; ++i) c.cnt.w[i] = 0u;
-#pragma unroll
-  for (int e = 0; e < MPT; ++e) {
-    const int64_t j = c.base + e;
-    const bool counts = j >= tl.out_lo && j <= tl.out_hi && j > 0 && j < M - 1;
-    c.cnt.w[e >> 5] |= counts ? (1u << (e & 31)) : 0u;
+  {
+    // nodes max(out_lo, 1) .. min(out_hi, M-2), as this lane's elements
+    const int64_t first = (tl.out_lo > 1 ? tl.out_lo : 1) - c.base;
+    const int64_t last = (tl.out_hi < M - 2 ? tl.out_hi : M - 2) - c.base;
+    const int64_t lo = first > 0 ? first : 0;
+    const int64_t hi = last < MPT - 1 ? last : MPT - 1;
+    c.cnt.lo = static_cast<int>(lo < MPT ? lo : MPT);
+    c.cnt.n = hi >= lo ? static_cast<int>(hi - lo + 1) : 0;
   }
 
   double acc = 0.0;
@@ -848,11 +868,19 @@ __global__ __launch_bounds__(NT) void k_adj_update(const AdjUpdateArgs<T> p0) {
       } else {
         tau = run(Plain{}, E2{});
       }
-    } else {
+    } else if constexpr (PART == 1) {
       // rows of 128 bytes and more: one path that tests for the frames
       // (fewest registers; the state itself fills most of them)
+      tau = run(Plain{}, Any{});
+    } else if constexpr (PART == 2) {
+      tau = run(Src{}, Any{});
+    } else {
       tau = src ? run(Src{}, Any{}) : run(Plain{}, Any{});
     }
+  } else if constexpr (MIX && PART == 1) {
+    tau = run(Plain{}, std::integral_constant<int, -1>{});
+  } else if constexpr (MIX && PART == 2) {
+    tau = run(Src{}, std::integral_constant<int, -1>{});
   } else if constexpr (MIX) {
     if (c.se > c.sb || c.wr_fa || c.wr_fb)
       tau = run(Src{}, std::integral_constant<int, -1>{});
@@ -895,42 +923,57 @@ __global__ __launch_bounds__(NT) void k_adj_update(const AdjUpdateArgs<T> p0) {
 
 // Launch of the update kernels of one kind (FR: fused update); the library
 // instantiates FR = false in rswr_adjoint.hip and FR = true in
-// rswr_adjoint_fused_*.hip, one translation unit each.
+// rswr_adjoint_fused_*.hip, one translation unit each.  Plain (not general)
+// tiles of long rows go out as two launches, the parts of k_adj_update.
+template <typename T, int NT, int MPT, bool FR>
+hipError_t launch_adj_update_shape(const AdjUpdateArgs<T>& a, bool general, hipStream_t s) {
+  const dim3 grid(a.n_tiles, ny(a.ys));
+  if (general) {
+    hipLaunchKernelGGL((k_adj_update<T, NT, MPT, true, false, FR>), grid, dim3(NT), 0, s, a);
+  } else if constexpr (adj_split_mix<T, MPT>()) {
+    hipLaunchKernelGGL((k_adj_update<T, NT, MPT, false, true, FR, 1>), grid, dim3(NT), 0, s, a);
+    hipLaunchKernelGGL((k_adj_update<T, NT, MPT, false, true, FR, 2>), grid, dim3(NT), 0, s, a);
+  } else {
+    hipLaunchKernelGGL((k_adj_update<T, NT, MPT, false, true, FR>), grid, dim3(NT), 0, s, a);
+  }
+  return hipGetLastError();
+}
+
 template <typename T, bool FR>
 hipError_t launch_adj_update_kind(const AdjUpdateArgs<T>& a, int threads, int per_thread,
                                   bool general, hipStream_t s) {
   if (a.n_tiles <= 0) return hipSuccess;
-#define RSWR_ADJ_LAUNCH(NT_, MPT_)                                                  \
-  if (threads == NT_ && per_thread == MPT_) {                                     \
-    if (general)                                                                  \
-      hipLaunchKernelGGL((k_adj_update<T, NT_, MPT_, true, false, FR>),          \
-                         dim3(a.n_tiles, ny(a.ys)), dim3(NT_), 0, s, a);          \
-    else                                                                          \
-      hipLaunchKernelGGL((k_adj_update<T, NT_, MPT_, false, true, FR>),          \
-                         dim3(a.n_tiles, ny(a.ys)), dim3(NT_), 0, s, a);          \
-    return hipGetLastError();                                                     \
-  }
+#define RSWR_ADJ_LAUNCH(NT_, MPT_)              \
+  if (threads == NT_ && per_thread == MPT_)   \
+    return launch_adj_update_shape<T, NT_, MPT_, FR>(a, general, s);
   RSWR_SHAPES(RSWR_ADJ_LAUNCH)
 #undef RSWR_ADJ_LAUNCH
   return hipErrorInvalidValue;
 }
 
-// Whether both fused update kernels of a shape keep their state in
+// Whether the fused update kernels of a shape keep their state in
 // registers (no scratch): the fused adjoint runs only there.
+template <typename T, int NT, int MPT>
+bool adj_update_fused_fits_shape() {
+  auto no_scratch = [](const void* f) {
+    hipFuncAttributes at{};
+    return hipFuncGetAttributes(&at, f) == hipSuccess && at.localSizeBytes == 0;
+  };
+  if (!no_scratch(reinterpret_cast<const void*>(k_adj_update<T, NT, MPT, true, false, true>)))
+    return false;
+  if constexpr (adj_split_mix<T, MPT>())
+    return no_scratch(reinterpret_cast<const void*>(
+               k_adj_update<T, NT, MPT, false, true, true, 1>)) &&
+           no_scratch(reinterpret_cast<const void*>(
+               k_adj_update<T, NT, MPT, false, true, true, 2>));
+  else
+    return no_scratch(reinterpret_cast<const void*>(k_adj_update<T, NT, MPT, false, true, true>));
+}
+
 template <typename T>
 bool adj_update_fused_fits(int threads, int per_thread) {
-#define RSWR_ADJ_FIT(NT_, MPT_)                                                          \
-  if (threads == NT_ && per_thread == MPT_) {                                          \
-    hipFuncAttributes g{}, f{};                                                        \
-    if (hipFuncGetAttributes(&g, reinterpret_cast<const void*>(                        \
-                                     k_adj_update<T, NT_, MPT_, true, false, true>)) !=  \
-            hipSuccess ||                                                              \
-        hipFuncGetAttributes(&f, reinterpret_cast<const void*>(                        \
-                                     k_adj_update<T, NT_, MPT_, false, true, true>)) !=  \
-            hipSuccess)                                                                \
-      return false;                                                                    \
-    return g.localSizeBytes == 0 && f.localSizeBytes == 0;                             \
-  }
+#define RSWR_ADJ_FIT(NT_, MPT_) \
+  if (threads == NT_ && per_thread == MPT_) return adj_update_fused_fits_shape<T, NT_, MPT_>();
   RSWR_SHAPES(RSWR_ADJ_FIT)
 #undef RSWR_ADJ_FIT
   return false;

@@ -46,8 +46,8 @@ CASES = [
     # four receivers (one repeated) in the frame around node 510, two beyond
     # the registers the fused update gives a frame's sources
     (1001, 2, 20, None, 600, [3, 489, 500, 505, 505, 510, 990]),
-    # FP64 at this shape: the fused update would need scratch, so the fused
-    # plan's adjoint keeps the predict launch
+    # FP64 rows of 96 bytes per lane: the fused update's plain tiles and its
+    # tiles with sources go out as two launches
     (40001, 8, 64, (512, 12), 200, [7, 5000, 5001, 20000, 39999]),
 ]
 
@@ -199,9 +199,14 @@ def test_fused_adjoint_equals_two_launch(case, dtype):
     assert not plans[1].info["fused"] and not rs.rswr_adjoint_fused(plans[1])
     if not plans[0].info["fused"]:
         pytest.skip("plan does not run the fused span")
-    # the fused adjoint runs, except where its FP64 kernels would spill
-    spills = dtype == torch.float64 and tile == (512, 12)
-    assert rs.rswr_adjoint_fused(plans[0]) == (not spills)
+    # every shape here keeps the fused update in registers
+    assert rs.rswr_adjoint_fused(plans[0])
+    assert adjoint_gradients_equal(plans, case, dtype, n_steps, rec)
+
+
+def adjoint_gradients_equal(plans, case, dtype, n_steps, rec):
+    """Gradients of the same seeded problem from each plan, compared bit for
+    bit."""
     g = np.random.default_rng(100 + case)
     fa = g.standard_normal(n_steps + 1)
     fa[0] = 0.0
@@ -216,9 +221,22 @@ def test_fused_adjoint_equals_two_launch(case, dtype):
                                            rec, dev(w, dtype))
         torch.cuda.synchronize()
         out.append((ga.cpu().numpy(), gb.cpu().numpy(), float(gl.item())))
-    assert np.array_equal(out[0][0], out[1][0])
-    assert np.array_equal(out[0][1], out[1][1])
-    assert out[0][2] == out[1][2]
+    return (np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][1], out[1][1])
+            and out[0][2] == out[1][2])
+
+
+def test_fused_adjoint_falls_back_where_it_would_spill():
+    """FP32 at 64x65 the fused update's general-tile kernel would need
+    scratch memory: the fused plan's adjoint keeps the predict launch and
+    gives the two-launch plan's gradients bit for bit."""
+    M, N, P, tile, n_steps = 40001, 8, 64, (64, 65), 200
+    rec = [7, 5000, 5001, 20000, 39999]
+    say("fused-adjoint fallback", tile)
+    dt = torch.float32
+    plans = [rs.Plan(M, N, P, tile=tile, dtype=dt, fuse=f) for f in (True, False)]
+    assert plans[0].info["fused"] and not plans[1].info["fused"]
+    assert not rs.rswr_adjoint_fused(plans[0]) and not rs.rswr_adjoint_fused(plans[1])
+    assert adjoint_gradients_equal(plans, len(CASES), dt, n_steps, rec)
 
 
 @pytest.mark.parametrize("tile", [(64, 33), (128, 33), (64, 65)])
