@@ -227,10 +227,11 @@ __device__ __forceinline__ void adj_frame_extra(T (&old)[2], const AdjFrame<T, N
 // ---------------------------------------------------------------------------
 // A lane's counted elements (stored interior nodes, whose dJ/dlam terms
 // count): one run lo .. lo + n - 1 of its MPT consecutive nodes, since the
-// nodes counted are those of the intersection of two node ranges.  The
-// test is made per step on values re-read through an empty asm statement:
-// a mask per element hoisted out of the step loop would need a register
-// pair each (with 33 nodes per lane, more than the scalar file holds).
+// nodes counted are those of the intersection of two node ranges.  On long
+// rows the test is made per step on values re-read through an empty asm
+// statement: a mask per element hoisted out of the step loop would need a
+// register pair each (with 33 nodes per lane, more than the scalar file
+// holds); short rows keep the hoisted masks.
 struct ElemRun {
   int lo, n;
 };
@@ -330,7 +331,7 @@ __device__ __forceinline__ void lap_and_reverse(const T (&wn)[MPT], const T (&uc
                                                 double& acc) {
   T step = T(0);
   int clo = cnt.lo, cn = cnt.n;
-  asm volatile("" : "+v"(clo), "+v"(cn));
+  if constexpr (MPT * sizeof(T) > 64) asm volatile("" : "+v"(clo), "+v"(cn));
 #pragma unroll
   for (int e = 0; e < MPT; ++e) {
     T ul = (e == 0) ? L : ucur[e - 1];
