@@ -225,6 +225,21 @@ def adjoint_gradients_equal(plans, case, dtype, n_steps, rec):
             and out[0][2] == out[1][2])
 
 
+@pytest.mark.parametrize("tile", [(64, 33), (128, 33), (192, 22)])
+def test_fused_adjoint_long_rows_fp32(tile):
+    """FP32 rows above 64 bytes per lane: the fused update runs as two
+    launches (plain tiles, then tiles with sources or holding nodes 1 and
+    M-2), bitwise equal to the two-launch adjoint; receivers on nodes 1 and
+    M-2, beside window ends and in one tile's interior."""
+    M, N, P, n_steps = 40001, 8, 64, 300
+    rec = [1, 4990, 5000, 5001, 5070, 20000, 20001, 39999]
+    say("fused-adjoint long rows fp32", tile)
+    dt = torch.float32
+    plans = [rs.Plan(M, N, P, tile=tile, dtype=dt, fuse=f) for f in (True, False)]
+    assert plans[0].info["fused"] and rs.rswr_adjoint_fused(plans[0])
+    assert adjoint_gradients_equal(plans, len(CASES) + 1, dt, n_steps, rec)
+
+
 def test_fused_adjoint_falls_back_where_it_would_spill():
     """FP32 at 64x65 the fused update's general-tile kernel would need
     scratch memory: the fused plan's adjoint keeps the predict launch and
