@@ -870,8 +870,8 @@ __global__ __launch_bounds__(NT) void k_adj_update(const AdjUpdateArgs<T> p0) {
         tau = run(Plain{}, E2{});
       }
     } else if constexpr (PART == 1) {
-      // rows of 128 bytes and more: one path that tests for the frames
-      // (fewest registers; the state itself fills most of them)
+      // rows above 64 bytes: one path that tests for the frames (fewest
+      // registers; the state itself fills most of them)
       tau = run(Plain{}, Any{});
     } else if constexpr (PART == 2) {
       tau = run(Src{}, Any{});
