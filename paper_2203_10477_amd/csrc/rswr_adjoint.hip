@@ -107,16 +107,26 @@ __global__ __launch_bounds__(256) void k_adj_finish(T* grad_fa, T* grad_fb, cons
                                                    double lam, double* grad_lam) {
   __shared__ double red[256];
   const int tid = threadIdx.x;
-  for (int64_t L = 1 + tid; L <= n_steps; L += 256) {
+  // dJ/df: receivers on the Dirichlet nodes add their dJ/dtrace sample, in
+  // receiver order (levels spread over the grid; the others are not read)
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * 256;
+  for (int64_t L = 1 + static_cast<int64_t>(blockIdx.x) * 256 + tid; L <= n_steps;
+       L += stride) {
     T ga = grad_fa[L], gb = grad_fb[L];
     for (int r = 0; r < n_rec; ++r) {
-      const T g = gtr[static_cast<int64_t>(r) * gtr_ld + (L - 1)];
-      if (rec_node[r] == 0) ga = ga + g;
-      if (rec_node[r] == M - 1) gb = gb + g;
+      const int64_t j = rec_node[r];
+      if (j == 0 || j == M - 1) {
+        const T g = gtr[static_cast<int64_t>(r) * gtr_ld + (L - 1)];
+        if (j == 0) ga = ga + g;
+        if (j == M - 1) gb = gb + g;
+      }
     }
     grad_fa[L] = ga;
     grad_fb[L] = gb;
   }
+  // dJ/dlam: the tiles' partials summed by the first work-group in a fixed
+  // order
+  if (blockIdx.x != 0) return;
   double t = 0.0;
   for (int i = tid; i < n_part; i += 256) t += lam_part[i];
   red[tid] = t;
@@ -162,8 +172,11 @@ hipError_t launch_adj_finish(T* grad_fa, T* grad_fb, const T* gtr, int64_t gtr_l
                              const int64_t* rec_node, int32_t n_rec, int64_t M,
                              int64_t n_steps, const double* lam_part, int32_t n_part,
                              double lam, double* grad_lam, hipStream_t s) {
-  hipLaunchKernelGGL(k_adj_finish<T>, dim3(1), dim3(256), 0, s, grad_fa, grad_fb, gtr,
-                     gtr_ld, rec_node, n_rec, M, n_steps, lam_part, n_part, lam, grad_lam);
+  int64_t blocks = (n_steps + 255) / 256;
+  blocks = blocks < 1 ? 1 : (blocks > 1024 ? 1024 : blocks);
+  hipLaunchKernelGGL(k_adj_finish<T>, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s,
+                     grad_fa, grad_fb, gtr, gtr_ld, rec_node, n_rec, M, n_steps, lam_part,
+                     n_part, lam, grad_lam);
   return hipGetLastError();
 }
 
